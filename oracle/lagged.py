@@ -1,0 +1,67 @@
+"""Algorithm 3: the priorconditioned lagged-diffusivity solver (Section 4.1).
+
+Outer iteration k (k = 1..K, starting from f^0 = 0):
+  1. form M_{f^{k-1}} from the current iterate: kappa = r'(t)/t at t = |grad f^{k-1}|
+     (eq. (1.12)-(1.13)), once per outer iteration, fixed during the inner solve;
+  2. solve the damped priorconditioned problem (4.3) with MLSQR (Algorithm 2),
+     restarted from f = 0 (Section 4.3 notes every outer step restarts the residual at ||g||),
+     with the V-cycle standing in for M^{-1};
+  3. record ||g - A f^k|| and R(f^k) (the quantities the paper monitors for the
+     discrepancy principle S4 and the outer stopping rule).
+
+The iteration counts are fixed (K outer x m inner); the adaptive stops of the
+paper (S4, and R not decreasing fast enough) are not part of this oracle.
+"""
+
+import numpy as np
+
+from . import grid, multigrid, mlsqr, regularizers
+from .operators import Blur, Dense
+
+
+def make_operator(op_kind, shape, taps=None, A=None):
+    if op_kind == "blur":
+        return Blur(taps, shape)
+    if op_kind == "dense":
+        return Dense(A, shape)
+    raise ValueError(op_kind)
+
+
+def solve(shape, op, g, reg, T, tau, eps, outer, inner, levels, smoother, history=None):
+    """Return f^K (array of ``shape``) and a per-outer record list.
+
+    ``shape`` is (nz, ny, nx); ``op`` has ``apply``/``apply_T``; ``smoother`` is a
+    ``multigrid.Smoother``.
+    """
+    g = np.asarray(g, dtype=np.float64)
+    f = np.zeros(shape)
+    records = []
+    for k in range(1, outer + 1):
+        kappa = regularizers.diffusivity(reg, grid.grad_norm(f), T)
+        M = grid.prior_matrix(kappa, eps)
+        h = multigrid.Hierarchy(M, shape, levels)
+
+        def apply_Minv(p, h=h):
+            return multigrid.vcycle(h, np.asarray(p).ravel(), smoother).reshape(shape)
+
+        inner_hist = [] if history is not None else None
+        f, done = mlsqr.mlsqr(op.apply, op.apply_T, apply_Minv, g, tau, inner, inner_hist)
+        f = np.asarray(f).reshape(shape)
+        resid = float(np.linalg.norm(g.ravel() - np.asarray(op.apply(f)).ravel()))
+        records.append(dict(k=k, inner_done=done, resid=resid, penalty=grid.penalty(f, reg, T)))
+        if history is not None:
+            history.append(inner_hist)
+    return f, records
+
+
+def solve_problem(prob, history=None, outer=None, inner=None):
+    """Convenience wrapper taking a ``gen.Problem``-like object (fields only, no behaviour)."""
+    nx, ny, nz = prob.dims
+    shape = (nz, ny, nx)
+    op = make_operator(prob.op_kind, shape, taps=prob.taps, A=prob.A)
+    sm = multigrid.Smoother(prob.smoother, prob.nu_pre, prob.nu_post, prob.omega,
+                            prob.cheb_degree, prob.cheb_lo, prob.cheb_hi)
+    g = np.asarray(prob.g, dtype=np.float64).reshape(shape if prob.op_kind == "blur" else (-1,))
+    return solve(shape, op, g, prob.reg, prob.T, prob.tau, prob.eps,
+                 prob.outer if outer is None else outer, prob.inner if inner is None else inner,
+                 prob.levels, sm, history)
