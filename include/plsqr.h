@@ -1,0 +1,196 @@
+/*
+ * plsqr.h -- C ABI of the MI355X (gfx950) priorconditioned LSQR library.
+ *
+ * The library solves the edge-preserving regularised linear inverse problem
+ *     min_f  1/2 ||g - A f||^2 + tau R(f),   R(f) = sum_j r(|grad f|_j)
+ * (the MAP estimate of Section 1.1, eq. (1.6), with r from eq. (1.3)-(1.5)) by the
+ * priorconditioned lagged-diffusivity method: Algorithm 3 (outer loop: freeze the
+ * diffusivity kappa = r'(t)/t of eq. (1.12)-(1.13) at the previous iterate) around
+ * Algorithm 2 (MLSQR, factorization-free priorconditioned LSQR) with the damping of
+ * Section 3.3 / eq. (3.6), where the solve with the prior matrix
+ *     M = G^T diag(kappa) G + eps I   (G: forward differences, zero at the upper
+ *                                      boundary, i.e. the Neumann condition of (1.12))
+ * is replaced by one geometric-multigrid V-cycle, a fixed SPD operator (Section 4.2).
+ * Iteration counts are fixed: `outer` lagged-diffusivity steps x `inner` MLSQR steps.
+ *
+ * Conventions
+ *  - Grids are (nx, ny, nz), x fastest, float32, contiguous; nz == 1 is a 2D image.
+ *  - Every call returns an int status (PLSQR_OK = 0, errors < 0); no exception crosses
+ *    the ABI. plsqr_last_error() returns a message for the calling thread's last error.
+ *  - Pointers named *_dev are device pointers on the engine's device; they are
+ *    BORROWED: the caller keeps them alive (and, for inputs, unchanged) until the
+ *    request that uses them has completed (plsqr_poll returned something other than
+ *    PLSQR_PENDING), and for operators until plsqr_destroy.
+ *  - Host pointers are read during the call only and may be freed afterwards.
+ *  - An engine is driven by one host thread at a time (calls are serialised by an
+ *    internal lock); work runs on the stream given at creation, in submission order.
+ */
+#ifndef PLSQR_H
+#define PLSQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------- */
+enum {
+  PLSQR_OK = 0,
+  PLSQR_PENDING = 1,            /* plsqr_poll: request not finished yet */
+  PLSQR_E_INVALID = -1,         /* bad argument (sizes, enum values, null pointers) */
+  PLSQR_E_NOMEM = -2,           /* device allocation failed */
+  PLSQR_E_BUDGET = -3,          /* request can never fit the engine's HBM budget */
+  PLSQR_E_HIP = -4,             /* a HIP runtime call failed */
+  PLSQR_E_NOT_SPD = -5,         /* preconditioner or coarsest matrix not positive definite */
+  PLSQR_E_NONFINITE = -6,       /* NaN/Inf met in the Krylov scalars (e.g. NaN in g) */
+  PLSQR_E_UNKNOWN_TICKET = -7   /* ticket never issued, or already retired */
+};
+
+/* ---- enumerations ---------------------------------------------------------------- */
+enum { PLSQR_OP_BLUR = 1, PLSQR_OP_DENSE = 2 };
+/* r(t) of eq. (1.3) (Tikhonov), (1.4) smoothed TV, (1.5) Perona-Malik log / exp forms */
+enum { PLSQR_REG_TIKHONOV = 0, PLSQR_REG_STV = 1, PLSQR_REG_PM_LOG = 2, PLSQR_REG_PM_EXP = 3 };
+enum { PLSQR_SMOOTH_JACOBI = 0, PLSQR_SMOOTH_CHEBYSHEV = 1 };
+/* FP32: float32 vectors and products, float64 Krylov scalars and coarsest solve.
+ * BF16_REFINED: dense products of a batch run as BF16 MFMA GEMMs with FP32
+ * accumulation plus one refinement term (needs A_hi_dev, optionally A_lo_dev). */
+enum { PLSQR_PREC_FP32 = 0, PLSQR_PREC_BF16_REFINED = 1 };
+
+/* engine creation flags */
+enum {
+  PLSQR_ENGINE_SERVE = 1u << 0  /* run a scheduler thread that admits requests by HBM
+                                   budget and advances all resident requests together
+                                   (continuous batching); default: each request is
+                                   enqueued whole on submission */
+};
+
+/* problem flags */
+enum {
+  PLSQR_FLAG_TIME_PRODUCTS = 1u << 0  /* time every launch of the forward/adjoint product
+                                         kernels with HIP events; totals in plsqr_result */
+};
+
+#define PLSQR_MAX_LEVELS 12
+#define PLSQR_MAX_OUTER 64
+#define PLSQR_MAX_RADIUS 16
+#define PLSQR_MAX_COARSE 512     /* largest coarsest-grid size solved by dense Cholesky */
+
+typedef struct plsqr_engine plsqr_engine;   /* opaque; owns all internal device state */
+
+/* Forward map A: R^{nx*ny*nz} -> R^{n_y} (the method only needs its action and that
+ * of A^T; Section 1).
+ *  PLSQR_OP_BLUR : separable correlation with taps[0..2*radius] (taps[radius] is the
+ *                  centre) along every axis of extent > 1, zero outside the grid,
+ *                  n_y = nx*ny*nz. The adjoint uses the reversed taps. taps is a HOST
+ *                  pointer copied during the call. radius <= PLSQR_MAX_RADIUS.
+ *  PLSQR_OP_DENSE: A_dev is a row-major n_y x (nx*ny*nz) float32 DEVICE matrix
+ *                  (BORROWED). A_hi_dev / A_lo_dev are optional bf16 (uint16 bit
+ *                  pattern) copies with the same layout: A_hi = bf16(A),
+ *                  A_lo = bf16(A - A_hi); they are used by PLSQR_PREC_BF16_REFINED.
+ */
+typedef struct {
+  int32_t kind;
+  int32_t nx, ny, nz;
+  int32_t radius;
+  int32_t reserved0;
+  const float *taps;
+  int64_t n_y;
+  const float *A_dev;
+  const uint16_t *A_hi_dev;
+  const uint16_t *A_lo_dev;
+} plsqr_operator;
+
+/* One reconstruction. Grid must equal the operator's grid.
+ *  reg, T        : regulariser r(t) and its parameter T > 0 (ignored for Tikhonov)
+ *  tau >= 0      : prior weight; MLSQR damping is sqrt(tau) (Section 3.3)
+ *  eps > 0       : shift making M = G^T diag(kappa) G + eps I positive definite
+ *  outer, inner  : fixed iteration counts, 1 <= outer <= PLSQR_MAX_OUTER, inner >= 1
+ *  mg_levels     : number of grids (0: halve while every coarsened axis is even and
+ *                  > 4); each coarsening halves nx, ny and (3D) nz, which must be even;
+ *                  the coarsest grid must have <= PLSQR_MAX_COARSE cells
+ *  smoother      : PLSQR_SMOOTH_JACOBI (damped, weight omega in (0,1]) with nu_pre = nu_post
+ *                  sweeps, or PLSQR_SMOOTH_CHEBYSHEV (degree cheb_degree in D^{-1}A on
+ *                  [cheb_lo, cheb_hi], applied nu_pre = nu_post times); equal pre and
+ *                  post smoothing keeps the V-cycle symmetric (Section 4.2)
+ *  precision     : PLSQR_PREC_*
+ *  flags         : PLSQR_FLAG_*
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t reg;
+  double T, tau, eps;
+  int32_t outer, inner;
+  int32_t mg_levels;
+  int32_t smoother;
+  int32_t nu_pre, nu_post;
+  double omega;
+  int32_t cheb_degree;
+  int32_t precision;
+  double cheb_lo, cheb_hi;
+  uint32_t flags;
+  int32_t reserved0;
+} plsqr_problem;
+
+/* Completion record of one request (filled by plsqr_poll). */
+typedef struct {
+  int32_t status;                     /* PLSQR_OK or the request's error code */
+  int32_t outer_done;                 /* outer iterations run */
+  int32_t levels;                     /* multigrid levels used */
+  int32_t reserved0;
+  int32_t inner_done[PLSQR_MAX_OUTER];/* MLSQR steps completed per outer iteration
+                                         (< inner after an exact-termination stop) */
+  double resid[PLSQR_MAX_OUTER];      /* ||g - A f^k|| per outer iteration k */
+  double penalty[PLSQR_MAX_OUTER];    /* R(f^k) per outer iteration k */
+  double submit_to_done_ms;           /* host wall time from plsqr_solve to completion
+                                         being observed */
+  double device_ms;                   /* device time of the request (HIP events) */
+  double product_ms;                  /* with PLSQR_FLAG_TIME_PRODUCTS: summed time of the
+                                         forward/adjoint product kernel launches */
+  int64_t product_launches;           /* ... and their count */
+  int64_t workspace_bytes;            /* device memory the request held */
+} plsqr_result;
+
+/* Create an engine on HIP device `device`, with at most `hbm_budget_bytes` of
+ * internal device memory (0 = no limit) and work submitted to `hip_stream`
+ * (a hipStream_t, or NULL for the null stream). flags: PLSQR_ENGINE_*.
+ * On success *out receives the engine; on error *out is NULL. */
+int plsqr_create(plsqr_engine **out, int device, uint64_t hbm_budget_bytes, void *hip_stream,
+                 uint32_t flags);
+
+/* Register a forward operator (see plsqr_operator); *op_id receives its handle. */
+int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_id);
+
+/* Submit one reconstruction: g_dev (n_y floats) is the data, f_dev (nx*ny*nz floats)
+ * receives f^outer. Validates, then returns at once with *ticket; the work runs
+ * asynchronously. f_dev is written only if the request succeeds. A request larger
+ * than the whole budget fails with PLSQR_E_BUDGET; one that does not fit the memory
+ * left waits until earlier requests complete. */
+int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, const float *g_dev,
+                float *f_dev, uint64_t *ticket);
+
+/* Non-blocking completion check: PLSQR_PENDING while the request runs; otherwise the
+ * request's status (PLSQR_OK or an error), with *out filled (out may be NULL). A
+ * ticket is retired after its first non-PENDING return. */
+int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out);
+
+/* Block until every submitted request has completed (results stay pollable). */
+int plsqr_wait_all(plsqr_engine *eng);
+
+/* Wait for in-flight work, free all internal state and the engine. NULL is a no-op. */
+int plsqr_destroy(plsqr_engine *eng);
+
+/* Message describing the calling thread's last error (never NULL). */
+const char *plsqr_last_error(const plsqr_engine *eng);
+
+/* Number of grids the automatic rule picks for (nx, ny, nz) (mg_levels = 0). */
+int plsqr_auto_levels(int32_t nx, int32_t ny, int32_t nz);
+
+/* Bytes of device workspace one request of this problem needs (for HBM budgeting);
+ * 0 if the arguments are invalid. op_kind is PLSQR_OP_*, n_y the operator's row count. */
+uint64_t plsqr_workspace_bytes(const plsqr_problem *prob, int32_t op_kind, int64_t n_y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLSQR_H */

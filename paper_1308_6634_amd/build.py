@@ -1,0 +1,62 @@
+"""Build the HIP library ``libplsqr.so`` in-tree for gfx950.
+
+Kernels are compiled by hipcc for gfx950 only; the host engine is plain C++ compiled
+by the ROCm clang; the shared object is linked by hipcc. Usage:
+``python -m paper_1308_6634_amd.build`` (or ``build()`` from Python).
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libplsqr.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = "gfx950"
+
+KERNEL_SOURCES = ["kernels.hip"]
+HOST_SOURCES = ["driver.cpp", "api.cpp"]
+HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp"]
+
+# Packed-FP32 instructions are disabled for every device compile (the compiler would
+# otherwise form v_pk_* FP32 ops from ordinary float code).
+DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
+                "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-Wall", "-Wno-unused-value"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose=True):
+    hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+    clang = os.path.join(ROCM, "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = shutil.which("g++")
+    os.makedirs(BUILD, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", os.path.join(ROCM, "include")]
+    objs = []
+    for src in KERNEL_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        _run([hipcc, "-c", *DEVICE_FLAGS, *inc, os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        _run([clang, "-x", "c++", "-c", *HOST_FLAGS, *inc, os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+          "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lpthread"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)

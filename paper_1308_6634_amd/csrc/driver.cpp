@@ -1,0 +1,346 @@
+// Solve driver: the kernel sequence of Algorithm 3 around Algorithm 2, for one instance
+// or for a lockstep batch of same-shaped instances. No host/device synchronisation
+// happens inside: every scalar of the Krylov recurrence lives in device memory.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace plsqr {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::string *why) {
+  auto bad = [&](const char *m) {
+    *why = m;
+    return PLSQR_E_INVALID;
+  };
+  if (!op) return bad("unknown operator id");
+  if (pb.nx < 1 || pb.ny < 1 || pb.nz < 1) return bad("grid extents must be >= 1");
+  if (pb.nx != op->op.nx || pb.ny != op->op.ny || pb.nz != op->op.nz)
+    return bad("problem grid differs from the operator's grid");
+  if (pb.reg < PLSQR_REG_TIKHONOV || pb.reg > PLSQR_REG_PM_EXP) return bad("unknown regulariser");
+  if (pb.reg != PLSQR_REG_TIKHONOV && !(pb.T > 0.0 && std::isfinite(pb.T)))
+    return bad("T must be positive and finite");
+  if (!(pb.tau >= 0.0 && std::isfinite(pb.tau))) return bad("tau must be >= 0 and finite");
+  if (!(pb.eps > 0.0 && std::isfinite(pb.eps))) return bad("eps must be positive and finite");
+  if (pb.outer < 1 || pb.outer > PLSQR_MAX_OUTER) return bad("outer must be in [1, 64]");
+  if (pb.inner < 1 || pb.inner > 1000000) return bad("inner must be in [1, 1e6]");
+  if (pb.nu_pre < 1 || pb.nu_pre != pb.nu_post)
+    return bad("nu_pre must equal nu_post and be >= 1 (symmetric V-cycle)");
+  if (pb.smoother == PLSQR_SMOOTH_JACOBI) {
+    if (!(pb.omega > 0.0 && pb.omega <= 1.0)) return bad("Jacobi omega must be in (0, 1]");
+  } else if (pb.smoother == PLSQR_SMOOTH_CHEBYSHEV) {
+    if (pb.cheb_degree < 1 || pb.cheb_degree > 16) return bad("cheb_degree must be in [1, 16]");
+    if (!(pb.cheb_lo > 0.0 && pb.cheb_hi > pb.cheb_lo && pb.cheb_hi <= 4.0))
+      return bad("Chebyshev interval must satisfy 0 < lo < hi <= 4");
+  } else {
+    return bad("unknown smoother");
+  }
+  if (pb.precision != PLSQR_PREC_FP32 && pb.precision != PLSQR_PREC_BF16_REFINED)
+    return bad("unknown precision");
+  int levels = pb.mg_levels;
+  if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
+  if (levels < 1 || levels > kMaxLevels) return bad("mg_levels out of range");
+  long long nx = pb.nx, ny = pb.ny, nz = pb.nz;
+  for (int l = 1; l < levels; ++l) {
+    if ((nx & 1) || (ny & 1) || (nz > 1 && (nz & 1)))
+      return bad("each coarsening needs even nx, ny (and nz in 3D)");
+    nx /= 2;
+    ny /= 2;
+    if (nz > 1) nz /= 2;
+  }
+  if (nx * ny * nz > PLSQR_MAX_COARSE) return bad("coarsest grid has more than 512 cells");
+  if (op->op.kind == PLSQR_OP_BLUR && 2 * op->op.radius + 1 > kMaxTaps) return bad("radius too large");
+  *levels_out = levels;
+  return PLSQR_OK;
+}
+
+Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind) {
+  Layout L;
+  L.levels = levels;
+  L.n = (long long)pb.nx * pb.ny * pb.nz;
+  L.m = n_y;
+  const bool dense = (op_kind == PLSQR_OP_DENSE);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, 256);
+    const size_t o = off;
+    off += std::max<size_t>(bytes, 4);
+    return o;
+  };
+  L.lnx[0] = pb.nx;
+  L.lny[0] = pb.ny;
+  L.lnz[0] = pb.nz;
+  for (int l = 0; l < levels; ++l) {
+    if (l > 0) {
+      L.lnx[l] = L.lnx[l - 1] / 2;
+      L.lny[l] = L.lny[l - 1] / 2;
+      L.lnz[l] = L.lnz[l - 1] > 1 ? L.lnz[l - 1] / 2 : 1;
+    }
+    L.ln[l] = (long long)L.lnx[l] * L.lny[l] * L.lnz[l];
+  }
+  L.nc = (int)L.ln[levels - 1];
+  const long long nb = (L.n + kBlock - 1) / kBlock;
+  const long long mb = (L.m + kBlock - 1) / kBlock;
+  const long long mr = (L.m + 3) / 4;
+  L.nparts = (int)std::max({nb, mb, mr, 1LL});
+  L.desc = take(sizeof(InstDesc));
+  L.descptr = take(sizeof(void *));
+  L.sc = take(SC_COUNT * sizeof(double));
+  L.diag = take((size_t)(pb.outer + 1) * DG_COUNT * sizeof(double));
+  L.part = take((size_t)L.nparts * sizeof(double));
+  L.cfac = take((size_t)L.nc * L.nc * sizeof(double));
+  const size_t vb = (size_t)L.n * sizeof(float);
+  L.f = take(vb);
+  L.p = take(vb);
+  L.v = take(vb);
+  L.w = take(vb);
+  L.kappa = take(vb);
+  L.u = take((size_t)L.m * sizeof(float));
+  L.colchunks = 0;
+  if (!dense) {
+    L.tmp1 = take(vb);
+    L.tmp2 = take(vb);
+  } else {
+    // dense adjoint row chunks: aim for >= 2048 blocks in total
+    const long long colblocks = (L.n + 4 * kBlock - 1) / (4 * kBlock);
+    long long ch = (2048 + colblocks - 1) / colblocks;
+    ch = std::max(1LL, std::min({ch, 64LL, L.m}));
+    L.colchunks = (int)ch;
+    L.colpart = take((size_t)ch * vb);
+  }
+  for (int l = 0; l < levels; ++l) {
+    const size_t b = (size_t)L.ln[l] * sizeof(float);
+    if (l > 0) {
+      L.lvl[l][0] = take(b);  // x
+      L.lvl[l][1] = take(b);  // b
+    }
+    L.lvl[l][2] = take(b);    // r
+    L.lvl[l][3] = take(b);    // t
+    L.lvl[l][4] = take(b);    // s
+    if (l > 0) {
+      L.lvl[l][5] = take(b);  // wx
+      L.lvl[l][6] = take(b);  // wy
+      if (L.lnz[l] > 1) L.lvl[l][7] = take(b);  // wz
+    }
+    L.lvl[l][8] = take(b);    // dinv
+  }
+  L.total = align_up(off, 256);
+  return L;
+}
+
+// ---------------------------------------------------------------------------------
+// products
+// ---------------------------------------------------------------------------------
+static void time_begin(hipStream_t st, const BatchView &bv, hipEvent_t *a) {
+  if (!bv.prod_events) return;
+  hipEventCreate(a);
+  hipEventRecord(*a, st);
+}
+static void time_end(hipStream_t st, const BatchView &bv, hipEvent_t a) {
+  if (!bv.prod_events) return;
+  hipEvent_t b;
+  hipEventCreate(&b);
+  hipEventRecord(b, st);
+  bv.prod_events->emplace_back(a, b);
+}
+
+static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi) {
+  const InstDesc &H = *bv.h;
+  int axes[3], na = 0;
+  const int ext[3] = {H.nx, H.ny, H.nz};
+  for (int a = 0; a < 3; ++a)
+    if (ext[a] > 1) axes[na++] = a;
+  if (na == 0) axes[na++] = 0;
+  int cur = src, np = 0;
+  for (int i = 0; i < na; ++i) {
+    const bool last = (i == na - 1);
+    const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
+    np = launch_blur_pass(st, bv.d_descs, bv.B, H.n, axes[i], cur, dst, adj, last ? epi : EPI_STORE);
+    cur = dst;
+  }
+  return np;
+}
+
+// y = A x from vector `src`, epilogue `epi`; returns the partial count.
+static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi) {
+  const InstDesc &H = *bv.h;
+  hipEvent_t a = nullptr;
+  time_begin(st, bv, &a);
+  int np;
+  if (H.op_kind == PLSQR_OP_BLUR)
+    np = blur_chain(st, bv, src, 0, epi);
+  else
+    np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi);
+  time_end(st, bv, a);
+  return np;
+}
+
+// p <- su A^T u (- beta sv p).
+static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
+  const InstDesc &H = *bv.h;
+  hipEvent_t a = nullptr;
+  time_begin(st, bv, &a);
+  if (H.op_kind == PLSQR_OP_BLUR) {
+    blur_chain(st, bv, V_U, 1, epi);
+  } else {
+    launch_gemv_cols(st, bv.d_descs, bv.B, H.n, H.colchunks);
+    launch_colsum(st, bv.d_descs, bv.B, H.n, epi);
+  }
+  time_end(st, bv, a);
+}
+
+// ---------------------------------------------------------------------------------
+// V-cycle: v = B p; returns the partial count of the alpha^2 = v.p reduction
+// ---------------------------------------------------------------------------------
+static int other(int s) { return s == LB_X ? LB_T : LB_X; }
+
+static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  const Layout &Ly = *bv.lay;
+  const int L = H.levels;
+  InstDesc *const *d = bv.d_descs;
+  const int B = bv.B;
+  if (L == 1) {
+    launch_coarse_solve(st, d, B);   // exact M^{-1} on a single grid
+    return launch_dot_vp(st, d, B, H.n);
+  }
+  int np = 0;
+  if (H.smoother == PLSQR_SMOOTH_JACOBI) {
+    const int nsw = H.nu_pre + H.nu_post;
+    int cur_l[kMaxLevels];
+    for (int l = 0; l < L - 1; ++l) {
+      int cur = -1;
+      for (int s = 0; s < H.nu_pre; ++s) {
+        const int dst = (s == 0) ? ((nsw % 2) ? LB_X : LB_T) : other(cur);
+        launch_jacobi(st, d, B, l, Ly.ln[l], s == 0, cur < 0 ? LB_X : cur, dst, 0);
+        cur = dst;
+      }
+      cur_l[l] = cur;
+      launch_restrict(st, d, B, l, Ly.ln[l + 1], cur, 0);
+    }
+    launch_coarse_solve(st, d, B);
+    for (int l = L - 2; l >= 0; --l) {
+      int cur = cur_l[l];
+      launch_prolong(st, d, B, l, Ly.ln[l], cur);
+      for (int s = 0; s < H.nu_post; ++s) {
+        const int dst = other(cur);
+        const bool last = (s == H.nu_post - 1);
+        const int r = launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, dst, (l == 0 && last) ? 1 : 0);
+        if (l == 0 && last) np = r;
+        cur = dst;
+      }
+    }
+  } else {
+    const int m = H.cheb_degree, nu = H.nu_pre;
+    for (int l = 0; l < L - 1; ++l) {
+      for (int a = 0; a < nu; ++a) {
+        const bool zero = (a == 0);
+        launch_cheb_start(st, d, B, l, Ly.ln[l], zero ? 1 : 0, LB_T);
+        int dcur = LB_T;
+        for (int k = 0; k < m; ++k) {
+          const bool last = (k == m - 1);
+          const bool upd = !last || (a == nu - 1);
+          const int dn = (dcur == LB_T) ? LB_S : LB_T;
+          launch_cheb_step(st, d, B, l, Ly.ln[l], (zero && k == 0) ? 1 : 0, upd ? 1 : 0,
+                           last ? 1 : 0, dcur, dn, k, 0);
+          dcur = dn;
+        }
+      }
+      launch_restrict(st, d, B, l, Ly.ln[l + 1], LB_X, 1);
+    }
+    launch_coarse_solve(st, d, B);
+    for (int l = L - 2; l >= 0; --l) {
+      launch_prolong(st, d, B, l, Ly.ln[l], LB_X);
+      for (int a = 0; a < nu; ++a) {
+        launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
+        int dcur = LB_T;
+        for (int k = 0; k < m; ++k) {
+          const bool last = (k == m - 1);
+          const int dn = (dcur == LB_T) ? LB_S : LB_T;
+          const bool want = (l == 0 && a == nu - 1 && last);
+          const int r = launch_cheb_step(st, d, B, l, Ly.ln[l], 0, last ? 0 : 1, last ? 1 : 0, dcur,
+                                         dn, k, want ? 1 : 0);
+          if (want) np = r;
+          dcur = dn;
+        }
+      }
+    }
+  }
+  return np;
+}
+
+// ---------------------------------------------------------------------------------
+// phases
+// ---------------------------------------------------------------------------------
+void enqueue_request_begin(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  launch_request_begin(st, bv.d_descs, bv.B, H.n);
+  const int np = launch_diffusivity(st, bv.d_descs, bv.B, H.n, 1);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_PENALTY);
+}
+
+void enqueue_outer_setup(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  const Layout &Ly = *bv.lay;
+  launch_outer_begin(st, bv.d_descs, bv.B);
+  launch_level0_dinv(st, bv.d_descs, bv.B, H.n);
+  for (int l = 0; l + 1 < H.levels; ++l) {
+    launch_coarsen(st, bv.d_descs, bv.B, l, Ly.ln[l + 1]);
+    launch_level_dinv(st, bv.d_descs, bv.B, l + 1, Ly.ln[l + 1]);
+  }
+  launch_coarse_factor(st, bv.d_descs, bv.B);
+}
+
+void enqueue_mlsqr_init(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  int np = launch_copy_g_u(st, bv.d_descs, bv.B, H.m);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA_INIT);
+  enqueue_adjoint(st, bv, EPI_ADJ_INIT);
+  np = enqueue_vcycle(st, bv);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA_INIT);
+  launch_init_wf(st, bv.d_descs, bv.B, H.n);
+}
+
+void enqueue_inner(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  int np = enqueue_forward(st, bv, V_V, EPI_FWD);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
+  enqueue_adjoint(st, bv, EPI_ADJ);
+  np = enqueue_vcycle(st, bv);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
+  launch_update_fw(st, bv.d_descs, bv.B, H.n);
+}
+
+void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  int np = enqueue_forward(st, bv, V_F, EPI_RESID);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_RESID);
+  np = launch_diffusivity(st, bv.d_descs, bv.B, H.n, 1);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_PENALTY);
+}
+
+void enqueue_request_end(hipStream_t st, const BatchView &bv) {
+  launch_copy_out(st, bv.d_descs, bv.B, bv.h->n);
+}
+
+void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner) {
+  enqueue_request_begin(st, bv);
+  for (int k = 1; k <= outer; ++k) {
+    enqueue_outer_setup(st, bv);
+    enqueue_mlsqr_init(st, bv);
+    for (int i = 0; i < inner; ++i) enqueue_inner(st, bv);
+    enqueue_outer_end(st, bv);
+  }
+  enqueue_request_end(st, bv);
+}
+
+}  // namespace plsqr

@@ -1,0 +1,113 @@
+// Host engine: operators, requests, device workspaces and the solve driver.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plsqr_internal.hpp"
+
+namespace plsqr {
+
+struct Operator {
+  plsqr_operator op{};
+  std::vector<float> taps;
+};
+
+// Byte offsets of every buffer inside one request's workspace.
+struct Layout {
+  size_t total = 0;
+  size_t desc = 0, descptr = 0, sc = 0, diag = 0, part = 0, cfac = 0;
+  size_t f = 0, p = 0, v = 0, w = 0, kappa = 0, u = 0, tmp1 = 0, tmp2 = 0, colpart = 0;
+  size_t lvl[kMaxLevels][10] = {};   // x b r t s wx wy wz dinv (unused slots 0)
+  int nparts = 0, colchunks = 0, levels = 0, nc = 0;
+  long long n = 0, m = 0;
+  long long ln[kMaxLevels] = {};
+  int lnx[kMaxLevels] = {}, lny[kMaxLevels] = {}, lnz[kMaxLevels] = {};
+};
+
+// Validate a problem against an operator; fills *levels. Returns PLSQR_OK or an error
+// with a message in *why.
+int validate(const plsqr_problem &pb, const Operator *op, int *levels, std::string *why);
+Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind);
+
+// Workspace cache: freed workspaces are kept for reuse by requests of the same size.
+class Pool {
+ public:
+  ~Pool();
+  void *get(size_t bytes);
+  void put(void *p, size_t bytes);
+  void trim();
+ private:
+  std::multimap<size_t, void *> free_;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  int op_id = 0;
+  plsqr_problem pb{};
+  const float *g = nullptr;
+  float *f_out = nullptr;
+  Layout lay;
+  char *ws = nullptr;                // device workspace
+  InstDesc host{};                   // host copy of the descriptor
+  InstDesc **d_descs = nullptr;      // device: 1-element pointer array (in ws)
+  enum State { QUEUED, RUNNING, DONE } state = QUEUED;
+  int status = PLSQR_OK;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  char *pinned = nullptr;            // pinned host staging: descriptor up, scalars/records down
+  size_t pinned_bytes = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prod_events;
+  double t_submit = 0.0, t_done = 0.0;
+  plsqr_result result{};
+  // serving mode: progress through the fixed schedule
+  int outer_k = 0, inner_i = 0, phase = 0;
+};
+
+// A view of B same-shaped instances launched together.
+struct BatchView {
+  InstDesc *const *d_descs;   // device array of B descriptor pointers
+  int B;
+  const InstDesc *h;          // host copy of one member (shapes and schedule)
+  const Layout *lay;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> *prod_events;  // optional timing
+};
+
+// Solve driver (same sequence for one instance or a lockstep batch).
+void enqueue_request_begin(hipStream_t st, const BatchView &bv);
+void enqueue_outer_setup(hipStream_t st, const BatchView &bv);
+void enqueue_mlsqr_init(hipStream_t st, const BatchView &bv);
+void enqueue_inner(hipStream_t st, const BatchView &bv);
+void enqueue_outer_end(hipStream_t st, const BatchView &bv);
+void enqueue_request_end(hipStream_t st, const BatchView &bv);
+void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner);
+
+double now_ms();
+
+}  // namespace plsqr
+
+struct plsqr_engine {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;      // 0 = unlimited
+  uint64_t used = 0;
+  uint32_t flags = 0;
+  std::mutex mu;
+  std::vector<plsqr::Operator> ops;
+  std::map<uint64_t, std::unique_ptr<plsqr::Request>> reqs;
+  std::deque<uint64_t> queued;
+  uint64_t next_ticket = 1;
+  plsqr::Pool pool;
+  // serving mode
+  std::thread worker;
+  std::condition_variable cv;
+  bool stop_worker = false;
+};

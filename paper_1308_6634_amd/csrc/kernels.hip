@@ -1,0 +1,868 @@
+// HIP kernels (gfx950) of the priorconditioned lagged-diffusivity solver.
+//
+// Every kernel is batched: blockIdx.y selects an instance through a device array of
+// InstDesc pointers, blockIdx.x tiles that instance's grid. Blocks past an instance's
+// extent still take part in block reductions (they contribute 0), so every reduction
+// writes exactly gridDim.x partials per instance, which one finaliser block then sums
+// in a fixed order (deterministic FP64 reductions).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace plsqr {
+
+// ------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ const InstDesc &inst(InstDesc *const *descs) {
+  return *descs[blockIdx.y];
+}
+
+__device__ __forceinline__ float *vec_of(const InstDesc &D, int sel) {
+  switch (sel) {
+    case V_F: return D.f;
+    case V_U: return D.u;
+    case V_P: return D.p;
+    case V_V: return D.v;
+    case V_W: return D.w;
+    case V_TMP1: return D.tmp1;
+    case V_TMP2: return D.tmp2;
+    default: return const_cast<float *>(D.g);
+  }
+}
+
+__device__ __forceinline__ float *lvbuf(const LevelDesc &L, int sel) {
+  switch (sel) {
+    case LB_X: return L.x;
+    case LB_B: return L.b;
+    case LB_R: return L.r;
+    case LB_T: return L.t;
+    default: return L.s;
+  }
+}
+
+// Sum of v over the block (valid in thread 0). blockDim.x must be kBlock.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) r += red[i];
+  return r;
+}
+
+__device__ __forceinline__ float block_sum_f(float v) {
+  __shared__ float redf[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) redf[wid] = v;
+  __syncthreads();
+  float r = 0.f;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) r += redf[i];
+  return r;
+}
+
+// kappa(t) = r'(t)/t in closed form (eq. (1.12)-(1.13) with r from (1.3)-(1.5)).
+__device__ __forceinline__ float kappa_of(int reg, float t, float T) {
+  switch (reg) {
+    case PLSQR_REG_STV: return 1.0f / sqrtf(T * T + t * t);
+    case PLSQR_REG_PM_LOG: return 1.0f / (1.0f + (t * t) / (T * T));
+    case PLSQR_REG_PM_EXP: return expf(-(t * t) / (T * T));
+    default: return 1.0f;
+  }
+}
+
+// r(t), eq. (1.3)-(1.5), in FP64.
+__device__ __forceinline__ double penalty_of(int reg, double t, double T) {
+  switch (reg) {
+    case PLSQR_REG_STV: return T * sqrt(1.0 + (t / T) * (t / T));
+    case PLSQR_REG_PM_LOG: return 0.5 * T * T * log1p((t / T) * (t / T));
+    case PLSQR_REG_PM_EXP: return 0.5 * T * T * (1.0 - exp(-(t * t) / (T * T)));
+    default: return 0.5 * t * t;
+  }
+}
+
+struct Coord { int x, y, z; };
+__device__ __forceinline__ Coord coord_of(long long j, int nx, int ny) {
+  Coord c;
+  c.x = (int)(j % nx);
+  long long q = j / nx;
+  c.y = (int)(q % ny);
+  c.z = (int)(q / ny);
+  return c;
+}
+
+// (A_l x)_j on level l: eps_l x_j + sum over the faces of cell j of w (x_j - x_nb).
+// Level 0 face weight to the +a neighbour is kappa_j; coarser levels store them.
+__device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *__restrict__ x,
+                                         long long j, Coord c) {
+  const LevelDesc &L = D.lv[l];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const long long sx = 1, sy = nx, sz = (long long)nx * ny;
+  const float xj = x[j];
+  float acc = (float)L.eps * xj;
+  if (l == 0) {
+    const float *__restrict__ k = D.kappa;
+    const float kj = k[j];
+    if (c.x + 1 < nx) acc += kj * (xj - x[j + sx]);
+    if (c.x > 0) acc += k[j - sx] * (xj - x[j - sx]);
+    if (c.y + 1 < ny) acc += kj * (xj - x[j + sy]);
+    if (c.y > 0) acc += k[j - sy] * (xj - x[j - sy]);
+    if (c.z + 1 < nz) acc += kj * (xj - x[j + sz]);
+    if (c.z > 0) acc += k[j - sz] * (xj - x[j - sz]);
+  } else {
+    if (c.x + 1 < nx) acc += L.wx[j] * (xj - x[j + sx]);
+    if (c.x > 0) acc += L.wx[j - sx] * (xj - x[j - sx]);
+    if (c.y + 1 < ny) acc += L.wy[j] * (xj - x[j + sy]);
+    if (c.y > 0) acc += L.wy[j - sy] * (xj - x[j - sy]);
+    if (nz > 1) {
+      if (c.z + 1 < nz) acc += L.wz[j] * (xj - x[j + sz]);
+      if (c.z > 0) acc += L.wz[j - sz] * (xj - x[j - sz]);
+    }
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------------------------
+// a1: |grad f|, kappa and R(f)
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, int write_kappa) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double r = 0.0;
+  if (j < D.n) {
+    const int nx = D.nx, ny = D.ny, nz = D.nz;
+    const Coord c = coord_of(j, nx, ny);
+    const float *__restrict__ f = D.f;
+    const float fj = f[j];
+    const float gx = (c.x + 1 < nx) ? f[j + 1] - fj : 0.f;
+    const float gy = (c.y + 1 < ny) ? f[j + nx] - fj : 0.f;
+    const float gz = (c.z + 1 < nz) ? f[j + (long long)nx * ny] - fj : 0.f;
+    const float t = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (write_kappa) D.kappa[j] = kappa_of(D.reg, t, D.T);
+    r = penalty_of(D.reg, (double)t, (double)D.T);
+  }
+  r = block_sum(r);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = r;
+}
+
+// ------------------------------------------------------------------------------------
+// a2: multigrid hierarchy (Galerkin face sums), diagonals, coarsest Cholesky
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_level0_dinv(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= D.n) return;
+  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const Coord c = coord_of(j, nx, ny);
+  const float *__restrict__ k = D.kappa;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const float kj = k[j];
+  float d = (float)D.lv[0].eps;
+  if (c.x + 1 < nx) d += kj;
+  if (c.x > 0) d += k[j - 1];
+  if (c.y + 1 < ny) d += kj;
+  if (c.y > 0) d += k[j - sy];
+  if (c.z + 1 < nz) d += kj;
+  if (c.z > 0) d += k[j - sz];
+  D.lv[0].dinv[j] = 1.0f / d;
+}
+
+// Face weight of the fine level l from cell j to its +a neighbour (0 outside the grid).
+__device__ __forceinline__ float face_w(const InstDesc &D, int l, int a, long long j, Coord c) {
+  const LevelDesc &L = D.lv[l];
+  if (l == 0) {
+    const bool in = (a == 0) ? (c.x + 1 < L.nx) : (a == 1) ? (c.y + 1 < L.ny) : (c.z + 1 < L.nz);
+    return in ? D.kappa[j] : 0.f;
+  }
+  return (a == 0) ? L.wx[j] : (a == 1) ? L.wy[j] : L.wz[j];
+}
+
+// Galerkin coarsening l -> l+1 with piecewise-constant P: the weight of coarse face
+// (J, J+e_a) is the sum of the fine face weights crossing it.
+__global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int l) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &F = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (J >= Cl.n) return;
+  const Coord cc = coord_of(J, Cl.nx, Cl.ny);
+  const int cz = (F.nz > 1) ? 2 : 1;
+  const int naxes = (F.nz > 1) ? 3 : 2;
+  for (int a = 0; a < naxes; ++a) {
+    float s = 0.f;
+    // children of J with local coordinate 1 along a (their +a face leaves J)
+    for (int dz = 0; dz < cz; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int lx = dx, ly = dy, lz = dz;
+          const int loc = (a == 0) ? lx : (a == 1) ? ly : lz;
+          if (loc != 1) continue;
+          Coord fc;
+          fc.x = 2 * cc.x + dx;
+          fc.y = 2 * cc.y + dy;
+          fc.z = cz * cc.z + dz;
+          const long long j = fc.x + (long long)F.nx * (fc.y + (long long)F.ny * fc.z);
+          s += face_w(D, l, a, j, fc);
+        }
+    float *dst = (a == 0) ? Cl.wx : (a == 1) ? Cl.wy : Cl.wz;
+    dst[J] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, int l) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= L.n) return;
+  const Coord c = coord_of(j, L.nx, L.ny);
+  const long long sy = L.nx, sz = (long long)L.nx * L.ny;
+  float d = (float)L.eps;
+  d += L.wx[j] + (c.x > 0 ? L.wx[j - 1] : 0.f);
+  d += L.wy[j] + (c.y > 0 ? L.wy[j - sy] : 0.f);
+  if (L.nz > 1) d += L.wz[j] + (c.z > 0 ? L.wz[j - sz] : 0.f);
+  L.dinv[j] = 1.0f / d;
+}
+
+// Assemble the coarsest operator densely in FP64 and factor it (lower Cholesky, in
+// place). One block per instance.
+__global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const int l = D.levels - 1;
+  const LevelDesc &L = D.lv[l];
+  const int n = (int)L.n;
+  double *__restrict__ A = D.cfac;
+  for (long long i = threadIdx.x; i < (long long)n * n; i += kBlock) A[i] = 0.0;
+  __syncthreads();
+  for (int J = threadIdx.x; J < n; J += kBlock) {
+    const Coord c = coord_of(J, L.nx, L.ny);
+    const int strides[3] = {1, L.nx, L.nx * L.ny};
+    const int ext[3] = {L.nx, L.ny, L.nz};
+    const int pos[3] = {c.x, c.y, c.z};
+    double diag = L.eps;
+    for (int a = 0; a < 3; ++a) {
+      if (ext[a] == 1) continue;
+      if (pos[a] + 1 < ext[a]) {
+        const double w = face_w(D, l, a, J, c);
+        diag += w;
+        A[(long long)J * n + J + strides[a]] = -w;
+      }
+      if (pos[a] > 0) {
+        Coord cm = c;
+        if (a == 0) cm.x -= 1; else if (a == 1) cm.y -= 1; else cm.z -= 1;
+        const double w = face_w(D, l, a, J - strides[a], cm);
+        diag += w;
+        A[(long long)J * n + J - strides[a]] = -w;
+      }
+    }
+    A[(long long)J * n + J] = diag;
+  }
+  __syncthreads();
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      double d = A[(long long)k * n + k];
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      A[(long long)k * n + k] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = A[(long long)k * n + k];
+    for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) A[(long long)i * n + k] /= piv;
+    __syncthreads();
+    const int rem = n - k - 1;
+    for (long long q = threadIdx.x; q < (long long)rem * rem; q += kBlock) {
+      const int i = k + 1 + (int)(q / rem), jj = k + 1 + (int)(q % rem);
+      if (jj <= i) A[(long long)i * n + jj] -= A[(long long)i * n + k] * A[(long long)jj * n + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && bad) {
+    D.sc[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
+    D.sc[SC_STOP] = 1.0;
+  }
+}
+
+// Coarsest solve: x = L^{-T} L^{-1} b in FP64. One block per instance.
+__global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[D.levels - 1];
+  const int n = (int)L.n;
+  const double *__restrict__ A = D.cfac;
+  __shared__ double y[PLSQR_MAX_COARSE];
+  for (int i = threadIdx.x; i < n; i += kBlock) y[i] = (double)L.b[i];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double yk = y[k] / A[(long long)k * n + k];
+    __syncthreads();
+    if (threadIdx.x == 0) y[k] = yk;
+    for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) y[i] -= A[(long long)i * n + k] * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double yk = y[k] / A[(long long)k * n + k];
+    __syncthreads();
+    if (threadIdx.x == 0) y[k] = yk;
+    for (int i = threadIdx.x; i < k; i += kBlock) y[i] -= A[(long long)k * n + i] * yk;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += kBlock) L.x[i] = (float)y[i];
+}
+
+// ------------------------------------------------------------------------------------
+// a6: V-cycle pieces
+// ------------------------------------------------------------------------------------
+// Damped Jacobi sweep dst = src + omega D^{-1} (b - A src)  (first: src = 0).
+// With want_dot, also the partial of sum_j dst_j b_j (alpha^2 on level 0).
+__global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l, int first,
+                                                  int src_sel, int dst_sel, int want_dot) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < L.n) {
+    const float *__restrict__ b = L.b;
+    float *dst = lvbuf(L, dst_sel);
+    float xn;
+    if (first) {
+      xn = D.omega * L.dinv[j] * b[j];
+    } else {
+      const float *__restrict__ src = lvbuf(L, src_sel);
+      const Coord c = coord_of(j, L.nx, L.ny);
+      const float ax = stencil(D, l, src, j, c);
+      xn = src[j] + D.omega * L.dinv[j] * (b[j] - ax);
+    }
+    dst[j] = xn;
+    if (want_dot) dot = (double)xn * (double)b[j];
+  }
+  if (want_dot) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// Chebyshev start: r = b - A x (or r = b when x = 0), d = D^{-1} r / theta -> d buffer.
+__global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, int l, int zero_x,
+                                                      int d_sel) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= L.n) return;
+  float r = L.b[j];
+  if (!zero_x) {
+    const Coord c = coord_of(j, L.nx, L.ny);
+    r -= stencil(D, l, L.x, j, c);
+  }
+  L.r[j] = r;
+  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * L.dinv[j] * r;
+}
+
+// One Chebyshev step: x += d (x = d when set_x); r -= A d (if update_r);
+// d' = c_dd d + c_dr D^{-1} r (if !last). d is read from d_sel, d' written to dn_sel.
+// With want_dot, partial of sum x_j b_j after the update.
+__global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, int l, int set_x,
+                                                     int update_r, int last, int d_sel, int dn_sel,
+                                                     int step, int want_dot) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  // rho_0 = 1/sigma, rho_{k+1} = 1/(2 sigma - rho_k); d' = rho_{k+1} rho_k d + 2 rho_{k+1}/delta D^{-1} r
+  double rho = 1.0 / D.cheb_sigma;
+  for (int i = 0; i < step; ++i) rho = 1.0 / (2.0 * D.cheb_sigma - rho);
+  const double rho_next = 1.0 / (2.0 * D.cheb_sigma - rho);
+  const float c_dd = (float)(rho_next * rho), c_dr = (float)(2.0 * rho_next / D.cheb_delta);
+  double dot = 0.0;
+  if (j < L.n) {
+    const float *__restrict__ d = lvbuf(L, d_sel);
+    const float dj = d[j];
+    const float xn = set_x ? dj : L.x[j] + dj;
+    L.x[j] = xn;
+    if (want_dot) dot = (double)xn * (double)L.b[j];
+    if (update_r) {
+      const Coord c = coord_of(j, L.nx, L.ny);
+      const float r = L.r[j] - stencil(D, l, d, j, c);
+      L.r[j] = r;
+      if (!last) lvbuf(L, dn_sel)[j] = c_dd * dj + c_dr * L.dinv[j] * r;
+    }
+  }
+  if (want_dot) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// Restriction of the residual: b_{l+1}[J] = sum over children j of J of (b - A_l x)_j,
+// or of a stored residual r_l when use_r.
+__global__ void __launch_bounds__(kBlock) k_restrict(InstDesc *const *descs, int l, int x_sel,
+                                                    int use_r) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &F = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (J >= Cl.n) return;
+  const Coord cc = coord_of(J, Cl.nx, Cl.ny);
+  const int cz = (F.nz > 1) ? 2 : 1;
+  const float *__restrict__ x = lvbuf(F, x_sel);
+  float s = 0.f;
+  for (int dz = 0; dz < cz; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        Coord fc;
+        fc.x = 2 * cc.x + dx;
+        fc.y = 2 * cc.y + dy;
+        fc.z = cz * cc.z + dz;
+        const long long j = fc.x + (long long)F.nx * (fc.y + (long long)F.ny * fc.z);
+        s += use_r ? F.r[j] : F.b[j] - stencil(D, l, x, j, fc);
+      }
+  Cl.b[J] = s;
+}
+
+// Prolongation: x_l[j] += x_{l+1}[parent(j)].
+__global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int l, int x_sel) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &F = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= F.n) return;
+  const Coord c = coord_of(j, F.nx, F.ny);
+  const int cz = (F.nz > 1) ? 2 : 1;
+  const long long J = (c.x >> 1) + (long long)Cl.nx * ((c.y >> 1) + (long long)Cl.ny * (c.z / cz));
+  lvbuf(F, x_sel)[j] += Cl.x[J];
+}
+
+// ------------------------------------------------------------------------------------
+// a4/a5/a10: forward and adjoint products
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void epilogue(const InstDesc &D, int epi, long long j, float y,
+                                         float *out, double &dot) {
+  const double *sc = D.sc;
+  switch (epi) {
+    case EPI_FWD: {
+      const float c1 = (float)sc[SC_SV], c2 = (float)(sc[SC_ALPHA] * sc[SC_SU]);
+      const float un = c1 * y - c2 * D.u[j];
+      D.u[j] = un;
+      dot = (double)un * (double)un;
+      break;
+    }
+    case EPI_ADJ: {
+      const float c1 = (float)sc[SC_SU], c2 = (float)(sc[SC_BETA] * sc[SC_SV]);
+      D.p[j] = c1 * y - c2 * D.p[j];
+      break;
+    }
+    case EPI_ADJ_INIT: D.p[j] = (float)sc[SC_SU] * y; break;
+    case EPI_RESID: {
+      const double e = (double)D.g[j] - (double)y;
+      dot = e * e;
+      break;
+    }
+    default: out[j] = y; break;
+  }
+}
+
+// One 1D correlation pass of the separable blur along `axis`, zero outside the grid.
+// adj selects the reversed taps (the adjoint). The last pass applies the epilogue.
+__global__ void __launch_bounds__(kBlock) k_blur_pass(InstDesc *const *descs, int axis,
+                                                     int src_sel, int dst_sel, int adj, int epi) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < D.n) {
+    const int nx = D.nx, ny = D.ny;
+    const Coord c = coord_of(j, nx, ny);
+    const int pos = (axis == 0) ? c.x : (axis == 1) ? c.y : c.z;
+    const int ext = (axis == 0) ? nx : (axis == 1) ? ny : D.nz;
+    const long long stride = (axis == 0) ? 1 : (axis == 1) ? (long long)nx : (long long)nx * ny;
+    const int r = D.radius;
+    const float *__restrict__ src = vec_of(D, src_sel);
+    const int klo = -min(r, pos), khi = min(r, ext - 1 - pos);
+    float y = 0.f;
+    for (int k = klo; k <= khi; ++k) {
+      const float w = D.taps[adj ? (r - k) : (r + k)];
+      y += w * src[j + k * stride];
+    }
+    epilogue(D, epi, j, y, vec_of(D, dst_sel), dot);
+  }
+  if (epi == EPI_FWD || epi == EPI_RESID) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// Dense forward product y = A x for kRows rows per block, epilogue per row.
+template <int kRows>
+__global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, int src_sel, int epi) {
+  const InstDesc &D = inst(descs);
+  const long long row0 = (long long)blockIdx.x * kRows;
+  const long long n = D.n;
+  const float *__restrict__ x = vec_of(D, src_sel);
+  const float *__restrict__ A = D.A;
+  float acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+  const int nrows = (int)min((long long)kRows, max(0LL, D.m - row0));
+  if ((n & 3) == 0) {
+    const long long n4 = n >> 2;
+    const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
+    for (long long c = threadIdx.x; c < n4; c += kBlock) {
+      const float4 xv = x4[c];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        if (r < nrows) {
+          const float4 a = reinterpret_cast<const float4 *>(A + (row0 + r) * n)[c];
+          acc[r] += a.x * xv.x + a.y * xv.y + a.z * xv.z + a.w * xv.w;
+        }
+      }
+    }
+  } else {
+    for (long long c = threadIdx.x; c < n; c += kBlock) {
+      const float xv = x[c];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r)
+        if (r < nrows) acc[r] += A[(row0 + r) * n + c] * xv;
+    }
+  }
+  __shared__ float ys[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const float s = block_sum_f(acc[r]);
+    if (threadIdx.x == 0) ys[r] = s;
+  }
+  __syncthreads();
+  double dot = 0.0;
+  if (threadIdx.x < nrows) {
+    const long long i = row0 + threadIdx.x;
+    epilogue(D, epi, i, ys[threadIdx.x], nullptr, dot);
+  }
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+}
+
+// Dense adjoint, stage 1: column partial sums over a chunk of rows.
+// grid (ceil(n/(4*kBlock)), B, chunks); colpart[chunk][col] = sum_{rows in chunk} A[row][col] u[row]
+__global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long n = D.n, m = D.m;
+  const int chunks = D.colchunks;
+  const int ch = blockIdx.z;
+  if (ch >= chunks) return;
+  const long long rc = (m + chunks - 1) / chunks;
+  const long long r0 = ch * rc, r1 = min(m, r0 + rc);
+  const float *__restrict__ A = D.A;
+  const float *__restrict__ u = D.u;
+  float *__restrict__ out = D.colpart + (long long)ch * n;
+  if ((n & 3) == 0) {
+    const long long c4 = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c4 * 4 >= n) return;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (long long r = r0; r < r1; ++r) {
+      const float ur = u[r];
+      const float4 a = reinterpret_cast<const float4 *>(A + r * n)[c4];
+      acc.x += a.x * ur;
+      acc.y += a.y * ur;
+      acc.z += a.z * ur;
+      acc.w += a.w * ur;
+    }
+    reinterpret_cast<float4 *>(out)[c4] = acc;
+  } else {
+    const long long c0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4;
+    for (int q = 0; q < 4; ++q) {
+      const long long c = c0 + q;
+      if (c >= n) break;
+      float acc = 0.f;
+      for (long long r = r0; r < r1; ++r) acc += A[r * n + c] * u[r];
+      out[c] = acc;
+    }
+  }
+}
+
+// Dense adjoint, stage 2: sum the chunk partials and apply the epilogue.
+__global__ void __launch_bounds__(kBlock) k_colsum(InstDesc *const *descs, int epi) {
+  const InstDesc &D = inst(descs);
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= D.n) return;
+  float y = 0.f;
+  for (int ch = 0; ch < D.colchunks; ++ch) y += D.colpart[(long long)ch * D.n + c];
+  double dot = 0.0;
+  epilogue(D, epi, c, y, nullptr, dot);
+}
+
+// ------------------------------------------------------------------------------------
+// a3/a7/a8/a9: copies, reductions, rotations, updates
+// ------------------------------------------------------------------------------------
+// Start of outer step k: reset the per-step Krylov flags.
+__global__ void k_outer_begin(InstDesc *const *descs, int nblocks_unused) {
+  const InstDesc &D = inst(descs);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double *sc = D.sc;
+    sc[SC_OUTER] += 1.0;
+    sc[SC_STOP] = (sc[SC_STATUS] != 0.0) ? 1.0 : 0.0;
+    sc[SC_DONE] = 0.0;
+    sc[SC_SU] = 0.0;
+    sc[SC_SV] = 0.0;
+    sc[SC_ALPHA] = 0.0;
+    sc[SC_BETA] = 0.0;
+  }
+  (void)nblocks_unused;
+}
+
+// Start of a request: zero f and the scalar block.
+__global__ void __launch_bounds__(kBlock) k_request_begin(InstDesc *const *descs, float tau_unused) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j < D.n) D.f[j] = 0.f;
+  if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) {
+    D.sc[threadIdx.x] = (threadIdx.x == SC_LAMBDA) ? sqrt(D.tau) : 0.0;
+  }
+  (void)tau_unused;
+}
+
+// u = g, partial ||g||^2 (first step of Algorithm 2).
+__global__ void __launch_bounds__(kBlock) k_copy_g_u(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < D.m) {
+    const float gj = D.g[j];
+    D.u[j] = gj;
+    dot = (double)gj * (double)gj;
+  }
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+}
+
+// Deterministic sum of the partials, then the scalar recurrences.
+__global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int nparts, int what) {
+  const InstDesc &D = inst(descs);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += D.part[i];
+  s = block_sum(s);
+  if (threadIdx.x != 0) return;
+  double *sc = D.sc;
+  const int k = (int)sc[SC_OUTER];
+  double *dg = D.diag + (long long)k * DG_COUNT;
+  auto fail = [&](int code) {
+    if (sc[SC_STATUS] == 0.0) sc[SC_STATUS] = (double)code;
+    sc[SC_STOP] = 1.0;
+  };
+  switch (what) {
+    case FIN_BETA_INIT: {
+      const double beta = sqrt(s);
+      if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
+      if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
+      sc[SC_BETA] = beta;
+      sc[SC_SU] = 1.0 / beta;
+      sc[SC_PHIBAR] = beta;
+      break;
+    }
+    case FIN_ALPHA_INIT: {
+      if (sc[SC_STOP] != 0.0) break;
+      if (!isfinite(s)) { fail(PLSQR_E_NONFINITE); break; }
+      if (s < 0.0) { fail(PLSQR_E_NOT_SPD); break; }
+      const double alpha = sqrt(s);
+      if (alpha <= kTiny) { sc[SC_STOP] = 1.0; break; }
+      sc[SC_ALPHA] = alpha;
+      sc[SC_SV] = 1.0 / alpha;
+      sc[SC_RHOBAR] = alpha;
+      break;
+    }
+    case FIN_BETA: {
+      if (sc[SC_STOP] != 0.0) break;
+      const double beta = sqrt(s);
+      if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
+      if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
+      sc[SC_BETA] = beta;
+      sc[SC_SU] = 1.0 / beta;
+      break;
+    }
+    case FIN_ALPHA: {
+      if (sc[SC_STOP] != 0.0) break;
+      if (!isfinite(s)) { fail(PLSQR_E_NONFINITE); break; }
+      if (s < 0.0) { fail(PLSQR_E_NOT_SPD); break; }
+      const double alpha = sqrt(s);
+      if (alpha <= kTiny) { sc[SC_STOP] = 1.0; break; }
+      const double beta = sc[SC_BETA], lam = sc[SC_LAMBDA];
+      double rhobar = sc[SC_RHOBAR], phibar = sc[SC_PHIBAR];
+      // damping rotation (row sqrt(tau) of (3.6)), then the Givens rotation with beta
+      const double rhohat = hypot(rhobar, lam);
+      const double c1 = rhobar / rhohat;
+      phibar = c1 * phibar;
+      const double rho = hypot(rhohat, beta);
+      const double c = rhohat / rho, sn = beta / rho;
+      const double theta = sn * alpha;
+      rhobar = -c * alpha;
+      const double phi = c * phibar;
+      phibar = sn * phibar;
+      sc[SC_CF] = phi / rho;
+      sc[SC_CW] = theta / rho;
+      sc[SC_RHOBAR] = rhobar;
+      sc[SC_PHIBAR] = phibar;
+      sc[SC_ALPHA] = alpha;
+      sc[SC_SV] = 1.0 / alpha;
+      sc[SC_DONE] += 1.0;
+      break;
+    }
+    case FIN_RESID: {
+      dg[DG_RESID] = sqrt(s);
+      dg[DG_INNER] = sc[SC_DONE];
+      dg[DG_STATUS] = sc[SC_STATUS];
+      break;
+    }
+    case FIN_PENALTY: {
+      dg[DG_PENALTY] = s;
+      break;
+    }
+    default: break;
+  }
+}
+
+// Initialisation of the update vectors: w = v / alpha_1, f = 0.
+__global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= D.n) return;
+  const bool stop = D.sc[SC_STOP] != 0.0;
+  D.f[j] = 0.f;
+  D.w[j] = stop ? 0.f : (float)D.sc[SC_SV] * D.v[j];
+}
+
+// f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step).
+__global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= D.n) return;
+  const double *sc = D.sc;
+  if (sc[SC_STOP] != 0.0) return;
+  const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
+  const float wj = D.w[j];
+  D.f[j] += cf * wj;
+  D.w[j] = sv * D.v[j] - cw * wj;
+}
+
+// partial of v . p (alpha^2 when the V-cycle is a single exact solve)
+__global__ void __launch_bounds__(kBlock) k_dot_vp(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < D.n) dot = (double)D.v[j] * (double)D.p[j];
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+}
+
+// Copy f^K to the caller's buffer if the request succeeded.
+__global__ void __launch_bounds__(kBlock) k_copy_out(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= D.n) return;
+  if (D.sc[SC_STATUS] != 0.0) return;
+  D.out_f[j] = D.f[j];
+}
+
+// ------------------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------------------
+static inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+#define LAUNCH(kern, gx, gy, ...) \
+  hipLaunchKernelGGL(kern, dim3(gx, gy), dim3(kBlock), 0, st, __VA_ARGS__)
+
+void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_request_begin, blocks_for(n), B, d, 0.f);
+}
+void launch_outer_begin(hipStream_t st, InstDesc *const *d, int B) {
+  hipLaunchKernelGGL(k_outer_begin, dim3(1, B), dim3(64), 0, st, d, 0);
+}
+int launch_diffusivity(hipStream_t st, InstDesc *const *d, int B, long long n, int write_kappa) {
+  const unsigned g = blocks_for(n);
+  LAUNCH(k_diffusivity, g, B, d, write_kappa);
+  return (int)g;
+}
+void launch_level0_dinv(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_level0_dinv, blocks_for(n), B, d);
+}
+void launch_coarsen(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse) {
+  LAUNCH(k_coarsen, blocks_for(n_coarse), B, d, l);
+}
+void launch_level_dinv(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l) {
+  LAUNCH(k_level_dinv, blocks_for(n_l), B, d, l);
+}
+void launch_coarse_factor(hipStream_t st, InstDesc *const *d, int B) {
+  LAUNCH(k_coarse_factor, 1, B, d);
+}
+void launch_coarse_solve(hipStream_t st, InstDesc *const *d, int B) {
+  LAUNCH(k_coarse_solve, 1, B, d);
+}
+int launch_jacobi(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int first,
+                  int src, int dst, int want_dot) {
+  const unsigned g = blocks_for(n_l);
+  LAUNCH(k_jacobi, g, B, d, l, first, src, dst, want_dot);
+  return (int)g;
+}
+void launch_cheb_start(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int zero_x,
+                       int d_sel) {
+  LAUNCH(k_cheb_start, blocks_for(n_l), B, d, l, zero_x, d_sel);
+}
+int launch_cheb_step(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
+                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot) {
+  const unsigned g = blocks_for(n_l);
+  LAUNCH(k_cheb_step, g, B, d, l, set_x, update_r, last, d_sel, dn_sel, step, want_dot);
+  return (int)g;
+}
+void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
+                     int x_sel, int use_r) {
+  LAUNCH(k_restrict, blocks_for(n_coarse), B, d, l, x_sel, use_r);
+}
+void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel) {
+  LAUNCH(k_prolong, blocks_for(n_l), B, d, l, x_sel);
+}
+int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
+                     int dst, int adj, int epi) {
+  const unsigned g = blocks_for(n);
+  LAUNCH(k_blur_pass, g, B, d, axis, src, dst, adj, epi);
+  return (int)g;
+}
+constexpr int kGemvRows = 4;
+int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi) {
+  const unsigned g = (unsigned)((m + kGemvRows - 1) / kGemvRows);
+  LAUNCH(k_gemv_rows<kGemvRows>, g, B, d, src, epi);
+  return (int)g;
+}
+void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks) {
+  const unsigned gx = (unsigned)((n + 4 * kBlock - 1) / (4 * kBlock));
+  hipLaunchKernelGGL(k_gemv_cols, dim3(gx, B, chunks), dim3(kBlock), 0, st, d);
+}
+void launch_colsum(hipStream_t st, InstDesc *const *d, int B, long long n, int epi) {
+  LAUNCH(k_colsum, blocks_for(n), B, d, epi);
+}
+int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m) {
+  const unsigned g = blocks_for(m);
+  LAUNCH(k_copy_g_u, g, B, d);
+  return (int)g;
+}
+void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what) {
+  LAUNCH(k_finalize, 1, B, d, nparts, what);
+}
+void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_init_wf, blocks_for(n), B, d);
+}
+void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_update_fw, blocks_for(n), B, d);
+}
+int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  const unsigned g = blocks_for(n);
+  LAUNCH(k_dot_vp, g, B, d);
+  return (int)g;
+}
+void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_copy_out, blocks_for(n), B, d);
+}
+
+}  // namespace plsqr

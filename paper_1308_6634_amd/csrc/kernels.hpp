@@ -1,0 +1,43 @@
+// Host-side launchers of the batched HIP kernels. Each takes the stream, a device array
+// of B instance-descriptor pointers and the largest extent among the B instances; the
+// ones that reduce return the number of partials written per instance.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "plsqr_internal.hpp"
+
+namespace plsqr {
+
+// level buffer selectors
+enum LevelBuf : int { LB_X = 0, LB_B, LB_R, LB_T, LB_S };
+
+void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_outer_begin(hipStream_t st, InstDesc *const *d, int B);
+int launch_diffusivity(hipStream_t st, InstDesc *const *d, int B, long long n, int write_kappa);
+void launch_level0_dinv(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_coarsen(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse);
+void launch_level_dinv(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l);
+void launch_coarse_factor(hipStream_t st, InstDesc *const *d, int B);
+void launch_coarse_solve(hipStream_t st, InstDesc *const *d, int B);
+int launch_jacobi(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int first,
+                  int src, int dst, int want_dot);
+void launch_cheb_start(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int zero_x,
+                       int d_sel);
+int launch_cheb_step(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
+                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot);
+void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
+                     int x_sel, int use_r);
+void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel);
+int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
+                     int dst, int adj, int epi);
+int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi);
+void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
+void launch_colsum(hipStream_t st, InstDesc *const *d, int B, long long n, int epi);
+int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m);
+void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what);
+void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n);
+int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
+
+}  // namespace plsqr

@@ -1,0 +1,92 @@
+// Internal device-side layout shared by the HIP kernels and the host engine.
+//
+// One reconstruction ("instance") owns one contiguous workspace holding its Krylov
+// vectors, its multigrid hierarchy, its FP64 scalar block and reduction partials. A
+// POD descriptor (InstDesc) in that workspace records every pointer and parameter;
+// kernels receive a device array of descriptor pointers and work on instance
+// blockIdx.y, so one launch serves a whole batch of instances.
+#pragma once
+#include <cstdint>
+
+#include "../../include/plsqr.h"
+
+namespace plsqr {
+
+constexpr int kMaxLevels = PLSQR_MAX_LEVELS;
+constexpr int kMaxTaps = 2 * PLSQR_MAX_RADIUS + 1;
+constexpr int kBlock = 256;          // threads per block for grid kernels (4 wave64)
+constexpr double kTiny = 1e-300;     // exact-termination threshold for alpha, beta
+
+// FP64 scalar block of one instance (MLSQR state of Algorithm 2 with damping).
+enum ScalarSlot : int {
+  SC_ALPHA = 0,   // alpha_i (true value)
+  SC_BETA,        // beta_i
+  SC_RHOBAR,      // rho_bar_i
+  SC_PHIBAR,      // phi_bar_i
+  SC_SU,          // 1/beta_i: scale of the stored (unnormalised) u
+  SC_SV,          // 1/alpha_i: scale of the stored p and v
+  SC_CF,          // phi_i / rho_i   (f update)
+  SC_CW,          // theta_{i+1} / rho_i (w update)
+  SC_STOP,        // 1 once the Krylov process terminated (breakdown) this outer step
+  SC_DONE,        // MLSQR steps completed in this outer step
+  SC_STATUS,      // 0 or a PLSQR_E_* code (sticky for the whole request)
+  SC_OUTER,       // current outer index k (0 before the first)
+  SC_LAMBDA,      // sqrt(tau)
+  SC_COUNT = 16
+};
+
+// Per-outer diagnostic record layout (doubles).
+enum DiagSlot : int { DG_RESID = 0, DG_PENALTY, DG_INNER, DG_STATUS, DG_COUNT = 4 };
+
+struct LevelDesc {
+  int nx, ny, nz, pad;
+  long long n;
+  float *x, *b, *r, *t, *s;          // iterate, rhs, residual and two scratch vectors
+  float *wx, *wy, *wz;               // face weights to the +x/+y/+z neighbour (levels >= 1)
+  float *dinv;                       // 1 / diag(A_l)
+  double eps;                        // eps_l = 2^{d l} eps
+};
+
+struct InstDesc {
+  int nx, ny, nz, levels;
+  long long n;                       // n_X
+  long long m;                       // n_Y
+  int reg, op_kind, radius, smoother;
+  int nu_pre, nu_post, cheb_degree, dims;
+  float T, omega;
+  double tau, eps;
+  double cheb_theta, cheb_delta, cheb_sigma;
+  float taps[kMaxTaps];
+  const float *g;                    // data (n_Y)
+  const float *A;                    // dense operator (row-major n_Y x n_X) or null
+  float *f, *u, *p, *v, *w, *kappa;  // Krylov vectors (u has n_Y entries)
+  float *tmp1, *tmp2;                // blur pass buffers
+  float *colpart;                    // dense adjoint: per-row-chunk column partial sums
+  float *out_f;                      // caller's output
+  double *sc;                        // scalar block (SC_COUNT)
+  double *part;                      // per-block reduction partials
+  double *cfac;                      // coarsest-level dense Cholesky factor (nc x nc, lower)
+  double *diag;                      // (outer + 1) x DG_COUNT records
+  int nc, colchunks;
+  LevelDesc lv[kMaxLevels];
+};
+
+// Selectors for vectors inside an instance (kernels are batched, so they cannot take
+// per-instance pointers directly).
+enum VecSel : int { V_F = 0, V_U, V_P, V_V, V_W, V_TMP1, V_TMP2, V_G };
+
+// Epilogues of the last pass of a forward/adjoint product.
+enum Epi : int {
+  EPI_STORE = 0,    // out = y
+  EPI_FWD,          // u <- sv * y - (alpha * su) * u, partial ||u||^2
+  EPI_ADJ,          // p <- su * y - (beta * sv) * p
+  EPI_ADJ_INIT,     // p <- su * y
+  EPI_RESID         // partial ||g - y||^2 (nothing stored)
+};
+
+// Reduction finalisers (one block per instance).
+enum Fin : int {
+  FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY
+};
+
+}  // namespace plsqr

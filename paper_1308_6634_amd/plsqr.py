@@ -1,0 +1,206 @@
+"""ctypes binding of ``libplsqr.so`` (argument marshalling only).
+
+The functions carry the C names and follow the C ABI of ``include/plsqr.h``. Calls that
+fail with a negative status raise ``PlsqrError``; ``plsqr_poll`` returns the status of a
+finished request (it only raises for an unknown ticket or a bad engine). Device memory
+and streams come from PyTorch: pass ``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``.
+
+Importing this module loads the library and fails loudly if it is missing: there is no
+fallback implementation.
+"""
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library then shares with torch)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplsqr.so")
+
+PLSQR_OK = 0
+PLSQR_PENDING = 1
+PLSQR_E_INVALID = -1
+PLSQR_E_NOMEM = -2
+PLSQR_E_BUDGET = -3
+PLSQR_E_HIP = -4
+PLSQR_E_NOT_SPD = -5
+PLSQR_E_NONFINITE = -6
+PLSQR_E_UNKNOWN_TICKET = -7
+
+PLSQR_OP_BLUR = 1
+PLSQR_OP_DENSE = 2
+PLSQR_REG_TIKHONOV, PLSQR_REG_STV, PLSQR_REG_PM_LOG, PLSQR_REG_PM_EXP = 0, 1, 2, 3
+PLSQR_SMOOTH_JACOBI, PLSQR_SMOOTH_CHEBYSHEV = 0, 1
+PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED = 0, 1
+PLSQR_ENGINE_SERVE = 1
+PLSQR_FLAG_TIME_PRODUCTS = 1
+PLSQR_MAX_LEVELS = 12
+PLSQR_MAX_OUTER = 64
+PLSQR_MAX_RADIUS = 16
+PLSQR_MAX_COARSE = 512
+
+REG_CODES = {"tikhonov": PLSQR_REG_TIKHONOV, "stv": PLSQR_REG_STV, "pm_log": PLSQR_REG_PM_LOG,
+             "pm_exp": PLSQR_REG_PM_EXP}
+SMOOTHER_CODES = {"jacobi": PLSQR_SMOOTH_JACOBI, "chebyshev": PLSQR_SMOOTH_CHEBYSHEV}
+
+EXPORTED = ("plsqr_create", "plsqr_set_operator", "plsqr_solve", "plsqr_poll", "plsqr_wait_all",
+            "plsqr_destroy", "plsqr_last_error", "plsqr_auto_levels", "plsqr_workspace_bytes")
+
+
+class plsqr_operator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("radius", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("taps", ctypes.POINTER(ctypes.c_float)), ("n_y", ctypes.c_int64),
+                ("A_dev", ctypes.c_void_p), ("A_hi_dev", ctypes.c_void_p),
+                ("A_lo_dev", ctypes.c_void_p)]
+
+
+class plsqr_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reg", ctypes.c_int32), ("T", ctypes.c_double), ("tau", ctypes.c_double),
+                ("eps", ctypes.c_double), ("outer", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("cheb_degree", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved0", ctypes.c_int32)]
+
+
+class plsqr_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_done", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("inner_done", ctypes.c_int32 * PLSQR_MAX_OUTER),
+                ("resid", ctypes.c_double * PLSQR_MAX_OUTER),
+                ("penalty", ctypes.c_double * PLSQR_MAX_OUTER),
+                ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("product_ms", ctypes.c_double), ("product_launches", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+class PlsqrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"plsqr error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1308_6634_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.plsqr_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                 ctypes.c_uint32]
+    lib.plsqr_set_operator.argtypes = [ctypes.c_void_p, P(plsqr_operator), P(ctypes.c_int32)]
+    lib.plsqr_solve.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(plsqr_problem), ctypes.c_void_p,
+                                ctypes.c_void_p, P(ctypes.c_uint64)]
+    lib.plsqr_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(plsqr_result)]
+    lib.plsqr_wait_all.argtypes = [ctypes.c_void_p]
+    lib.plsqr_destroy.argtypes = [ctypes.c_void_p]
+    lib.plsqr_last_error.argtypes = [ctypes.c_void_p]
+    lib.plsqr_last_error.restype = ctypes.c_char_p
+    lib.plsqr_auto_levels.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.plsqr_workspace_bytes.argtypes = [P(plsqr_problem), ctypes.c_int32, ctypes.c_int64]
+    lib.plsqr_workspace_bytes.restype = ctypes.c_uint64
+    for name in EXPORTED:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc, eng=None):
+    if rc < 0:
+        raise PlsqrError(rc, _lib.plsqr_last_error(eng).decode())
+    return rc
+
+
+def plsqr_create(device=0, hbm_budget_bytes=0, hip_stream=None, flags=0):
+    eng = ctypes.c_void_p()
+    _check(_lib.plsqr_create(ctypes.byref(eng), device, hbm_budget_bytes, hip_stream, flags))
+    return eng
+
+
+def plsqr_set_operator(eng, op):
+    op_id = ctypes.c_int32()
+    _check(_lib.plsqr_set_operator(eng, ctypes.byref(op), ctypes.byref(op_id)), eng)
+    return op_id.value
+
+
+def plsqr_solve(eng, op_id, prob, g_dev, f_dev):
+    ticket = ctypes.c_uint64()
+    _check(_lib.plsqr_solve(eng, op_id, ctypes.byref(prob), g_dev, f_dev, ctypes.byref(ticket)), eng)
+    return ticket.value
+
+
+def plsqr_poll(eng, ticket):
+    """Returns (status, plsqr_result or None). status is PLSQR_PENDING, PLSQR_OK or a
+    request error; an unknown ticket raises."""
+    res = plsqr_result()
+    rc = _lib.plsqr_poll(eng, ticket, ctypes.byref(res))
+    if rc in (PLSQR_E_UNKNOWN_TICKET, PLSQR_E_INVALID):
+        _check(rc, eng)
+    return rc, (None if rc == PLSQR_PENDING else res)
+
+
+def plsqr_wait_all(eng):
+    return _check(_lib.plsqr_wait_all(eng), eng)
+
+
+def plsqr_destroy(eng):
+    return _check(_lib.plsqr_destroy(eng))
+
+
+def plsqr_last_error(eng=None):
+    return _lib.plsqr_last_error(eng).decode()
+
+
+def plsqr_auto_levels(nx, ny, nz):
+    return _lib.plsqr_auto_levels(nx, ny, nz)
+
+
+def plsqr_workspace_bytes(prob, op_kind, n_y):
+    return _lib.plsqr_workspace_bytes(ctypes.byref(prob), op_kind, n_y)
+
+
+# ---- marshalling helpers -----------------------------------------------------------
+
+def blur_operator(dims, taps):
+    """plsqr_operator for a separable blur on dims = (nx, ny, nz); taps is a float32 array."""
+    import numpy as np
+    t = np.ascontiguousarray(taps, dtype=np.float32)
+    op = plsqr_operator()
+    op.kind = PLSQR_OP_BLUR
+    op.nx, op.ny, op.nz = dims
+    op.radius = (len(t) - 1) // 2
+    op.taps = t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    op._keep = t
+    return op
+
+
+def dense_operator(dims, n_y, A_dev, A_hi_dev=None, A_lo_dev=None):
+    op = plsqr_operator()
+    op.kind = PLSQR_OP_DENSE
+    op.nx, op.ny, op.nz = dims
+    op.n_y = n_y
+    op.A_dev = A_dev
+    op.A_hi_dev = A_hi_dev
+    op.A_lo_dev = A_lo_dev
+    return op
+
+
+def make_problem(dims, reg="stv", T=0.01, tau=1.0, eps=1e-6, outer=1, inner=1, levels=0,
+                 smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8, cheb_degree=3,
+                 cheb_lo=1.0 / 3.0, cheb_hi=2.0, precision=PLSQR_PREC_FP32, flags=0):
+    pb = plsqr_problem()
+    pb.nx, pb.ny, pb.nz = dims
+    pb.reg = REG_CODES[reg] if isinstance(reg, str) else int(reg)
+    pb.T, pb.tau, pb.eps = T, tau, eps
+    pb.outer, pb.inner, pb.mg_levels = outer, inner, levels
+    pb.smoother = SMOOTHER_CODES[smoother] if isinstance(smoother, str) else int(smoother)
+    pb.nu_pre, pb.nu_post, pb.omega = nu_pre, nu_post, omega
+    pb.cheb_degree, pb.cheb_lo, pb.cheb_hi = cheb_degree, cheb_lo, cheb_hi
+    pb.precision, pb.flags = precision, flags
+    return pb

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Bar (FP32 vectors, FP64 Krylov scalars): relative L2 error of f^K <= 1e-3 at identical
+outer x inner counts, multigrid and smoother settings. Per-outer diagnostics
+(||g - A f^k||, R(f^k)) are compared to the same relative tolerance.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import lagged
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def engine():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1308_6634_amd.engine import Engine
+    eng = Engine(0)
+    yield eng
+    eng.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) /
+                 max(np.linalg.norm(np.asarray(b, float)), 1e-300))
+
+
+def _check(problem, engine, tol=TOL):
+    from paper_1308_6634_amd.engine import solve
+    _say(f"[parity] {problem.name} dims={problem.dims} op={problem.op_kind} reg={problem.reg} "
+         f"{problem.outer}x{problem.inner} L={problem.levels} {problem.smoother}")
+    f_gpu, res = solve(problem, engine=engine)
+    f_ref, rec = lagged.solve_problem(problem)
+    err = _rel(f_gpu, f_ref)
+    _say(f"[parity] {problem.name}: rel L2 = {err:.3e}")
+    assert np.all(np.isfinite(f_gpu))
+    assert err <= tol, err
+    for k, r in enumerate(rec):
+        assert res.inner_done[k] == r["inner_done"]
+        assert abs(res.resid[k] - r["resid"]) <= tol * max(abs(r["resid"]), 1e-30)
+        assert abs(res.penalty[k] - r["penalty"]) <= tol * max(abs(r["penalty"]), 1e-30)
+    return err
+
+
+def test_c1_full_size(engine):
+    _check(gen.config_c1(), engine)
+
+
+@pytest.mark.parametrize("reg,T", [("stv", 0.05), ("pm_log", 0.1), ("pm_exp", 0.1),
+                                   ("tikhonov", 1.0)])
+def test_blur_3d_jacobi_regularizers(engine, reg, T):
+    p = gen.small_blur_case(11, (20, 12, 8), reg=reg, T=T, tau=5.0, outer=3, inner=8, levels=2)
+    _check(p, engine)
+
+
+def test_blur_3d_chebyshev(engine):
+    p = gen.small_blur_case(12, (32, 32, 16), reg="pm_log", T=0.1, tau=20.0, outer=3, inner=10,
+                            levels=3, smoother="chebyshev", nu_pre=1, nu_post=1)
+    _check(p, engine)
+
+
+def test_blur_2d_ragged_three_levels(engine):
+    p = gen.small_blur_case(13, (40, 24, 1), reg="stv", T=0.02, tau=2.0, outer=4, inner=12,
+                            levels=3)
+    _check(p, engine)
+
+
+def test_blur_single_level_exact_prior(engine):
+    p = gen.small_blur_case(14, (16, 16, 1), reg="stv", T=0.05, tau=1.0, outer=3, inner=10,
+                            levels=1)
+    _check(p, engine)
+
+
+def test_blur_radius_exceeds_grid(engine):
+    p = gen.small_blur_case(15, (6, 5, 3), sigma=4.0, radius=8, reg="pm_log", T=0.1, tau=1.0,
+                            outer=2, inner=6, levels=1)
+    _check(p, engine)
+
+
+def test_blur_undamped(engine):
+    p = gen.small_blur_case(16, (24, 24, 1), reg="pm_log", T=0.05, tau=0.0, outer=2, inner=6,
+                            levels=3)
+    _check(p, engine)
+
+
+def test_blur_non_power_of_two_levels(engine):
+    p = gen.small_blur_case(17, (24, 24, 24), reg="stv", T=0.02, tau=30.0, outer=2, inner=8,
+                            levels=4)   # 24 -> 12 -> 6 -> 3 (27 coarse cells)
+    _check(p, engine)
+
+
+def test_dense_small(engine):
+    p = gen.small_dense_case(21, 8, outer=3, inner=10, levels=2)
+    _check(p, engine)
+
+
+def test_dense_16_three_levels(engine):
+    p = gen.small_dense_case(22, 16, reg="stv", T=0.02, outer=3, inner=10, levels=3)
+    _check(p, engine)
+
+
+def test_dense_unaligned_columns(engine):
+    rng = np.random.default_rng(5)
+    f = np.zeros((3, 3, 5))
+    f[1, 1, 1:4] = 1.0
+    A = (rng.standard_normal((37, 45)) / 6.0).astype(np.float32)
+    p = gen.make_dense_problem("dense_unaligned", f, rng, A, noise_frac=0.01, reg="pm_log", T=0.1,
+                               tau=1.0, eps=1e-4, outer=2, inner=6, levels=1, smoother="jacobi",
+                               nu_pre=2, nu_post=2, omega=0.8)
+    _check(p, engine)
+
+
+def test_c3_reduced_chebyshev(engine):
+    _check(gen.config_c3(n=32), engine)
+
+
+def test_c2_reduced(engine):
+    _check(gen.config_c2(n=16), engine)
+
+
+def test_zero_data_returns_zero(engine):
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import problem_struct
+    p = gen.small_blur_case(31, (16, 8, 1), outer=2, inner=4, levels=2)
+    op = engine.blur_operator(p.dims, p.taps)
+    g = torch.zeros(p.n_x, device="cuda")
+    f = torch.full((p.n_x,), 7.0, device="cuda")
+    st, res = engine.wait(engine.submit(op, problem_struct(p), g, f))
+    assert st == P.PLSQR_OK
+    assert torch.count_nonzero(f).item() == 0
+    assert list(res.inner_done[:2]) == [0, 0]
+
+
+def test_nan_data_fails_and_leaves_output(engine):
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import problem_struct
+    p = gen.small_blur_case(32, (16, 8, 1), outer=2, inner=4, levels=2)
+    op = engine.blur_operator(p.dims, p.taps)
+    g = torch.from_numpy(p.g.ravel().copy()).cuda()
+    g[5] = float("nan")
+    f = torch.full((p.n_x,), 7.0, device="cuda")
+    st, _ = engine.wait(engine.submit(op, problem_struct(p), g, f))
+    assert st == P.PLSQR_E_NONFINITE
+    assert torch.all(f == 7.0).item()
+
+
+def test_invalid_arguments_raise(engine):
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import problem_struct
+    p = gen.small_blur_case(33, (16, 8, 1), outer=1, inner=2, levels=2)
+    op = engine.blur_operator(p.dims, p.taps)
+    g = torch.zeros(p.n_x, device="cuda")
+    f = torch.zeros(p.n_x, device="cuda")
+    bad = problem_struct(p)
+    bad.nx = 15
+    with pytest.raises(P.PlsqrError) as ei:
+        engine.submit(op, bad, g, f)
+    assert ei.value.code == P.PLSQR_E_INVALID
+    bad = problem_struct(p)
+    bad.mg_levels = 5          # 16x8 cannot be halved four times
+    with pytest.raises(P.PlsqrError):
+        engine.submit(op, bad, g, f)
+    bad = problem_struct(p)
+    bad.nu_post = 1            # unsymmetric V-cycle
+    with pytest.raises(P.PlsqrError):
+        engine.submit(op, bad, g, f)
+
+
+def test_concurrent_requests_match_alone(engine):
+    """Several requests of different sizes in flight together give the same f as alone."""
+    import torch
+    from paper_1308_6634_amd.engine import problem_struct
+    cases = [gen.small_blur_case(40 + i, d, outer=2, inner=6, levels=2)
+             for i, d in enumerate([(16, 16, 8), (24, 8, 4), (16, 16, 1), (32, 16, 8)])]
+    alone = []
+    for p in cases:
+        op = engine.blur_operator(p.dims, p.taps)
+        g = torch.from_numpy(p.g.ravel().copy()).cuda()
+        f = torch.zeros(p.n_x, device="cuda")
+        st, _ = engine.wait(engine.submit(op, problem_struct(p), g, f))
+        assert st == 0
+        alone.append(f.cpu().numpy())
+    tickets, outs = [], []
+    for p in cases:
+        op = engine.blur_operator(p.dims, p.taps)
+        g = torch.from_numpy(p.g.ravel().copy()).cuda()
+        f = torch.zeros(p.n_x, device="cuda")
+        tickets.append(engine.submit(op, problem_struct(p), g, f))
+        outs.append(f)
+    for t in tickets:
+        assert engine.wait(t)[0] == 0
+    for a, f in zip(alone, outs):
+        np.testing.assert_array_equal(a, f.cpu().numpy())
+
+
+def test_budget_admission_queues_and_rejects():
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+    p = gen.small_blur_case(50, (16, 16, 8), outer=2, inner=4, levels=2)
+    need = P.plsqr_workspace_bytes(problem_struct(p), P.PLSQR_OP_BLUR, p.n_x)
+    with Engine(0, hbm_budget_bytes=int(need * 1.5)) as eng:
+        op = eng.blur_operator(p.dims, p.taps)
+        g = torch.from_numpy(p.g.ravel().copy()).cuda()
+        fs = [torch.zeros(p.n_x, device="cuda") for _ in range(3)]
+        ts = [eng.submit(op, problem_struct(p), g, f) for f in fs]   # only one fits at a time
+        for t in ts:
+            assert eng.wait(t)[0] == 0
+        for f in fs[1:]:
+            assert torch.equal(f, fs[0])
+    with Engine(0, hbm_budget_bytes=int(need // 2)) as eng:
+        op = eng.blur_operator(p.dims, p.taps)
+        with pytest.raises(P.PlsqrError) as ei:
+            eng.submit(op, problem_struct(p), g, fs[0])
+        assert ei.value.code == P.PLSQR_E_BUDGET
+
+
+@pytest.mark.parametrize("which", ["c2", "c3"])
+def test_full_size_first_iterations(engine, which):
+    """Full-size workloads in the benchmark's launch configuration, first outer step with a
+    few inner steps (the oracle's cost grows with the counts, not with the check)."""
+    if which == "c2":
+        p = gen.config_c2(outer=1, inner=2)
+    else:
+        p = gen.config_c3(outer=1, inner=3)
+    _check(p, engine)
