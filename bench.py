@@ -1,0 +1,214 @@
+#!/usr/bin/env python
+"""Throughput benchmark: voxel-LSQR-iterations per second on one MI355X.
+
+Workload (default): a 64^3 grid reconstructed from a dense 4096 x 262144 float32 ring
+sensitivity matrix (64 sources x 64 detectors on four rings), five ellipsoid
+inclusions, 1% noise, Perona-Malik (log) diffusivity T = 0.05, tau = 20, 8 outer x 40
+inner iterations, 5-level Jacobi V(2,2) priorconditioner. A step is one whole
+reconstruction (all outer and inner iterations, setup and diagnostics included) with
+inputs already resident in HBM.
+
+value = n_X * outer * inner * steps / wall seconds of the timed steps.
+
+Beside it: the roofline of the dominant kernel (the dense forward product, timed with
+HIP events on the stream it runs on) and the FP64 oracle timed on the host cores on a
+bounded sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1308_6634_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    import gen
+    if name == "c2":
+        p = gen.config_c2()
+        desc = ("64^3 grid, dense ring sensitivity 4096x262144 fp32 (64 src x 64 det, 4 rings, "
+                "mu=0.5), 5 ellipsoids, 1% noise, Perona-Malik log T=0.05, tau=20, 8 outer x 40 "
+                "inner, 5-level Jacobi V(2,2) omega=0.8, eps=1e-6")
+    elif name == "c3":
+        p = gen.config_c3()
+        desc = ("128^3 grid, separable Gaussian blur sigma=3 (19 taps), 20 boxes/spheres, 0.5% "
+                "noise, smoothed TV T=0.02, tau=100, 10 outer x 60 inner, 6-level Chebyshev(3)")
+    elif name == "c1":
+        p = gen.config_c1()
+        desc = ("64^2 image, Gaussian blur sigma=2 (9 taps), 8 rectangles, 1% noise, smoothed TV "
+                "T=0.01, tau=50, 10 outer x 50 inner, 4-level Jacobi V(2,2)")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, desc
+
+
+def dominant_bytes(p):
+    """Algorithmic HBM bytes of one dominant-kernel launch."""
+    nx, ny, nz = p.dims
+    n = nx * ny * nz
+    if p.op_kind == "dense":
+        m = p.A.shape[0]
+        return 4 * m * n + 4 * n + 8 * m, "k_gemv_rows (dense forward product A v, u update)"
+    # blur: one 1D pass reads and writes one vector (halo re-reads come from cache)
+    return 8 * n, "k_blur_pass (forward blur pass)"
+
+
+def cpu_baseline(p, target_s=15.0):
+    """The FP64 oracle on a bounded sample: the first outer iteration with S inner steps."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import lagged
+
+    nx, ny, nz = p.dims
+    shape = (nz, ny, nx)
+    op = lagged.make_operator(p.op_kind, shape, taps=p.taps, A=p.A)   # input prep, untimed
+    from oracle import multigrid
+    sm = multigrid.Smoother(p.smoother, p.nu_pre, p.nu_post, p.omega, p.cheb_degree, p.cheb_lo,
+                            p.cheb_hi)
+    g = np.asarray(p.g, dtype=np.float64).reshape(shape if p.op_kind == "blur" else (-1,))
+
+    def run(inner):
+        t0 = time.perf_counter()
+        f, _ = lagged.solve(shape, op, g, p.reg, p.T, p.tau, p.eps, 1, inner, p.levels, sm)
+        return time.perf_counter() - t0, f
+
+    t2, _ = run(2)
+    per_iter = max(t2 / 3.0, 1e-3)
+    S = int(min(p.inner, max(4, target_s / per_iter)))
+    t, f = run(S)
+    threads = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
+    cores = max(threads) if threads else 1
+    n = nx * ny * nz
+    return {"value": n * S / t, "unit": "voxel-iter/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first outer iteration with {S} inner iterations (setup included), "
+                      f"{t:.1f} s, FP64 NumPy/SciPy, host cores: {len(os.sched_getaffinity(0))}"}, S, f
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(instances shard across GPUs without communication, see the "
+                                   "design notes)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+
+    p, desc = workload(args.workload)
+    nx, ny, nz = p.dims
+    n = nx * ny * nz
+    print(f"[bench] workload {args.workload}: {desc}", file=sys.stderr, flush=True)
+    eng = Engine(0)
+    if p.op_kind == "dense":
+        op = eng.dense_operator(p.dims, p.A)
+    else:
+        op = eng.blur_operator(p.dims, p.taps)
+    g = torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda()
+    f = torch.zeros(n, dtype=torch.float32, device="cuda")
+    pb = problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS)
+
+    for _ in range(args.warmup):
+        st, _ = eng.wait(eng.submit(op, pb, g, f))
+        assert st == 0, P.plsqr_last_error(eng.handle)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [eng.submit(op, pb, g, f) for _ in range(args.steps)]
+    results = [eng.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for st, _ in results:
+        assert st == 0
+    iters = n * p.outer * p.inner * args.steps
+    value = iters / elapsed
+    fwd_ms = sum(r.forward_ms for _, r in results)
+    fwd_n = sum(r.forward_launches for _, r in results)
+    adj_ms = sum(r.adjoint_ms for _, r in results)
+    adj_n = sum(r.adjoint_launches for _, r in results)
+    avg_fwd_s = fwd_ms / max(fwd_n, 1) / 1e3
+    nbytes, kname = dominant_bytes(p)
+    achieved = nbytes / avg_fwd_s / 1e9 if avg_fwd_s > 0 else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernels_hip_sha") == kernel_source_hash() and tr.get("workload") == args.workload:
+                traffic = tr.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; forward product avg "
+          f"{avg_fwd_s * 1e3:.3f} ms, adjoint avg {adj_ms / max(adj_n, 1):.3f} ms",
+          file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "voxel-LSQR-iters/s",
+        "value": value,
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n_x": n, "n_y": int(p.n_y),
+                   "outer": p.outer, "inner": p.inner, "precision": "fp32 vectors, fp64 scalars"},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic, "bytes_per_launch": nbytes,
+                     "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
+        cb, S, f_ref = cpu_baseline(p)
+        out["cpu_baseline"] = cb
+        # the same sample on the GPU, for a parity figure at full size
+        import dataclasses
+        q = dataclasses.replace(p, outer=1, inner=S)
+        st, _ = eng.wait(eng.submit(op, problem_struct(q), g, f))
+        assert st == 0
+        fg = f.cpu().numpy().astype(np.float64).reshape(f_ref.shape)
+        out["parity_sample_rel_l2"] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

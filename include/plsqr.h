@@ -145,9 +145,11 @@ typedef struct {
   double submit_to_done_ms;           /* host wall time from plsqr_solve to completion
                                          being observed */
   double device_ms;                   /* device time of the request (HIP events) */
-  double product_ms;                  /* with PLSQR_FLAG_TIME_PRODUCTS: summed time of the
-                                         forward/adjoint product kernel launches */
-  int64_t product_launches;           /* ... and their count */
+  double forward_ms;                  /* with PLSQR_FLAG_TIME_PRODUCTS: summed device time of
+                                         the forward-product launches (A x) ... */
+  int64_t forward_launches;           /* ... and their count */
+  double adjoint_ms;                  /* same for the adjoint products (A^T u) */
+  int64_t adjoint_launches;
   int64_t workspace_bytes;            /* device memory the request held */
 } plsqr_result;
 

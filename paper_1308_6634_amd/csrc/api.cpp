@@ -122,11 +122,13 @@ void release(plsqr_engine *eng, Request &r) {
   if (r.ev_start) hipEventDestroy(r.ev_start);
   if (r.ev_end) hipEventDestroy(r.ev_end);
   r.ev_start = r.ev_end = nullptr;
-  for (auto &e : r.prod_events) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+  for (auto *lst : {&r.prod_events, &r.adj_events}) {
+    for (auto &e : *lst) {
+      hipEventDestroy(e.first);
+      hipEventDestroy(e.second);
+    }
+    lst->clear();
   }
-  r.prod_events.clear();
   if (r.ws) {
     eng->pool.put(r.ws, r.lay.total);
     eng->used -= r.lay.total;
@@ -157,8 +159,9 @@ int start_request_impl(plsqr_engine *eng, Request &r) {
   HIP_TRY(hipMemcpyAsync(d_desc, r.pinned, sizeof(InstDesc), hipMemcpyHostToDevice, eng->stream));
   HIP_TRY(hipMemcpyAsync(r.d_descs, r.pinned + pin_desc_ptr_off(), sizeof(void *),
                          hipMemcpyHostToDevice, eng->stream));
-  BatchView bv{r.d_descs, 1, &r.host, &r.lay,
-               (r.pb.flags & PLSQR_FLAG_TIME_PRODUCTS) ? &r.prod_events : nullptr};
+  const bool timed = (r.pb.flags & PLSQR_FLAG_TIME_PRODUCTS) != 0;
+  BatchView bv{r.d_descs, 1, &r.host, &r.lay, timed ? &r.prod_events : nullptr,
+               timed ? &r.adj_events : nullptr};
   enqueue_whole_solve(eng->stream, bv, r.pb.outer, r.pb.inner);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(r.pinned + pin_sc_off(), r.ws + r.lay.sc, SC_COUNT * sizeof(double),
@@ -197,13 +200,18 @@ void reap(plsqr_engine *eng, Request &r) {
   float ms = 0.f;
   if (r.ev_start && r.ev_end && hipEventElapsedTime(&ms, r.ev_start, r.ev_end) == hipSuccess)
     res.device_ms = ms;
-  double pm = 0.0;
-  for (auto &e : r.prod_events) {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) pm += t;
-  }
-  res.product_ms = pm;
-  res.product_launches = (int64_t)r.prod_events.size();
+  auto total = [](const std::vector<std::pair<hipEvent_t, hipEvent_t>> &lst) {
+    double s = 0.0;
+    for (auto &e : lst) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) s += t;
+    }
+    return s;
+  };
+  res.forward_ms = total(r.prod_events);
+  res.forward_launches = (int64_t)r.prod_events.size();
+  res.adjoint_ms = total(r.adj_events);
+  res.adjoint_launches = (int64_t)r.adj_events.size();
   res.workspace_bytes = (int64_t)r.lay.total;
   r.t_done = now_ms();
   res.submit_to_done_ms = r.t_done - r.t_submit;

@@ -140,17 +140,18 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
 // ---------------------------------------------------------------------------------
 // products
 // ---------------------------------------------------------------------------------
-static void time_begin(hipStream_t st, const BatchView &bv, hipEvent_t *a) {
-  if (!bv.prod_events) return;
+using EventList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
+static void time_begin(hipStream_t st, EventList *ev, hipEvent_t *a) {
+  if (!ev) return;
   hipEventCreate(a);
   hipEventRecord(*a, st);
 }
-static void time_end(hipStream_t st, const BatchView &bv, hipEvent_t a) {
-  if (!bv.prod_events) return;
+static void time_end(hipStream_t st, EventList *ev, hipEvent_t a) {
+  if (!ev) return;
   hipEvent_t b;
   hipEventCreate(&b);
   hipEventRecord(b, st);
-  bv.prod_events->emplace_back(a, b);
+  ev->emplace_back(a, b);
 }
 
 static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi) {
@@ -174,13 +175,14 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
 static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi) {
   const InstDesc &H = *bv.h;
   hipEvent_t a = nullptr;
-  time_begin(st, bv, &a);
+  EventList *ev = (epi == EPI_FWD) ? bv.prod_events : nullptr;
+  time_begin(st, ev, &a);
   int np;
   if (H.op_kind == PLSQR_OP_BLUR)
     np = blur_chain(st, bv, src, 0, epi);
   else
     np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi);
-  time_end(st, bv, a);
+  time_end(st, ev, a);
   return np;
 }
 
@@ -188,14 +190,15 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
 static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
   const InstDesc &H = *bv.h;
   hipEvent_t a = nullptr;
-  time_begin(st, bv, &a);
+  EventList *ev = (epi == EPI_ADJ) ? bv.adj_events : nullptr;
+  time_begin(st, ev, &a);
   if (H.op_kind == PLSQR_OP_BLUR) {
     blur_chain(st, bv, V_U, 1, epi);
   } else {
     launch_gemv_cols(st, bv.d_descs, bv.B, H.n, H.colchunks);
     launch_colsum(st, bv.d_descs, bv.B, H.n, epi);
   }
-  time_end(st, bv, a);
+  time_end(st, ev, a);
 }
 
 // ---------------------------------------------------------------------------------

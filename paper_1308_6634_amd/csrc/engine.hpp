@@ -65,7 +65,8 @@ struct Request {
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   char *pinned = nullptr;            // pinned host staging: descriptor up, scalars/records down
   size_t pinned_bytes = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prod_events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prod_events;   // forward products
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> adj_events;    // adjoint products
   double t_submit = 0.0, t_done = 0.0;
   plsqr_result result{};
   // serving mode: progress through the fixed schedule
@@ -78,7 +79,8 @@ struct BatchView {
   int B;
   const InstDesc *h;          // host copy of one member (shapes and schedule)
   const Layout *lay;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> *prod_events;  // optional timing
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> *prod_events;  // optional timing (forward)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> *adj_events;   // optional timing (adjoint)
 };
 
 // Solve driver (same sequence for one instance or a lockstep batch).

@@ -74,7 +74,8 @@ class plsqr_result(ctypes.Structure):
                 ("resid", ctypes.c_double * PLSQR_MAX_OUTER),
                 ("penalty", ctypes.c_double * PLSQR_MAX_OUTER),
                 ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
-                ("product_ms", ctypes.c_double), ("product_launches", ctypes.c_int64),
+                ("forward_ms", ctypes.c_double), ("forward_launches", ctypes.c_int64),
+                ("adjoint_ms", ctypes.c_double), ("adjoint_launches", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64)]
 
 
