@@ -53,9 +53,13 @@ enum { PLSQR_OP_BLUR = 1, PLSQR_OP_DENSE = 2 };
 enum { PLSQR_REG_TIKHONOV = 0, PLSQR_REG_STV = 1, PLSQR_REG_PM_LOG = 2, PLSQR_REG_PM_EXP = 3 };
 enum { PLSQR_SMOOTH_JACOBI = 0, PLSQR_SMOOTH_CHEBYSHEV = 1 };
 /* FP32: float32 vectors and products, float64 Krylov scalars and coarsest solve.
- * BF16_REFINED: dense products of a batch run as BF16 MFMA GEMMs with FP32
- * accumulation plus one refinement term (needs A_hi_dev, optionally A_lo_dev). */
-enum { PLSQR_PREC_FP32 = 0, PLSQR_PREC_BF16_REFINED = 1 };
+ * BF16_REFINED / BF16 (batches on a dense operator only): the dense products of the
+ * batch run as BF16 MFMA GEMMs with FP32 accumulation. Every FP32 operand v is split
+ * v = hi + lo (hi = bf16(v), lo = bf16(v - hi)); BF16_REFINED keeps the terms
+ * A_hi X_hi + A_hi X_lo + A_lo X_hi (one refinement step of the BF16 product, error
+ * ~2^-16 relative per entry), BF16 keeps A_hi X_hi + A_hi X_lo (A read once, error
+ * ~2^-9 relative per entry of A). Vectors, stencils and scalars stay FP32/FP64. */
+enum { PLSQR_PREC_FP32 = 0, PLSQR_PREC_BF16_REFINED = 1, PLSQR_PREC_BF16 = 2 };
 
 /* engine creation flags */
 enum {
@@ -170,6 +174,18 @@ int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_
  * left waits until earlier requests complete. */
 int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, const float *g_dev,
                 float *f_dev, uint64_t *ticket);
+
+/* Submit `count` reconstructions that run in lockstep on one operator (one set of
+ * launches serves all of them; with a BF16 precision the dense products become MFMA
+ * GEMMs over the batch, reading A once per product for the whole batch). The problems
+ * may differ in reg, T, tau, eps, omega and the Chebyshev interval but must share grid,
+ * counts, levels, smoother kind and steps, precision and flags. BF16 batches need a
+ * dense operator, count <= 64 and n_X, n_Y divisible by 128; the BF16 copies of A
+ * (A_hi, A_lo and their transposes) are taken from the operator if given, else built
+ * by the library on first use and kept until plsqr_destroy. tickets[i] receives the
+ * ticket of request i; every ticket completes when the whole batch does. */
+int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const plsqr_problem *probs,
+                      const float *const *g_devs, float *const *f_devs, uint64_t *tickets);
 
 /* Non-blocking completion check: PLSQR_PENDING while the request runs; otherwise the
  * request's status (PLSQR_OK or an error), with *out filled (out may be NULL). A

@@ -18,9 +18,9 @@ LIB = os.path.join(HERE, "libplsqr.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-KERNEL_SOURCES = ["kernels.hip"]
+KERNEL_SOURCES = ["kernels.hip", "gemm_bf16.hip"]
 HOST_SOURCES = ["driver.cpp", "api.cpp"]
-HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp"]
+HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp", "device_common.hpp"]
 
 # Packed-FP32 instructions are disabled for every device compile (the compiler would
 # otherwise form v_pk_* FP32 ops from ordinary float code).

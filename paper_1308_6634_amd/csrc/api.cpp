@@ -113,136 +113,329 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   (void)eng;
 }
 
-// Pinned staging layout: [InstDesc][descriptor pointer][scalars][per-outer records].
-size_t pin_desc_ptr_off() { return (sizeof(InstDesc) + 255) / 256 * 256; }
-size_t pin_sc_off() { return pin_desc_ptr_off() + 256; }
+// Pinned staging layout of a request: [InstDesc][scalars][per-outer records].
+size_t pin_sc_off() { return (sizeof(InstDesc) + 255) / 256 * 256; }
 size_t pin_dg_off() { return pin_sc_off() + SC_COUNT * sizeof(double); }
+size_t pin_bytes(const plsqr_problem &pb) {
+  return pin_dg_off() + (size_t)(pb.outer + 1) * DG_COUNT * sizeof(double);
+}
 
-void release(plsqr_engine *eng, Request &r) {
-  if (r.ev_start) hipEventDestroy(r.ev_start);
-  if (r.ev_end) hipEventDestroy(r.ev_end);
-  r.ev_start = r.ev_end = nullptr;
-  for (auto *lst : {&r.prod_events, &r.adj_events}) {
+// Group workspace: descriptor pointer array, then (MFMA path) packed operands and partials.
+size_t plan_group(Group &G, const Operator &op, const Layout &Ly) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    off = (off + 255) / 256 * 256;
+    const size_t o = off;
+    off += std::max<size_t>(b, 4);
+    return o;
+  };
+  const int B = (int)G.members.size();
+  take((size_t)B * sizeof(void *));
+  G.use_gemm = (G.precision != PLSQR_PREC_FP32) && op.op.kind == PLSQR_OP_DENSE;
+  if (G.use_gemm) {
+    GemmArgs &g = G.gemm;
+    g.Bpad = B <= 32 ? 32 : 64;
+    const long long m = Ly.m, n = Ly.n;
+    const long long rowtiles = m / 128;
+    long long ks = std::max(1LL, std::min(n / 128, (1024 + rowtiles - 1) / rowtiles));
+    long long kchunk = ((n + ks - 1) / ks + 127) / 128 * 128;
+    ks = (n + kchunk - 1) / kchunk;
+    g.ks = (int)ks;
+    g.kchunk = kchunk;
+    g.use_A_lo = (G.precision == PLSQR_PREC_BF16_REFINED) ? 1 : 0;
+    // offsets now, pointers after allocation
+    g.X_hi = reinterpret_cast<void *>(take((size_t)g.Bpad * n * 2));
+    g.X_lo = reinterpret_cast<void *>(take((size_t)g.Bpad * n * 2));
+    g.U_hi = reinterpret_cast<void *>(take((size_t)g.Bpad * m * 2));
+    g.U_lo = reinterpret_cast<void *>(take((size_t)g.Bpad * m * 2));
+    g.Ypart = reinterpret_cast<float *>(take((size_t)g.ks * m * g.Bpad * 4));
+  }
+  return (off + 255) / 256 * 256;
+}
+
+// Build (once) the BF16 copies of a dense operator: A_hi, A_lo and their transposes.
+int ensure_bf16(plsqr_engine *eng, Operator &op, bool need_lo) {
+  const long long m = op.op.n_y, n = (long long)op.op.nx * op.op.ny * op.op.nz;
+  const size_t bytes = (size_t)m * n * 2;
+  auto alloc = [&](void **p) -> int {
+    if (*p) return PLSQR_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return set_error(PLSQR_E_NOMEM, "allocation of the BF16 operator copies failed");
+    }
+    return PLSQR_OK;
+  };
+  const bool have_hi = op.A_hi != nullptr, have_lo = op.A_lo != nullptr;
+  if (!have_hi && op.op.A_hi_dev) op.A_hi = const_cast<uint16_t *>(op.op.A_hi_dev);
+  if (!have_lo && op.op.A_lo_dev) op.A_lo = const_cast<uint16_t *>(op.op.A_lo_dev);
+  int rc;
+  if (!op.A_hi) {
+    if ((rc = alloc(&op.A_hi)) != PLSQR_OK) return rc;
+    op.own_A_hi = true;
+    if (!op.A_lo && (rc = alloc(&op.A_lo)) != PLSQR_OK) return rc;
+    op.own_A_lo = true;
+    launch_split_matrix(eng->stream, op.op.A_dev, op.A_hi, op.A_lo, m * n);
+  }
+  if (need_lo && !op.A_lo) {
+    if ((rc = alloc(&op.A_lo)) != PLSQR_OK) return rc;
+    op.own_A_lo = true;
+    // recompute the pair so that lo matches hi exactly
+    void *tmp = nullptr;
+    if ((rc = alloc(&tmp)) != PLSQR_OK) return rc;
+    launch_split_matrix(eng->stream, op.op.A_dev, tmp, op.A_lo, m * n);
+    HIP_TRY(hipStreamSynchronize(eng->stream));
+    HIP_TRY(hipFree(tmp));
+  }
+  if (!op.At_hi) {
+    if ((rc = alloc(&op.At_hi)) != PLSQR_OK) return rc;
+    launch_transpose16(eng->stream, op.A_hi, op.At_hi, m, n);
+  }
+  if (need_lo && !op.At_lo) {
+    if ((rc = alloc(&op.At_lo)) != PLSQR_OK) return rc;
+    launch_transpose16(eng->stream, op.A_lo, op.At_lo, m, n);
+  }
+  HIP_TRY(hipGetLastError());
+  return PLSQR_OK;
+}
+
+void release_group(plsqr_engine *eng, Group &G) {
+  if (G.ev_start) hipEventDestroy(G.ev_start);
+  if (G.ev_end) hipEventDestroy(G.ev_end);
+  G.ev_start = G.ev_end = nullptr;
+  for (auto *lst : {&G.fwd_events, &G.adj_events}) {
     for (auto &e : *lst) {
       hipEventDestroy(e.first);
       hipEventDestroy(e.second);
     }
     lst->clear();
   }
-  if (r.ws) {
-    eng->pool.put(r.ws, r.lay.total);
-    eng->used -= r.lay.total;
+  for (uint64_t t : G.members) {
+    auto it = eng->reqs.find(t);
+    if (it == eng->reqs.end()) continue;
+    Request &r = *it->second;
+    if (r.ws) eng->pool.put(r.ws, r.lay.total);
     r.ws = nullptr;
+    if (r.pinned) hipHostFree(r.pinned);
+    r.pinned = nullptr;
   }
-  if (r.pinned) hipHostFree(r.pinned);
-  r.pinned = nullptr;
+  if (G.gws) eng->pool.put(G.gws, G.gws_bytes);
+  G.gws = nullptr;
+  if (G.pinned) hipHostFree(G.pinned);
+  G.pinned = nullptr;
+  if (G.state == Group::RUNNING) eng->used -= G.bytes;
 }
 
-// Allocate and enqueue a request (state QUEUED -> RUNNING). Caller holds the lock.
-// Nothing here waits for earlier work on the stream: the descriptor goes up and the
-// results come down through pinned host memory with stream-ordered copies.
-int start_request_impl(plsqr_engine *eng, Request &r) {
-  const Operator &op = eng->ops[r.op_id];
-  r.ws = static_cast<char *>(eng->pool.get(r.lay.total));
-  if (!r.ws) return set_error(PLSQR_E_NOMEM, "device allocation of the request workspace failed");
-  eng->used += r.lay.total;
-  r.pinned_bytes = pin_dg_off() + (size_t)(r.pb.outer + 1) * DG_COUNT * sizeof(double);
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r.pinned), r.pinned_bytes, hipHostMallocDefault));
-  fill_desc(eng, r, op);
-  r.d_descs = reinterpret_cast<InstDesc **>(r.ws + r.lay.descptr);
-  InstDesc *d_desc = reinterpret_cast<InstDesc *>(r.ws + r.lay.desc);
-  std::memcpy(r.pinned, &r.host, sizeof(InstDesc));
-  std::memcpy(r.pinned + pin_desc_ptr_off(), &d_desc, sizeof(void *));
-  HIP_TRY(hipEventCreate(&r.ev_start));
-  HIP_TRY(hipEventCreate(&r.ev_end));
-  HIP_TRY(hipEventRecord(r.ev_start, eng->stream));
-  HIP_TRY(hipMemcpyAsync(d_desc, r.pinned, sizeof(InstDesc), hipMemcpyHostToDevice, eng->stream));
-  HIP_TRY(hipMemcpyAsync(r.d_descs, r.pinned + pin_desc_ptr_off(), sizeof(void *),
-                         hipMemcpyHostToDevice, eng->stream));
-  const bool timed = (r.pb.flags & PLSQR_FLAG_TIME_PRODUCTS) != 0;
-  BatchView bv{r.d_descs, 1, &r.host, &r.lay, timed ? &r.prod_events : nullptr,
-               timed ? &r.adj_events : nullptr};
-  enqueue_whole_solve(eng->stream, bv, r.pb.outer, r.pb.inner);
+// Allocate and enqueue a group (QUEUED -> RUNNING). Caller holds the lock. Nothing waits
+// for earlier work on the stream: descriptors go up and results come down through
+// pinned host memory with stream-ordered copies.
+int start_group_impl(plsqr_engine *eng, Group &G) {
+  Operator &op = eng->ops[G.op_id];
+  const int B = (int)G.members.size();
+  Request &r0 = *eng->reqs[G.members[0]];
+  if (G.use_gemm) {
+    const int rc = ensure_bf16(eng, op, G.gemm.use_A_lo != 0);
+    if (rc != PLSQR_OK) return rc;
+  }
+  G.state = Group::RUNNING;        // from here on release_group returns the budget
+  eng->used += G.bytes;
+  G.gws = static_cast<char *>(eng->pool.get(G.gws_bytes));
+  if (!G.gws) return set_error(PLSQR_E_NOMEM, "device allocation of the batch workspace failed");
+  G.d_descs = reinterpret_cast<InstDesc **>(G.gws);
+  if (G.use_gemm) {
+    GemmArgs &g = G.gemm;
+    auto fix = [&](void *&p) { p = G.gws + reinterpret_cast<size_t>(p); };
+    fix(g.X_hi);
+    fix(g.X_lo);
+    fix(g.U_hi);
+    fix(g.U_lo);
+    g.Ypart = reinterpret_cast<float *>(G.gws + reinterpret_cast<size_t>(g.Ypart));
+    g.A_hi = op.A_hi;
+    g.A_lo = op.A_lo;
+    g.At_hi = op.At_hi;
+    g.At_lo = op.At_lo;
+  }
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&G.pinned), (size_t)B * sizeof(void *),
+                        hipHostMallocDefault));
+  for (int b = 0; b < B; ++b) {
+    Request &r = *eng->reqs[G.members[b]];
+    r.ws = static_cast<char *>(eng->pool.get(r.lay.total));
+    if (!r.ws) return set_error(PLSQR_E_NOMEM, "device allocation of a request workspace failed");
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r.pinned), pin_bytes(r.pb), hipHostMallocDefault));
+    fill_desc(eng, r, op);
+    r.d_desc = reinterpret_cast<InstDesc *>(r.ws + r.lay.desc);
+    std::memcpy(r.pinned, &r.host, sizeof(InstDesc));
+    reinterpret_cast<InstDesc **>(G.pinned)[b] = r.d_desc;
+  }
+  HIP_TRY(hipEventCreate(&G.ev_start));
+  HIP_TRY(hipEventCreate(&G.ev_end));
+  HIP_TRY(hipEventRecord(G.ev_start, eng->stream));
+  for (int b = 0; b < B; ++b) {
+    Request &r = *eng->reqs[G.members[b]];
+    HIP_TRY(hipMemcpyAsync(r.d_desc, r.pinned, sizeof(InstDesc), hipMemcpyHostToDevice, eng->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(G.d_descs, G.pinned, (size_t)B * sizeof(void *), hipMemcpyHostToDevice,
+                         eng->stream));
+  BatchView bv{G.d_descs, B, &r0.host, &r0.lay, G.timed ? &G.fwd_events : nullptr,
+               G.timed ? &G.adj_events : nullptr, G.use_gemm ? &G.gemm : nullptr};
+  enqueue_whole_solve(eng->stream, bv, r0.pb.outer, r0.pb.inner);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(r.pinned + pin_sc_off(), r.ws + r.lay.sc, SC_COUNT * sizeof(double),
-                         hipMemcpyDeviceToHost, eng->stream));
-  HIP_TRY(hipMemcpyAsync(r.pinned + pin_dg_off(), r.ws + r.lay.diag,
-                         (size_t)(r.pb.outer + 1) * DG_COUNT * sizeof(double),
-                         hipMemcpyDeviceToHost, eng->stream));
-  HIP_TRY(hipEventRecord(r.ev_end, eng->stream));
-  r.state = Request::RUNNING;
+  for (int b = 0; b < B; ++b) {
+    Request &r = *eng->reqs[G.members[b]];
+    HIP_TRY(hipMemcpyAsync(r.pinned + pin_sc_off(), r.ws + r.lay.sc, SC_COUNT * sizeof(double),
+                           hipMemcpyDeviceToHost, eng->stream));
+    HIP_TRY(hipMemcpyAsync(r.pinned + pin_dg_off(), r.ws + r.lay.diag,
+                           (size_t)(r.pb.outer + 1) * DG_COUNT * sizeof(double),
+                           hipMemcpyDeviceToHost, eng->stream));
+  }
+  HIP_TRY(hipEventRecord(G.ev_end, eng->stream));
   return PLSQR_OK;
 }
 
-int start_request(plsqr_engine *eng, Request &r) {
-  const int rc = start_request_impl(eng, r);
+void fail_group(plsqr_engine *eng, Group &G, int rc) {
+  for (uint64_t t : G.members) {
+    auto it = eng->reqs.find(t);
+    if (it == eng->reqs.end()) continue;
+    Request &r = *it->second;
+    std::memset(&r.result, 0, sizeof(r.result));
+    r.result.status = rc;
+    r.status = rc;
+    r.done = true;
+  }
+  G.state = Group::DONE;
+}
+
+int start_group(plsqr_engine *eng, Group &G) {
+  const int rc = start_group_impl(eng, G);
   if (rc != PLSQR_OK) {
     hipStreamSynchronize(eng->stream);
-    release(eng, r);
+    release_group(eng, G);
+    fail_group(eng, G, rc);
   }
   return rc;
 }
 
-// Collect a finished request: read diagnostics, release its memory.
-void reap(plsqr_engine *eng, Request &r) {
-  plsqr_result &res = r.result;
-  std::memset(&res, 0, sizeof(res));
-  const double *sc = reinterpret_cast<const double *>(r.pinned + pin_sc_off());
-  const double *dg = reinterpret_cast<const double *>(r.pinned + pin_dg_off());
-  res.status = (int)sc[SC_STATUS];
-  res.outer_done = r.pb.outer;
-  res.levels = r.lay.levels;
-  for (int k = 1; k <= r.pb.outer; ++k) {
-    res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
-    res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
-    res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
+double total_ms(const EventList &lst) {
+  double s = 0.0;
+  for (auto &e : lst) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) s += t;
   }
-  float ms = 0.f;
-  if (r.ev_start && r.ev_end && hipEventElapsedTime(&ms, r.ev_start, r.ev_end) == hipSuccess)
-    res.device_ms = ms;
-  auto total = [](const std::vector<std::pair<hipEvent_t, hipEvent_t>> &lst) {
-    double s = 0.0;
-    for (auto &e : lst) {
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) s += t;
-    }
-    return s;
-  };
-  res.forward_ms = total(r.prod_events);
-  res.forward_launches = (int64_t)r.prod_events.size();
-  res.adjoint_ms = total(r.adj_events);
-  res.adjoint_launches = (int64_t)r.adj_events.size();
-  res.workspace_bytes = (int64_t)r.lay.total;
-  r.t_done = now_ms();
-  res.submit_to_done_ms = r.t_done - r.t_submit;
-  release(eng, r);
-  r.status = res.status;
-  r.state = Request::DONE;
+  return s;
 }
 
-// Reap every finished running request, then start queued ones that now fit.
+// Collect a finished group: read every member's diagnostics, release memory.
+void reap(plsqr_engine *eng, Group &G) {
+  float ms = 0.f;
+  if (G.ev_start && G.ev_end) hipEventElapsedTime(&ms, G.ev_start, G.ev_end);
+  const double fwd = total_ms(G.fwd_events), adj = total_ms(G.adj_events);
+  const double now = now_ms();
+  for (uint64_t t : G.members) {
+    Request &r = *eng->reqs[t];
+    plsqr_result &res = r.result;
+    std::memset(&res, 0, sizeof(res));
+    const double *sc = reinterpret_cast<const double *>(r.pinned + pin_sc_off());
+    const double *dg = reinterpret_cast<const double *>(r.pinned + pin_dg_off());
+    res.status = (int)sc[SC_STATUS];
+    res.outer_done = r.pb.outer;
+    res.levels = r.lay.levels;
+    for (int k = 1; k <= r.pb.outer; ++k) {
+      res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
+      res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
+      res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
+    }
+    res.device_ms = ms;
+    res.forward_ms = fwd;
+    res.forward_launches = (int64_t)G.fwd_events.size();
+    res.adjoint_ms = adj;
+    res.adjoint_launches = (int64_t)G.adj_events.size();
+    res.workspace_bytes = (int64_t)r.lay.total;
+    r.t_done = now;
+    res.submit_to_done_ms = r.t_done - r.t_submit;
+    r.status = res.status;
+    r.done = true;
+  }
+  release_group(eng, G);
+  G.state = Group::DONE;
+}
+
+// Reap every finished running group, then start queued ones that now fit (FIFO).
 void progress(plsqr_engine *eng) {
-  for (auto &kv : eng->reqs) {
-    Request &r = *kv.second;
-    if (r.state == Request::RUNNING && hipEventQuery(r.ev_end) == hipSuccess) reap(eng, r);
+  for (auto it = eng->groups.begin(); it != eng->groups.end();) {
+    Group &G = *it->second;
+    if (G.state == Group::RUNNING && hipEventQuery(G.ev_end) == hipSuccess) reap(eng, G);
+    if (G.state == Group::DONE) it = eng->groups.erase(it);
+    else ++it;
   }
   while (!eng->queued.empty()) {
-    auto it = eng->reqs.find(eng->queued.front());
-    if (it == eng->reqs.end()) {
+    auto it = eng->groups.find(eng->queued.front());
+    if (it == eng->groups.end()) {
       eng->queued.pop_front();
       continue;
     }
-    Request &r = *it->second;
-    if (eng->budget && eng->used + r.lay.total > eng->budget) break;
+    Group &G = *it->second;
+    if (eng->budget && eng->used + G.bytes > eng->budget) break;
     eng->queued.pop_front();
-    const int rc = start_request(eng, r);
-    if (rc != PLSQR_OK) {
-      r.status = rc;
-      r.state = Request::DONE;
-      std::memset(&r.result, 0, sizeof(r.result));
-      r.result.status = rc;
-    }
+    start_group(eng, G);
   }
+}
+
+// Validate and register a group of requests; returns PLSQR_OK and the tickets.
+int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_problem *probs,
+                 const float *const *g_devs, float *const *f_devs, uint64_t *tickets) {
+  const Operator *op = (op_id >= 0 && op_id < (int)eng->ops.size()) ? &eng->ops[op_id] : nullptr;
+  std::vector<Layout> lays(count);
+  for (int b = 0; b < count; ++b) {
+    if (!g_devs[b] || !f_devs[b]) return set_error(PLSQR_E_INVALID, "g_dev and f_dev must be device pointers");
+    int levels = 0;
+    std::string why;
+    const int rc = validate(probs[b], op, &levels, &why);
+    if (rc != PLSQR_OK) return set_error(rc, why);
+    lays[b] = make_layout(probs[b], op->op.n_y, levels, op->op.kind);
+    const plsqr_problem &a = probs[0], &c = probs[b];
+    if (c.outer != a.outer || c.inner != a.inner || lays[b].levels != lays[0].levels ||
+        c.smoother != a.smoother || c.nu_pre != a.nu_pre || c.cheb_degree != a.cheb_degree ||
+        c.precision != a.precision || c.flags != a.flags)
+      return set_error(PLSQR_E_INVALID,
+                       "a batch must share counts, levels, smoother schedule, precision and flags");
+  }
+  const int prec = probs[0].precision;
+  if (prec != PLSQR_PREC_FP32) {
+    if (op->op.kind != PLSQR_OP_DENSE)
+      return set_error(PLSQR_E_INVALID, "BF16 products need a dense operator");
+    if (count > 64) return set_error(PLSQR_E_INVALID, "a BF16 batch holds at most 64 instances");
+    if (lays[0].n % 128 || lays[0].m % 128)
+      return set_error(PLSQR_E_INVALID, "BF16 products need n_X and n_Y divisible by 128");
+  }
+  auto G = std::make_unique<Group>();
+  G->id = eng->next_group++;
+  G->op_id = op_id;
+  G->precision = prec;
+  G->timed = (probs[0].flags & PLSQR_FLAG_TIME_PRODUCTS) != 0;
+  const double t = now_ms();
+  for (int b = 0; b < count; ++b) {
+    auto r = std::make_unique<Request>();
+    r->ticket = eng->next_ticket++;
+    r->group = G->id;
+    r->pb = probs[b];
+    r->g = g_devs[b];
+    r->f_out = f_devs[b];
+    r->lay = lays[b];
+    r->t_submit = t;
+    G->members.push_back(r->ticket);
+    G->bytes += r->lay.total;
+    tickets[b] = r->ticket;
+    eng->reqs.emplace(r->ticket, std::move(r));
+  }
+  G->gws_bytes = plan_group(*G, *op, lays[0]);
+  G->bytes += G->gws_bytes;
+  if (eng->budget && G->bytes > eng->budget) {
+    for (uint64_t tk : G->members) eng->reqs.erase(tk);
+    return set_error(PLSQR_E_BUDGET, "request workspace exceeds the engine's HBM budget");
+  }
+  eng->queued.push_back(G->id);
+  eng->groups.emplace(G->id, std::move(G));
+  progress(eng);
+  return PLSQR_OK;
 }
 
 }  // namespace
@@ -346,34 +539,20 @@ int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_
 int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, const float *g_dev,
                 float *f_dev, uint64_t *ticket) {
   if (!eng || !prob || !ticket) return set_error(PLSQR_E_INVALID, "null argument");
-  if (!g_dev || !f_dev) return set_error(PLSQR_E_INVALID, "g_dev and f_dev must be device pointers");
-  std::lock_guard<std::mutex> lk(eng->mu);
-  DeviceGuard dg(eng->device);
-  const Operator *op = (op_id >= 0 && op_id < (int)eng->ops.size()) ? &eng->ops[op_id] : nullptr;
-  int levels = 0;
-  std::string why;
-  int rc = validate(*prob, op, &levels, &why);
-  if (rc != PLSQR_OK) return set_error(rc, why);
   if (prob->precision != PLSQR_PREC_FP32)
     return set_error(PLSQR_E_INVALID, "single requests run in PLSQR_PREC_FP32");
-  auto r = std::make_unique<Request>();
-  r->ticket = eng->next_ticket++;
-  r->op_id = op_id;
-  r->pb = *prob;
-  r->g = g_dev;
-  r->f_out = f_dev;
-  r->lay = make_layout(*prob, op->op.n_y, levels, op->op.kind);
-  if (eng->budget && r->lay.total > eng->budget)
-    return set_error(PLSQR_E_BUDGET, "request workspace exceeds the engine's HBM budget");
-  r->t_submit = now_ms();
-  const uint64_t t = r->ticket;
-  eng->reqs.emplace(t, std::move(r));
-  // FIFO admission: the request starts now if it and everything queued before it fit
-  // the budget; otherwise it waits for earlier requests to complete.
-  eng->queued.push_back(t);
-  progress(eng);
-  *ticket = t;
-  return PLSQR_OK;
+  std::lock_guard<std::mutex> lk(eng->mu);
+  DeviceGuard dg(eng->device);
+  return submit_group(eng, op_id, 1, prob, &g_dev, &f_dev, ticket);
+}
+
+int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const plsqr_problem *probs,
+                      const float *const *g_devs, float *const *f_devs, uint64_t *tickets) {
+  if (!eng || !probs || !g_devs || !f_devs || !tickets) return set_error(PLSQR_E_INVALID, "null argument");
+  if (count < 1) return set_error(PLSQR_E_INVALID, "count must be >= 1");
+  std::lock_guard<std::mutex> lk(eng->mu);
+  DeviceGuard dg(eng->device);
+  return submit_group(eng, op_id, count, probs, g_devs, f_devs, tickets);
 }
 
 int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {
@@ -384,7 +563,7 @@ int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {
   if (it == eng->reqs.end()) return set_error(PLSQR_E_UNKNOWN_TICKET, "unknown or retired ticket");
   progress(eng);
   Request &r = *it->second;
-  if (r.state != Request::DONE) return PLSQR_PENDING;
+  if (!r.done) return PLSQR_PENDING;
   if (out) *out = r.result;
   const int st = r.status;
   eng->reqs.erase(it);
@@ -404,9 +583,7 @@ int plsqr_wait_all(plsqr_engine *eng) {
   for (;;) {
     HIP_TRY(hipStreamSynchronize(eng->stream));
     progress(eng);
-    bool running = false;
-    for (auto &kv : eng->reqs) running = running || kv.second->state == Request::RUNNING;
-    if (eng->queued.empty() && !running) break;
+    if (eng->queued.empty() && eng->groups.empty()) break;
   }
   return PLSQR_OK;
 }
@@ -418,11 +595,19 @@ int plsqr_destroy(plsqr_engine *eng) {
     DeviceGuard dg(eng->device);
     hipStreamSynchronize(eng->stream);
     eng->queued.clear();
-    for (auto &kv : eng->reqs) {
-      Request &r = *kv.second;
-      if (r.state == Request::RUNNING) reap(eng, r);
+    for (auto &kv : eng->groups) {
+      Group &G = *kv.second;
+      if (G.state == Group::RUNNING) reap(eng, G);
     }
+    eng->groups.clear();
     eng->reqs.clear();
+    for (auto &op : eng->ops) {
+      if (op.own_A_hi && op.A_hi) hipFree(op.A_hi);
+      if (op.own_A_lo && op.A_lo) hipFree(op.A_lo);
+      if (op.At_hi) hipFree(op.At_hi);
+      if (op.At_lo) hipFree(op.At_lo);
+    }
+    eng->ops.clear();
     eng->pool.trim();
   }
   delete eng;

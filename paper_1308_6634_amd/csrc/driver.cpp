@@ -44,7 +44,8 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   } else {
     return bad("unknown smoother");
   }
-  if (pb.precision != PLSQR_PREC_FP32 && pb.precision != PLSQR_PREC_BF16_REFINED)
+  if (pb.precision != PLSQR_PREC_FP32 && pb.precision != PLSQR_PREC_BF16_REFINED &&
+      pb.precision != PLSQR_PREC_BF16)
     return bad("unknown precision");
   int levels = pb.mg_levels;
   if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
@@ -140,7 +141,6 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
 // ---------------------------------------------------------------------------------
 // products
 // ---------------------------------------------------------------------------------
-using EventList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
 static void time_begin(hipStream_t st, EventList *ev, hipEvent_t *a) {
   if (!ev) return;
   hipEventCreate(a);
@@ -180,6 +180,8 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   int np;
   if (H.op_kind == PLSQR_OP_BLUR)
     np = blur_chain(st, bv, src, 0, epi);
+  else if (bv.gemm)
+    np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, epi);
   else
     np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi);
   time_end(st, ev, a);
@@ -194,6 +196,8 @@ static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
   time_begin(st, ev, &a);
   if (H.op_kind == PLSQR_OP_BLUR) {
     blur_chain(st, bv, V_U, 1, epi);
+  } else if (bv.gemm) {
+    launch_gemm_adjoint(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, epi);
   } else {
     launch_gemv_cols(st, bv.d_descs, bv.B, H.n, H.colchunks);
     launch_colsum(st, bv.d_descs, bv.B, H.n, epi);

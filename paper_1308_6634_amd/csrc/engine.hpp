@@ -20,6 +20,9 @@ namespace plsqr {
 struct Operator {
   plsqr_operator op{};
   std::vector<float> taps;
+  // BF16 copies for batched MFMA products (built on first use; owned unless borrowed)
+  void *A_hi = nullptr, *A_lo = nullptr, *At_hi = nullptr, *At_lo = nullptr;
+  bool own_A_hi = false, own_A_lo = false;
 };
 
 // Byte offsets of every buffer inside one request's workspace.
@@ -50,27 +53,43 @@ class Pool {
   std::multimap<size_t, void *> free_;
 };
 
+using EventList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
+
+// One reconstruction.
 struct Request {
   uint64_t ticket = 0;
-  int op_id = 0;
+  uint64_t group = 0;
   plsqr_problem pb{};
   const float *g = nullptr;
   float *f_out = nullptr;
   Layout lay;
   char *ws = nullptr;                // device workspace
   InstDesc host{};                   // host copy of the descriptor
-  InstDesc **d_descs = nullptr;      // device: 1-element pointer array (in ws)
-  enum State { QUEUED, RUNNING, DONE } state = QUEUED;
+  InstDesc *d_desc = nullptr;        // device copy (in ws)
+  char *pinned = nullptr;            // pinned staging: descriptor up, scalars/records down
+  bool done = false;
   int status = PLSQR_OK;
-  hipEvent_t ev_start = nullptr, ev_end = nullptr;
-  char *pinned = nullptr;            // pinned host staging: descriptor up, scalars/records down
-  size_t pinned_bytes = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prod_events;   // forward products
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> adj_events;    // adjoint products
   double t_submit = 0.0, t_done = 0.0;
   plsqr_result result{};
-  // serving mode: progress through the fixed schedule
-  int outer_k = 0, inner_i = 0, phase = 0;
+};
+
+// Instances launched together in lockstep (a plain solve is a group of one).
+struct Group {
+  uint64_t id = 0;
+  int op_id = 0;
+  std::vector<uint64_t> members;
+  int precision = PLSQR_PREC_FP32;
+  enum State { QUEUED, RUNNING, DONE } state = QUEUED;
+  size_t bytes = 0;                  // members' workspaces + group workspace
+  char *gws = nullptr;               // group workspace: descriptor pointer array, MFMA buffers
+  size_t gws_bytes = 0;
+  InstDesc **d_descs = nullptr;
+  char *pinned = nullptr;            // staging of the pointer array
+  GemmArgs gemm{};
+  bool use_gemm = false;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  EventList fwd_events, adj_events;
+  bool timed = false;
 };
 
 // A view of B same-shaped instances launched together.
@@ -79,8 +98,9 @@ struct BatchView {
   int B;
   const InstDesc *h;          // host copy of one member (shapes and schedule)
   const Layout *lay;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> *prod_events;  // optional timing (forward)
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> *adj_events;   // optional timing (adjoint)
+  EventList *prod_events;     // optional timing (forward products)
+  EventList *adj_events;      // optional timing (adjoint products)
+  const GemmArgs *gemm;       // batched MFMA products, or null
 };
 
 // Solve driver (same sequence for one instance or a lockstep batch).
@@ -105,8 +125,10 @@ struct plsqr_engine {
   std::mutex mu;
   std::vector<plsqr::Operator> ops;
   std::map<uint64_t, std::unique_ptr<plsqr::Request>> reqs;
-  std::deque<uint64_t> queued;
+  std::map<uint64_t, std::unique_ptr<plsqr::Group>> groups;
+  std::deque<uint64_t> queued;       // group ids in FIFO order
   uint64_t next_ticket = 1;
+  uint64_t next_group = 1;
   plsqr::Pool pool;
   // serving mode
   std::thread worker;

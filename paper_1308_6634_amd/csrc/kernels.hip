@@ -9,127 +9,10 @@
 
 #include <cmath>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace plsqr {
-
-// ------------------------------------------------------------------------------------
-// helpers
-// ------------------------------------------------------------------------------------
-__device__ __forceinline__ const InstDesc &inst(InstDesc *const *descs) {
-  return *descs[blockIdx.y];
-}
-
-__device__ __forceinline__ float *vec_of(const InstDesc &D, int sel) {
-  switch (sel) {
-    case V_F: return D.f;
-    case V_U: return D.u;
-    case V_P: return D.p;
-    case V_V: return D.v;
-    case V_W: return D.w;
-    case V_TMP1: return D.tmp1;
-    case V_TMP2: return D.tmp2;
-    default: return const_cast<float *>(D.g);
-  }
-}
-
-__device__ __forceinline__ float *lvbuf(const LevelDesc &L, int sel) {
-  switch (sel) {
-    case LB_X: return L.x;
-    case LB_B: return L.b;
-    case LB_R: return L.r;
-    case LB_T: return L.t;
-    default: return L.s;
-  }
-}
-
-// Sum of v over the block (valid in thread 0). blockDim.x must be kBlock.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double red[kBlock / 64];
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / 64; ++i) r += red[i];
-  return r;
-}
-
-__device__ __forceinline__ float block_sum_f(float v) {
-  __shared__ float redf[kBlock / 64];
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) redf[wid] = v;
-  __syncthreads();
-  float r = 0.f;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / 64; ++i) r += redf[i];
-  return r;
-}
-
-// kappa(t) = r'(t)/t in closed form (eq. (1.12)-(1.13) with r from (1.3)-(1.5)).
-__device__ __forceinline__ float kappa_of(int reg, float t, float T) {
-  switch (reg) {
-    case PLSQR_REG_STV: return 1.0f / sqrtf(T * T + t * t);
-    case PLSQR_REG_PM_LOG: return 1.0f / (1.0f + (t * t) / (T * T));
-    case PLSQR_REG_PM_EXP: return expf(-(t * t) / (T * T));
-    default: return 1.0f;
-  }
-}
-
-// r(t), eq. (1.3)-(1.5), in FP64.
-__device__ __forceinline__ double penalty_of(int reg, double t, double T) {
-  switch (reg) {
-    case PLSQR_REG_STV: return T * sqrt(1.0 + (t / T) * (t / T));
-    case PLSQR_REG_PM_LOG: return 0.5 * T * T * log1p((t / T) * (t / T));
-    case PLSQR_REG_PM_EXP: return 0.5 * T * T * (1.0 - exp(-(t * t) / (T * T)));
-    default: return 0.5 * t * t;
-  }
-}
-
-struct Coord { int x, y, z; };
-__device__ __forceinline__ Coord coord_of(long long j, int nx, int ny) {
-  Coord c;
-  c.x = (int)(j % nx);
-  long long q = j / nx;
-  c.y = (int)(q % ny);
-  c.z = (int)(q / ny);
-  return c;
-}
-
-// (A_l x)_j on level l: eps_l x_j + sum over the faces of cell j of w (x_j - x_nb).
-// Level 0 face weight to the +a neighbour is kappa_j; coarser levels store them.
-__device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *__restrict__ x,
-                                         long long j, Coord c) {
-  const LevelDesc &L = D.lv[l];
-  const int nx = L.nx, ny = L.ny, nz = L.nz;
-  const long long sx = 1, sy = nx, sz = (long long)nx * ny;
-  const float xj = x[j];
-  float acc = (float)L.eps * xj;
-  if (l == 0) {
-    const float *__restrict__ k = D.kappa;
-    const float kj = k[j];
-    if (c.x + 1 < nx) acc += kj * (xj - x[j + sx]);
-    if (c.x > 0) acc += k[j - sx] * (xj - x[j - sx]);
-    if (c.y + 1 < ny) acc += kj * (xj - x[j + sy]);
-    if (c.y > 0) acc += k[j - sy] * (xj - x[j - sy]);
-    if (c.z + 1 < nz) acc += kj * (xj - x[j + sz]);
-    if (c.z > 0) acc += k[j - sz] * (xj - x[j - sz]);
-  } else {
-    if (c.x + 1 < nx) acc += L.wx[j] * (xj - x[j + sx]);
-    if (c.x > 0) acc += L.wx[j - sx] * (xj - x[j - sx]);
-    if (c.y + 1 < ny) acc += L.wy[j] * (xj - x[j + sy]);
-    if (c.y > 0) acc += L.wy[j - sy] * (xj - x[j - sy]);
-    if (nz > 1) {
-      if (c.z + 1 < nz) acc += L.wz[j] * (xj - x[j + sz]);
-      if (c.z > 0) acc += L.wz[j - sz] * (xj - x[j - sz]);
-    }
-  }
-  return acc;
-}
 
 // ------------------------------------------------------------------------------------
 // a1: |grad f|, kappa and R(f)
@@ -442,32 +325,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int 
 // ------------------------------------------------------------------------------------
 // a4/a5/a10: forward and adjoint products
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void epilogue(const InstDesc &D, int epi, long long j, float y,
-                                         float *out, double &dot) {
-  const double *sc = D.sc;
-  switch (epi) {
-    case EPI_FWD: {
-      const float c1 = (float)sc[SC_SV], c2 = (float)(sc[SC_ALPHA] * sc[SC_SU]);
-      const float un = c1 * y - c2 * D.u[j];
-      D.u[j] = un;
-      dot = (double)un * (double)un;
-      break;
-    }
-    case EPI_ADJ: {
-      const float c1 = (float)sc[SC_SU], c2 = (float)(sc[SC_BETA] * sc[SC_SV]);
-      D.p[j] = c1 * y - c2 * D.p[j];
-      break;
-    }
-    case EPI_ADJ_INIT: D.p[j] = (float)sc[SC_SU] * y; break;
-    case EPI_RESID: {
-      const double e = (double)D.g[j] - (double)y;
-      dot = e * e;
-      break;
-    }
-    default: out[j] = y; break;
-  }
-}
-
 // One 1D correlation pass of the separable blur along `axis`, zero outside the grid.
 // adj selects the reversed taps (the adjoint). The last pass applies the epilogue.
 __global__ void __launch_bounds__(kBlock) k_blur_pass(InstDesc *const *descs, int axis,

@@ -38,6 +38,13 @@ void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int 
 void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n);
 void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n);
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n);
+// batched dense products on MFMA (gemm_bf16.hip)
+int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
+                        long long n, int src_sel, int epi);
+void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
+                         long long n, int epi);
+void launch_split_matrix(hipStream_t st, const float *A, void *hi, void *lo, long long count);
+void launch_transpose16(hipStream_t st, const void *in, void *out, long long R, long long C);
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
 
 }  // namespace plsqr

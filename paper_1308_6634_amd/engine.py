@@ -65,6 +65,17 @@ class Engine:
         self._keep[("req", t)] = (g, f)
         return t
 
+    def submit_batch(self, op_id, probs, gs, fs):
+        """Lockstep batch; returns one ticket per instance."""
+        for g, f in zip(gs, fs):
+            assert g.dtype == torch.float32 and f.dtype == torch.float32
+            assert g.is_cuda and f.is_cuda and g.is_contiguous() and f.is_contiguous()
+        ts = P.plsqr_solve_batch(self.handle, op_id, probs, [g.data_ptr() for g in gs],
+                                 [f.data_ptr() for f in fs])
+        for t, g, f in zip(ts, gs, fs):
+            self._keep[("req", t)] = (g, f)
+        return ts
+
     def poll(self, ticket):
         st, res = P.plsqr_poll(self.handle, ticket)
         if st != P.PLSQR_PENDING:

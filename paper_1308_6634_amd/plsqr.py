@@ -32,7 +32,7 @@ PLSQR_OP_BLUR = 1
 PLSQR_OP_DENSE = 2
 PLSQR_REG_TIKHONOV, PLSQR_REG_STV, PLSQR_REG_PM_LOG, PLSQR_REG_PM_EXP = 0, 1, 2, 3
 PLSQR_SMOOTH_JACOBI, PLSQR_SMOOTH_CHEBYSHEV = 0, 1
-PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED = 0, 1
+PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED, PLSQR_PREC_BF16 = 0, 1, 2
 PLSQR_ENGINE_SERVE = 1
 PLSQR_FLAG_TIME_PRODUCTS = 1
 PLSQR_MAX_LEVELS = 12
@@ -44,7 +44,8 @@ REG_CODES = {"tikhonov": PLSQR_REG_TIKHONOV, "stv": PLSQR_REG_STV, "pm_log": PLS
              "pm_exp": PLSQR_REG_PM_EXP}
 SMOOTHER_CODES = {"jacobi": PLSQR_SMOOTH_JACOBI, "chebyshev": PLSQR_SMOOTH_CHEBYSHEV}
 
-EXPORTED = ("plsqr_create", "plsqr_set_operator", "plsqr_solve", "plsqr_poll", "plsqr_wait_all",
+EXPORTED = ("plsqr_create", "plsqr_set_operator", "plsqr_solve", "plsqr_solve_batch", "plsqr_poll",
+            "plsqr_wait_all",
             "plsqr_destroy", "plsqr_last_error", "plsqr_auto_levels", "plsqr_workspace_bytes")
 
 
@@ -96,6 +97,9 @@ def _load():
     lib.plsqr_set_operator.argtypes = [ctypes.c_void_p, P(plsqr_operator), P(ctypes.c_int32)]
     lib.plsqr_solve.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(plsqr_problem), ctypes.c_void_p,
                                 ctypes.c_void_p, P(ctypes.c_uint64)]
+    lib.plsqr_solve_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                      P(plsqr_problem), P(ctypes.c_void_p), P(ctypes.c_void_p),
+                                      P(ctypes.c_uint64)]
     lib.plsqr_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(plsqr_result)]
     lib.plsqr_wait_all.argtypes = [ctypes.c_void_p]
     lib.plsqr_destroy.argtypes = [ctypes.c_void_p]
@@ -134,6 +138,16 @@ def plsqr_solve(eng, op_id, prob, g_dev, f_dev):
     ticket = ctypes.c_uint64()
     _check(_lib.plsqr_solve(eng, op_id, ctypes.byref(prob), g_dev, f_dev, ctypes.byref(ticket)), eng)
     return ticket.value
+
+
+def plsqr_solve_batch(eng, op_id, probs, g_devs, f_devs):
+    n = len(probs)
+    arr = (plsqr_problem * n)(*probs)
+    gs = (ctypes.c_void_p * n)(*g_devs)
+    fs = (ctypes.c_void_p * n)(*f_devs)
+    tickets = (ctypes.c_uint64 * n)()
+    _check(_lib.plsqr_solve_batch(eng, op_id, n, arr, gs, fs, tickets), eng)
+    return list(tickets)
 
 
 def plsqr_poll(eng, ticket):

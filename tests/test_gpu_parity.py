@@ -253,3 +253,76 @@ def test_full_size_first_iterations(engine, which):
     else:
         p = gen.config_c3(outer=1, inner=3)
     _check(p, engine)
+
+
+# ---- lockstep batches ---------------------------------------------------------------
+
+def _run_batch(engine, problems, precision=0, op_id=None):
+    import torch
+    from paper_1308_6634_amd.engine import problem_struct
+    p0 = problems[0]
+    if op_id is None:
+        op_id = (engine.dense_operator(p0.dims, p0.A) if p0.op_kind == "dense"
+                 else engine.blur_operator(p0.dims, p0.taps))
+    gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda()
+          for p in problems]
+    fs = [torch.zeros(p.n_x, device="cuda") for p in problems]
+    ts = engine.submit_batch(op_id, [problem_struct(p, precision=precision) for p in problems],
+                             gs, fs)
+    for t in ts:
+        st, _ = engine.wait(t)
+        assert st == 0, st
+    nx, ny, nz = p0.dims
+    return [f.cpu().numpy().reshape(nz, ny, nx) for f in fs]
+
+
+def test_batch_fp32_blur_is_bitwise_equal_to_alone(engine):
+    from paper_1308_6634_amd.engine import solve
+    regs = [("stv", 0.05, 5.0), ("pm_log", 0.1, 20.0), ("tikhonov", 1.0, 2.0), ("pm_exp", 0.1, 8.0)]
+    probs = [gen.small_blur_case(60 + i, (16, 12, 8), reg=r, T=T, tau=tau, outer=2, inner=6,
+                                 levels=2) for i, (r, T, tau) in enumerate(regs)]
+    _say("[batch] fp32 blur x4 (16,12,8)")
+    batched = _run_batch(engine, probs)
+    for p, fb in zip(probs, batched):
+        fa, _ = solve(p, engine=engine)
+        np.testing.assert_array_equal(fa, fb)
+
+
+def test_batch_fp32_dense_matches_oracle(engine):
+    A = gen.small_dense_case(70, 8).A
+    probs = [gen.small_dense_case(70 + i, 8, reg=("stv", "pm_log")[i % 2],
+                                  T=(0.02, 0.05)[i % 2], outer=2, inner=6, levels=2, A=A)
+             for i in range(3)]
+    _say("[batch] fp32 dense x3 (8^3)")
+    for p, f in zip(probs, _run_batch(engine, probs)):
+        f_ref, _ = lagged.solve_problem(p)
+        assert _rel(f, f_ref) <= TOL
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 5e-3), (2, 5e-3)])
+def test_batch_bf16_dense_matches_oracle(engine, precision, tol):
+    A = gen.small_dense_case(80, 16).A            # 1024 x 4096: both divisible by 128
+    probs = [gen.small_dense_case(80 + i, 16, reg=("stv", "pm_log")[i % 2],
+                                  T=(0.02, 0.05)[i % 2], tau=20.0, outer=3, inner=10, levels=3,
+                                  A=A) for i in range(5)]
+    _say(f"[batch] bf16 precision={precision} dense x5 (16^3)")
+    errs = []
+    for p, f in zip(probs, _run_batch(engine, probs, precision=precision)):
+        f_ref, _ = lagged.solve_problem(p)
+        errs.append(_rel(f, f_ref))
+    _say(f"[batch] bf16 precision={precision}: rel L2 = {['%.2e' % e for e in errs]}")
+    assert max(errs) <= tol, errs
+
+
+def test_batch_bf16_alone_equals_in_batch(engine):
+    """An instance gives the same f alone (batch of one) and inside a batch of 33
+    (two MFMA column tiles): its column of the GEMM does not see the others."""
+    A = gen.small_dense_case(90, 16).A
+    probs = [gen.small_dense_case(90 + (i % 4), 16, outer=2, inner=5, levels=3, A=A)
+             for i in range(33)]
+    import torch
+    op = engine.dense_operator(probs[0].dims, torch.from_numpy(A).cuda())
+    alone = _run_batch(engine, probs[:1], precision=1, op_id=op)[0]
+    many = _run_batch(engine, probs, precision=1, op_id=op)
+    assert _rel(many[0], alone) <= 1e-6
+    assert _rel(many[32], many[0]) <= 1e-6
