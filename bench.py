@@ -103,7 +103,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1", "c4"])
+    ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "bf16"],
+                    help="c4 only: BF16 product mode of the batched path")
+    ap.add_argument("--plain-sample", type=int, default=2,
+                    help="c4 only: instances run one at a time on the FP32 path for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (HBM counter calibration)")
@@ -128,6 +132,8 @@ def main():
     from paper_1308_6634_amd import plsqr as P
     from paper_1308_6634_amd.engine import Engine, problem_struct
 
+    if args.workload == "c4":
+        return bench_c4(args)
     p, desc = workload(args.workload)
     nx, ny, nz = p.dims
     n = nx * ny * nz
@@ -206,6 +212,92 @@ def main():
         assert st == 0
         fg = f.cpu().numpy().astype(np.float64).reshape(f_ref.shape)
         out["parity_sample_rel_l2"] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(args):
+    """64 reconstructions of 64^3 sharing one 8192 x 262144 sensitivity, batched in lockstep
+    with the dense products on MFMA (BF16 split products), against the same instances run
+    one at a time on the FP32 path."""
+    import numpy as np
+    import torch
+    import gen
+    from gen.configs import c4_matrix
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+
+    B = 64
+    A = c4_matrix(64)
+    probs = [gen.config_c4(i, A) for i in range(B)]
+    p0 = probs[0]
+    n, m = p0.n_x, A.shape[0]
+    prec = P.PLSQR_PREC_BF16_REFINED if args.precision == "bf16_refined" else P.PLSQR_PREC_BF16
+    desc = (f"64 instances x 64^3, shared dense ring sensitivity {m}x{n} (8 source rings x 16, "
+            f"4 detector rings x 16, mu=0.5), own ellipsoid phantom / noise / regulariser "
+            f"(sTV 0.02 or PM-log 0.05), tau=20, 8 outer x 40 inner, 5-level Jacobi V(2,2); "
+            f"products {args.precision} on MFMA")
+    print(f"[bench] workload c4: {desc}", file=sys.stderr, flush=True)
+    eng = Engine(0)
+    A_dev = torch.from_numpy(A).cuda()
+    del A
+    op = eng.dense_operator(p0.dims, A_dev)
+    gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32)).cuda() for p in probs]
+    fs = [torch.zeros(n, device="cuda") for _ in probs]
+    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, precision=prec) for p in probs]
+
+    def run_batch():
+        ts = eng.submit_batch(op, pbs, gs, fs)
+        res = [eng.wait(t) for t in ts]
+        for st, _ in res:
+            assert st == 0, P.plsqr_last_error(eng.handle)
+        return res
+
+    for _ in range(args.warmup):
+        run_batch()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [run_batch() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = B * n * p0.outer * p0.inner * args.steps / elapsed
+    r0 = [res[0][1] for res in results]
+    fwd_ms = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1)
+    adj_ms = sum(r.adjoint_ms for r in r0) / max(sum(r.adjoint_launches for r in r0), 1)
+    lo = 2 if prec == P.PLSQR_PREC_BF16_REFINED else 1
+    fwd_bytes = lo * 2 * m * n + 2 * 2 * 64 * n
+    fwd_flops = 2.0 * m * n * 64 * (lo + 1)
+    print(f"[bench] batched: {elapsed / args.steps * 1e3:.1f} ms per batch; forward product "
+          f"{fwd_ms:.3f} ms, adjoint {adj_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    # plain comparison: the same instances one at a time, FP32 products
+    pl = [problem_struct(p, flags=0) for p in probs[:args.plain_sample]]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i, pb in enumerate(pl):
+        st, _ = eng.wait(eng.submit(op, pb, gs[i], torch.zeros(n, device="cuda")))
+        assert st == 0
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t1) / max(len(pl), 1)
+    plain_value = n * p0.outer * p0.inner / plain_s
+    out = {
+        "metric": "voxel-LSQR-iters/s", "value": value, "unit": "voxel-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {desc}", "instances": B, "n_x": n, "n_y": m,
+                   "outer": p0.outer, "inner": p0.inner, "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "forward product (pack + k_gemm_bf16 + reduce)",
+                     "achieved": fwd_bytes / (fwd_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": fwd_bytes / (fwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": fwd_bytes, "avg_launch_ms": fwd_ms,
+                     "mfma_tflops": fwd_flops / (fwd_ms / 1e3) / 1e12, "mfma_peak_tflops": 2500.0},
+        "plain_fp32_one_at_a_time": {"value": plain_value, "unit": "voxel-iter/s",
+                                     "sample": f"{len(pl)} of the {B} instances, FP32 products",
+                                     "s_per_instance": plain_s},
+        "batched_over_plain": value / plain_value,
+    }
     eng.close()
     print(json.dumps(out), flush=True)
 

@@ -326,3 +326,28 @@ def test_batch_bf16_alone_equals_in_batch(engine):
     many = _run_batch(engine, probs, precision=1, op_id=op)
     assert _rel(many[0], alone) <= 1e-6
     assert _rel(many[32], many[0]) <= 1e-6
+
+
+def test_full_size_c4_batch_first_iterations(engine):
+    """The 64-instance batch at full size (8192 x 262144 shared A, MFMA products with
+    refinement), first outer step with two inner steps; instances 0 and 63 against the
+    oracle. The oracle's FP64 copy of A is built once and shared."""
+    import torch
+    from gen.configs import c4_matrix
+    from oracle import multigrid
+    from oracle.operators import Dense
+    A = c4_matrix(64)
+    probs = [gen.config_c4(i, A, outer=1, inner=2) for i in range(64)]
+    _say("[parity] c4 full-size batch of 64, 1 x 2, bf16_refined")
+    op_id = engine.dense_operator(probs[0].dims, torch.from_numpy(A).cuda())
+    fs = _run_batch(engine, probs, precision=1, op_id=op_id)
+    op = Dense(A, (64, 64, 64))
+    del A
+    for i in (0, 63):
+        p = probs[i]
+        sm = multigrid.Smoother(p.smoother, p.nu_pre, p.nu_post, p.omega)
+        f_ref, _ = lagged.solve((64, 64, 64), op, p.g.astype(np.float64), p.reg, p.T, p.tau,
+                                p.eps, 1, 2, p.levels, sm)
+        err = _rel(fs[i], f_ref)
+        _say(f"[parity] c4 instance {i}: rel L2 = {err:.3e}")
+        assert err <= 5e-3
