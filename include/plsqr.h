@@ -180,7 +180,7 @@ int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, con
  * GEMMs over the batch, reading A once per product for the whole batch). The problems
  * may differ in reg, T, tau, eps, omega and the Chebyshev interval but must share grid,
  * counts, levels, smoother kind and steps, precision and flags. BF16 batches need a
- * dense operator, count <= 64 and n_X, n_Y divisible by 128; the BF16 copies of A
+ * dense operator, count <= 64 and n_X, n_Y divisible by 256; the BF16 copies of A
  * (A_hi, A_lo and their transposes) are taken from the operator if given, else built
  * by the library on first use and kept until plsqr_destroy. tickets[i] receives the
  * ticket of request i; every ticket completes when the whole batch does. */

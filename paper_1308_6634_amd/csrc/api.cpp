@@ -136,7 +136,7 @@ size_t plan_group(Group &G, const Operator &op, const Layout &Ly) {
     GemmArgs &g = G.gemm;
     g.Bpad = B <= 32 ? 32 : 64;
     const long long m = Ly.m, n = Ly.n;
-    const long long rowtiles = m / 128;
+    const long long rowtiles = m / 256;      // forward GEMM blocks own 256 rows of A
     long long ks = std::max(1LL, std::min(n / 128, (1024 + rowtiles - 1) / rowtiles));
     long long kchunk = ((n + ks - 1) / ks + 127) / 128 * 128;
     ks = (n + kchunk - 1) / kchunk;
@@ -403,8 +403,8 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
     if (op->op.kind != PLSQR_OP_DENSE)
       return set_error(PLSQR_E_INVALID, "BF16 products need a dense operator");
     if (count > 64) return set_error(PLSQR_E_INVALID, "a BF16 batch holds at most 64 instances");
-    if (lays[0].n % 128 || lays[0].m % 128)
-      return set_error(PLSQR_E_INVALID, "BF16 products need n_X and n_Y divisible by 128");
+    if (lays[0].n % 256 || lays[0].m % 256)
+      return set_error(PLSQR_E_INVALID, "BF16 products need n_X and n_Y divisible by 256");
   }
   auto G = std::make_unique<Group>();
   G->id = eng->next_group++;

@@ -6,12 +6,14 @@
 // v = hi + lo with hi = bf16(v), lo = bf16(v - hi); the product keeps hi.hi, hi.lo and
 // (optionally) lo.hi terms: the one-step refinement of a single BF16 product.
 //
-// Tiling (gfx950, v_mfma_f32_32x32x16_bf16, wave64): a block of 4 waves owns 128 rows of
+// Tiling (gfx950, v_mfma_f32_32x32x16_bf16, wave64): a block of 8 waves owns 256 rows of
 // the left operand; each wave owns 32 rows and all Bpad (= 32 * NT) columns. Per step of
 // 128 along K, lane (i, h) (i = lane % 32, h = lane / 32) loads 64 contiguous K values of
-// its row (8 x 16-byte loads) and feeds them to 8 MFMAs; the right-operand lane (j, h)
-// loads the same 64 K indices of column j, so every MFMA pairs identical K indices (the
-// K order inside one 128-step is a permutation, which the sum does not see).
+// its row (8 x 16-byte loads, prefetched one step ahead) and feeds them to 8 MFMAs; the
+// right-operand block of the step (hi and lo, Bpad x 128) is staged once per block in
+// LDS (double-buffered, rows padded against bank conflicts) and lane (j, h) reads the
+// same 64 K indices of column j, so every MFMA pairs identical K indices (the K order
+// inside one 128-step is a permutation, which the sum does not see).
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -21,14 +23,57 @@ namespace plsqr {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kGemmRows = 128;   // rows of the left operand per block
-constexpr int kKStep = 128;      // K per step
+constexpr int kGemmWaves = 8;                 // waves per block
+constexpr int kGemmRows = 32 * kGemmWaves;    // rows of the left operand per block
+constexpr int kKStep = 128;                   // K per step
+constexpr int kLdsRow = kKStep + 8;           // bf16 per LDS column row (padded: no bank conflicts)
 
-template <int NT, bool LO_L, bool LO_R, bool EPI>
-__global__ void __launch_bounds__(256) k_gemm_bf16(
+// Right-operand block of one K step in LDS: [hi | lo][Bpad columns][kLdsRow]. Each of
+// the 512 threads moves NT * 2 chunks of 16 bytes (held in named registers, not an array,
+// so that they never go to scratch).
+struct XChunks {
+  uint4 v[4];
+};
+
+__device__ __forceinline__ void chunk_coords(int q, int NT, int &half, int &col, int &chunk) {
+  const int idx = q * 512 + (int)threadIdx.x;   // 16-byte chunk index
+  half = idx / (NT * 32 * 16);                   // 0: hi, 1: lo
+  const int rem = idx % (NT * 32 * 16);
+  col = rem / 16;
+  chunk = rem % 16;
+}
+
+template <int NT>
+__device__ __forceinline__ XChunks stage_right(const __bf16 *__restrict__ Rhi,
+                                               const __bf16 *__restrict__ Rlo, long long K,
+                                               long long k0) {
+  XChunks x;
+#pragma unroll
+  for (int q = 0; q < NT * 2; ++q) {
+    int half, col, chunk;
+    chunk_coords(q, NT, half, col, chunk);
+    const __bf16 *src = (half ? Rlo : Rhi) + (long long)col * K + k0 + chunk * 8;
+    x.v[q] = *reinterpret_cast<const uint4 *>(src);
+  }
+  return x;
+}
+
+template <int NT>
+__device__ __forceinline__ void store_right(__bf16 *lds, const XChunks &x) {
+#pragma unroll
+  for (int q = 0; q < NT * 2; ++q) {
+    int half, col, chunk;
+    chunk_coords(q, NT, half, col, chunk);
+    *reinterpret_cast<uint4 *>(lds + ((half * NT * 32 + col) * kLdsRow + chunk * 8)) = x.v[q];
+  }
+}
+
+template <int NT, bool LO_L, bool EPI>
+__global__ void __launch_bounds__(512, 1) k_gemm_bf16(
     const __bf16 *__restrict__ Lhi, const __bf16 *__restrict__ Llo,
     const __bf16 *__restrict__ Rhi, const __bf16 *__restrict__ Rlo, long long M, long long K,
     long long kchunk, int Bpad, float *__restrict__ out, InstDesc *const *descs, int B, int epi) {
+  __shared__ __bf16 lds[2][2 * NT * 32 * kLdsRow];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, h = lane >> 5;
   const long long row0 = (long long)blockIdx.x * kGemmRows + wave * 32;
@@ -43,42 +88,61 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(
 
   const __bf16 *pa = Lhi + (row0 + li) * K + h * 64;
   const __bf16 *pal = LO_L ? Llo + (row0 + li) * K + h * 64 : nullptr;
-  const __bf16 *pb[NT];
-  const __bf16 *pbl[NT];
+  bf16x8 a[8], al[LO_L ? 8 : 1];
+  XChunks xr;
+  // prologue: step kbeg
+  if (kbeg < kend) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    pb[t] = Rhi + (long long)(t * 32 + li) * K + h * 64;
-    pbl[t] = LO_R ? Rlo + (long long)(t * 32 + li) * K + h * 64 : nullptr;
-  }
-  for (long long k0 = kbeg; k0 < kend; k0 += kKStep) {
-    bf16x8 a[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = *reinterpret_cast<const bf16x8 *>(pa + k0 + s * 8);
-    bf16x8 al[LO_L ? 8 : 1];
+    for (int s = 0; s < 8; ++s) a[s] = *reinterpret_cast<const bf16x8 *>(pa + kbeg + s * 8);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) al[s] = *reinterpret_cast<const bf16x8 *>(pal + k0 + s * 8);
+      for (int s = 0; s < 8; ++s) al[s] = *reinterpret_cast<const bf16x8 *>(pal + kbeg + s * 8);
     }
+    xr = stage_right<NT>(Rhi, Rlo, K, kbeg);
+    store_right<NT>(lds[0], xr);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = kbeg; k0 < kend; k0 += kKStep) {
+    const long long kn = k0 + kKStep;
+    const bool more = kn < kend;
+    // prefetch the next step's operands while this step computes
+    bf16x8 an[8], aln[LO_L ? 8 : 1];
+    if (more) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      bf16x8 b[8];
+      for (int s = 0; s < 8; ++s) an[s] = *reinterpret_cast<const bf16x8 *>(pa + kn + s * 8);
+      if constexpr (LO_L) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) b[s] = *reinterpret_cast<const bf16x8 *>(pb[t] + k0 + s * 8);
+        for (int s = 0; s < 8; ++s) aln[s] = *reinterpret_cast<const bf16x8 *>(pal + kn + s * 8);
+      }
+      xr = stage_right<NT>(Rhi, Rlo, K, kn);
+    }
+    const __bf16 *L0 = lds[buf];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], b[s], acc[t], 0, 0, 0);
+    for (int s = 0; s < 8; ++s) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int col = t * 32 + li;
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(L0 + col * kLdsRow + h * 64 + s * 8);
+        const bf16x8 bl =
+            *reinterpret_cast<const bf16x8 *>(L0 + (NT * 32 + col) * kLdsRow + h * 64 + s * 8);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], b, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], bl, acc[t], 0, 0, 0);
         if constexpr (LO_L)
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], b[s], acc[t], 0, 0, 0);
-      }
-      if constexpr (LO_R) {
-        bf16x8 bl[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) bl[s] = *reinterpret_cast<const bf16x8 *>(pbl[t] + k0 + s * 8);
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], bl[s], acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], b, acc[t], 0, 0, 0);
       }
     }
+    if (more) {
+      store_right<NT>(lds[buf ^ 1], xr);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[s] = an[s];
+      if constexpr (LO_L) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) al[s] = aln[s];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
   }
   // accumulator element r of lane (li, h) is (row 8*(r/4) + 4*h + r%4, column li) of the tile
 #pragma unroll
@@ -163,12 +227,12 @@ __global__ void __launch_bounds__(kBlock) k_transpose16(const uint16_t *in, uint
 // ------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------
-template <int NT, bool LO_L, bool LO_R, bool EPI>
+template <int NT, bool LO_L, bool EPI>
 static void gemm_launch(hipStream_t st, const void *Lhi, const void *Llo, const void *Rhi,
                         const void *Rlo, long long M, long long K, long long kchunk, int ks,
                         int Bpad, float *out, InstDesc *const *descs, int B, int epi) {
-  hipLaunchKernelGGL((k_gemm_bf16<NT, LO_L, LO_R, EPI>), dim3((unsigned)(M / kGemmRows), ks),
-                     dim3(256), 0, st, (const __bf16 *)Lhi, (const __bf16 *)Llo,
+  hipLaunchKernelGGL((k_gemm_bf16<NT, LO_L, EPI>), dim3((unsigned)(M / kGemmRows), ks),
+                     dim3(32 * kGemmWaves), 0, st, (const __bf16 *)Lhi, (const __bf16 *)Llo,
                      (const __bf16 *)Rhi, (const __bf16 *)Rlo, M, K, kchunk, Bpad, out, descs, B,
                      epi);
 }
@@ -179,11 +243,11 @@ static void gemm_dispatch(hipStream_t st, int NT, bool lo_l, const void *Lhi, co
                           long long kchunk, int ks, int Bpad, float *out, InstDesc *const *descs,
                           int B, int epi) {
   if (NT == 1) {
-    if (lo_l) gemm_launch<1, true, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
-    else gemm_launch<1, false, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    if (lo_l) gemm_launch<1, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    else gemm_launch<1, false, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
   } else {
-    if (lo_l) gemm_launch<2, true, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
-    else gemm_launch<2, false, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    if (lo_l) gemm_launch<2, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    else gemm_launch<2, false, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
   }
 }
 
