@@ -232,7 +232,7 @@ static void gemm_launch(hipStream_t st, const void *Lhi, const void *Llo, const 
                         const void *Rlo, long long M, long long K, long long kchunk, int ks,
                         int Bpad, float *out, InstDesc *const *descs, int B, int epi) {
   hipLaunchKernelGGL((k_gemm_bf16<NT, LO_L, EPI>), dim3((unsigned)(M / kGemmRows), ks),
-                     dim3(32 * kGemmWaves), 0, st, (const __bf16 *)Lhi, (const __bf16 *)Llo,
+                     dim3(64 * kGemmWaves), 0, st, (const __bf16 *)Lhi, (const __bf16 *)Llo,
                      (const __bf16 *)Rhi, (const __bf16 *)Rlo, M, K, kchunk, Bpad, out, descs, B,
                      epi);
 }
