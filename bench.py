@@ -103,7 +103,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=2000, help="c5 only: requests in the stream")
+    ap.add_argument("--templates", type=int, default=40,
+                    help="c5 only: distinct pre-generated reconstructions the stream cycles through")
+    ap.add_argument("--plain-requests", type=int, default=300,
+                    help="c5 only: prefix of the stream replayed on the plain one-at-a-time path")
     ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "bf16"],
                     help="c4 only: BF16 product mode of the batched path")
     ap.add_argument("--plain-sample", type=int, default=2,
@@ -134,6 +139,8 @@ def main():
 
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
     p, desc = workload(args.workload)
     nx, ny, nz = p.dims
     n = nx * ny * nz
@@ -299,6 +306,108 @@ def bench_c4(args):
         "batched_over_plain": value / plain_value,
     }
     eng.close()
+    print(json.dumps(out), flush=True)
+
+
+def _replay(eng, arrivals, reqs, poll_sleep=0.0005):
+    """Submit reqs[i] at arrivals[i] seconds from now (one thread) while another thread
+    polls; returns per-request (latency ms, status) and the wall span."""
+    import threading
+    n = len(reqs)
+    tickets = [None] * n
+    done = [None] * n
+    t0 = time.perf_counter()
+    t_sub = [0.0] * n
+
+    def submitter():
+        for i, (op, pb, g, f) in enumerate(reqs):
+            dt = t0 + arrivals[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            t_sub[i] = time.perf_counter()
+            tickets[i] = eng.submit(op, pb, g, f)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    remaining = set(range(n))
+    while remaining:
+        for i in list(remaining):
+            if tickets[i] is None:
+                continue
+            st, res = eng.poll(tickets[i])
+            if st != 1:
+                done[i] = (res.submit_to_done_ms if res is not None else float("nan"), st,
+                           time.perf_counter())
+                remaining.discard(i)
+        time.sleep(poll_sleep)
+    th.join()
+    span = max(d[2] for d in done) - t0
+    return done, span
+
+
+def bench_c5(args):
+    """Served stream: Poisson arrivals (mean 20 ms), grid sizes 32..128^3, blur sigma
+    U(1.5,3.5), regulariser and tau per request, 8 x 40; continuous batching engine
+    against the plain one-request-at-a-time path on a prefix of the same stream."""
+    import numpy as np
+    import torch
+    import gen
+    from gen.configs import c5_request
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+
+    N, NT = args.requests, args.templates
+    arrivals = gen.config_c5_requests(count=N)
+    print(f"[bench] c5: generating {NT} request templates", file=sys.stderr, flush=True)
+    temps = [c5_request(r) for r in range(NT)]
+    desc = (f"{N} Poisson requests (mean gap 20 ms) cycling through {NT} seeded reconstructions: "
+            f"grid uniform over {{32,48,64,96,128}}^3, blur sigma U(1.5,3.5) radius ceil(3 sigma), "
+            f"10 boxes/spheres, 1% noise, Tikhonov / sTV 0.02 / PM-log 0.05, tau U(10,100), 8x40, "
+            f"auto levels, Jacobi V(2,2); HBM budget 200 GB")
+    gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda() for p in temps]
+    work = [p.n_x * p.outer * p.inner for p in temps]
+
+    def build(eng, count):
+        ops = [eng.blur_operator(p.dims, p.taps) for p in temps]
+        pbs = [problem_struct(p) for p in temps]
+        out = []
+        for i in range(count):
+            k = i % NT
+            out.append((ops[k], pbs[k], gs[k], torch.zeros(temps[k].n_x, device="cuda")))
+        return out
+
+    srv = Engine(0, hbm_budget_bytes=200 * 10**9, flags=P.PLSQR_ENGINE_SERVE)
+    warm = build(srv, NT)
+    _replay(srv, np.zeros(NT), warm)            # warm-up: every template once
+    reqs = build(srv, N)
+    torch.cuda.synchronize()
+    print("[bench] c5: serving the stream", file=sys.stderr, flush=True)
+    done, span = _replay(srv, arrivals, reqs)
+    srv.close()
+    lat = np.array([d[0] for d in done])
+    assert all(d[1] == 0 for d in done)
+    total = sum(work[i % NT] for i in range(N))
+    served_value = total / span
+
+    plain = Engine(0, hbm_budget_bytes=200 * 10**9)
+    M = min(args.plain_requests, N)
+    preqs = build(plain, M)
+    print(f"[bench] c5: plain path on the first {M} requests", file=sys.stderr, flush=True)
+    pdone, pspan = _replay(plain, arrivals[:M], preqs)
+    plain.close()
+    plat = np.array([d[0] for d in pdone])
+    ptotal = sum(work[i % NT] for i in range(M))
+    out = {
+        "metric": "voxel-LSQR-iters/s", "value": served_value, "unit": "voxel-iter/s",
+        "n_gpus": 1, "steps": N, "warmup": NT, "ms_per_step": span / N * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": f"c5: {desc}"},
+        "served": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "requests": N, "span_s": span, "voxel_iters_per_s": served_value},
+        "plain": {"p50_ms": float(np.percentile(plat, 50)), "p99_ms": float(np.percentile(plat, 99)),
+                  "requests": M, "span_s": pspan, "voxel_iters_per_s": ptotal / pspan},
+        "served_over_plain_throughput": served_value / (ptotal / pspan),
+    }
     print(json.dumps(out), flush=True)
 
 

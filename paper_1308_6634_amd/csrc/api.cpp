@@ -7,6 +7,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <chrono>
+#include <thread>
+#include <tuple>
 
 #include "engine.hpp"
 
@@ -438,6 +441,221 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
   return PLSQR_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// Serving mode: a scheduler thread admits requests by HBM budget, keeps their Krylov and
+// multigrid state resident, and every tick advances each resident request by one step
+// of its fixed schedule. Requests of the same grid and multigrid schedule that are at the
+// same step type form one subgroup, launched together as a batch (their blur taps,
+// regulariser, tau, eps and scalars come from their own descriptors), so requests that
+// arrive while others run join the next tick. Only this thread issues HIP calls.
+// ------------------------------------------------------------------------------------
+struct ClassKey {
+  int nx, ny, nz, levels, smoother, nu, deg, kind, type;
+  bool operator<(const ClassKey &o) const {
+    return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type) <
+           std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type);
+  }
+};
+
+void serve_collect(plsqr_engine *eng) {
+  for (size_t i = 0; i < eng->finishing.size();) {
+    Request &r = *eng->reqs[eng->finishing[i]];
+    if (hipEventQuery(r.ev_done) != hipSuccess) {
+      ++i;
+      continue;
+    }
+    plsqr_result &res = r.result;
+    std::memset(&res, 0, sizeof(res));
+    const double *sc = reinterpret_cast<const double *>(r.pinned + pin_sc_off());
+    const double *dg = reinterpret_cast<const double *>(r.pinned + pin_dg_off());
+    res.status = (int)sc[SC_STATUS];
+    res.outer_done = r.pb.outer;
+    res.levels = r.lay.levels;
+    for (int k = 1; k <= r.pb.outer; ++k) {
+      res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
+      res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
+      res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.ev_start, r.ev_done) == hipSuccess) res.device_ms = ms;
+    res.workspace_bytes = (int64_t)r.lay.total;
+    r.t_done = now_ms();
+    res.submit_to_done_ms = r.t_done - r.t_submit;
+    hipEventDestroy(r.ev_start);
+    hipEventDestroy(r.ev_done);
+    r.ev_start = r.ev_done = nullptr;
+    hipHostFree(r.pinned);
+    r.pinned = nullptr;
+    r.status = res.status;
+    r.done = true;
+    eng->finishing[i] = eng->finishing.back();
+    eng->finishing.pop_back();
+  }
+}
+
+void serve_admit(plsqr_engine *eng) {
+  while (!eng->serve_queue.empty()) {
+    Request &r = *eng->reqs[eng->serve_queue.front()];
+    if (eng->budget && eng->used + r.lay.total > eng->budget) break;
+    eng->serve_queue.pop_front();
+    int rc = PLSQR_OK;
+    r.ws = static_cast<char *>(eng->pool.get(r.lay.total));
+    if (!r.ws) rc = PLSQR_E_NOMEM;
+    if (rc == PLSQR_OK &&
+        hipHostMalloc(reinterpret_cast<void **>(&r.pinned), pin_bytes(r.pb), hipHostMallocDefault) != hipSuccess)
+      rc = PLSQR_E_NOMEM;
+    if (rc == PLSQR_OK && (hipEventCreate(&r.ev_start) != hipSuccess || hipEventCreate(&r.ev_done) != hipSuccess))
+      rc = PLSQR_E_HIP;
+    if (rc != PLSQR_OK) {
+      if (r.ws) eng->pool.put(r.ws, r.lay.total);
+      r.ws = nullptr;
+      if (r.pinned) hipHostFree(r.pinned);
+      r.pinned = nullptr;
+      std::memset(&r.result, 0, sizeof(r.result));
+      r.result.status = rc;
+      r.status = rc;
+      r.done = true;
+      continue;
+    }
+    eng->used += r.lay.total;
+    fill_desc(eng, r, eng->ops[r.group]);   // in serving mode `group` holds the operator id
+    r.d_desc = reinterpret_cast<InstDesc *>(r.ws + r.lay.desc);
+    std::memcpy(r.pinned, &r.host, sizeof(InstDesc));
+    hipEventRecord(r.ev_start, eng->stream);
+    hipMemcpyAsync(r.d_desc, r.pinned, sizeof(InstDesc), hipMemcpyHostToDevice, eng->stream);
+    r.step = 0;
+    r.steps_total = step_count(r.pb);
+    eng->resident.push_back(r.ticket);
+  }
+}
+
+// Build and enqueue one tick. Caller holds the lock.
+void serve_tick(plsqr_engine *eng) {
+  std::map<ClassKey, std::vector<Request *>> groups;
+  for (uint64_t t : eng->resident) {
+    Request &r = *eng->reqs[t];
+    const plsqr_problem &pb = r.pb;
+    ClassKey key{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
+                 r.host.op_kind, step_type(pb, r.step)};
+    groups[key].push_back(&r);
+  }
+  plsqr_engine::TickSlot &slot = eng->ring[eng->ring_next];
+  const size_t need = eng->resident.size() * sizeof(void *) + groups.size() * 256;
+  if (slot.cap < need) {
+    if (slot.pinned) hipHostFree(slot.pinned);
+    if (slot.dev) hipFree(slot.dev);
+    slot.cap = std::max<size_t>(need * 2, 1 << 16);
+    hipHostMalloc(reinterpret_cast<void **>(&slot.pinned), slot.cap, hipHostMallocDefault);
+    hipMalloc(reinterpret_cast<void **>(&slot.dev), slot.cap);
+  }
+  size_t off = 0;
+  std::vector<std::pair<size_t, std::vector<Request *> *>> plan;
+  for (auto &kv : groups) {
+    off = (off + 255) / 256 * 256;
+    InstDesc **dst = reinterpret_cast<InstDesc **>(slot.pinned + off);
+    for (size_t i = 0; i < kv.second.size(); ++i) dst[i] = kv.second[i]->d_desc;
+    plan.emplace_back(off, &kv.second);
+    off += kv.second.size() * sizeof(void *);
+  }
+  hipMemcpyAsync(slot.dev, slot.pinned, off, hipMemcpyHostToDevice, eng->stream);
+  std::vector<Request *> finished;
+  for (auto &pl : plan) {
+    std::vector<Request *> &mem = *pl.second;
+    Request &r0 = *mem[0];
+    BatchView bv{reinterpret_cast<InstDesc *const *>(slot.dev + pl.first), (int)mem.size(),
+                 &r0.host, &r0.lay, nullptr, nullptr, nullptr};
+    switch (step_type(r0.pb, r0.step)) {
+      case ST_BEGIN: enqueue_request_begin(eng->stream, bv); break;
+      case ST_OUTER_START:
+        enqueue_outer_setup(eng->stream, bv);
+        enqueue_mlsqr_init(eng->stream, bv);
+        break;
+      case ST_INNER: enqueue_inner(eng->stream, bv); break;
+      case ST_OUTER_END: enqueue_outer_end(eng->stream, bv); break;
+      default: enqueue_request_end(eng->stream, bv); break;
+    }
+    for (Request *r : mem)
+      if (++r->step == r->steps_total) finished.push_back(r);
+  }
+  for (Request *r : finished) {
+    hipMemcpyAsync(r->pinned + pin_sc_off(), r->ws + r->lay.sc, SC_COUNT * sizeof(double),
+                   hipMemcpyDeviceToHost, eng->stream);
+    hipMemcpyAsync(r->pinned + pin_dg_off(), r->ws + r->lay.diag,
+                   (size_t)(r->pb.outer + 1) * DG_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                   eng->stream);
+    hipEventRecord(r->ev_done, eng->stream);
+    // stream order makes the workspace reusable by any later admission right away
+    eng->pool.put(r->ws, r->lay.total);
+    r->ws = nullptr;
+    eng->used -= r->lay.total;
+    eng->resident.erase(std::find(eng->resident.begin(), eng->resident.end(), r->ticket));
+    eng->finishing.push_back(r->ticket);
+  }
+  hipEventRecord(slot.ev, eng->stream);
+  eng->inflight.push_back(eng->ring_next);
+  eng->ring_next = (eng->ring_next + 1) % (int)eng->ring.size();
+  ++eng->ticks;
+}
+
+void serve_loop(plsqr_engine *eng) {
+  hipSetDevice(eng->device);
+  std::unique_lock<std::mutex> lk(eng->mu);
+  while (!eng->stop_worker) {
+    serve_collect(eng);
+    serve_admit(eng);
+    if (eng->resident.empty()) {
+      if (eng->finishing.empty()) {
+        eng->cv.wait_for(lk, std::chrono::milliseconds(2));
+      } else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+        lk.lock();
+      }
+      continue;
+    }
+    // bound the work queued ahead of the device so that new arrivals join quickly
+    while ((int)eng->inflight.size() >= eng->max_inflight_ticks) {
+      const int s = eng->inflight.front();
+      hipEvent_t ev = eng->ring[s].ev;
+      lk.unlock();
+      while (hipEventQuery(ev) == hipErrorNotReady) std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+      eng->inflight.pop_front();
+      serve_collect(eng);
+    }
+    serve_tick(eng);
+  }
+  // drain
+  lk.unlock();
+  hipStreamSynchronize(eng->stream);
+  lk.lock();
+  eng->inflight.clear();
+  serve_collect(eng);
+}
+
+int serve_start(plsqr_engine *eng) {
+  eng->ring.resize(4);
+  for (auto &s : eng->ring)
+    if (hipEventCreate(&s.ev) != hipSuccess) return set_error(PLSQR_E_HIP, "hipEventCreate failed");
+  eng->worker = std::thread(serve_loop, eng);
+  return PLSQR_OK;
+}
+
+void serve_stop(plsqr_engine *eng) {
+  {
+    std::lock_guard<std::mutex> lk(eng->mu);
+    eng->stop_worker = true;
+  }
+  eng->cv.notify_all();
+  if (eng->worker.joinable()) eng->worker.join();
+  for (auto &s : eng->ring) {
+    if (s.ev) hipEventDestroy(s.ev);
+    if (s.pinned) hipHostFree(s.pinned);
+    if (s.dev) hipFree(s.dev);
+  }
+  eng->ring.clear();
+}
+
 }  // namespace
 
 namespace plsqr {
@@ -497,13 +715,18 @@ int plsqr_create(plsqr_engine **out, int device, uint64_t hbm_budget_bytes, void
     return set_error(PLSQR_E_HIP, "no HIP device available");
   if (device < 0 || device >= ndev) return set_error(PLSQR_E_INVALID, "device index out of range");
   if (flags & ~(uint32_t)PLSQR_ENGINE_SERVE) return set_error(PLSQR_E_INVALID, "unknown engine flags");
-  if (flags & PLSQR_ENGINE_SERVE)
-    return set_error(PLSQR_E_INVALID, "serving mode is not available in this build");
   auto *e = new plsqr_engine();
   e->device = device;
   e->stream = static_cast<hipStream_t>(hip_stream);
   e->budget = hbm_budget_bytes;
   e->flags = flags;
+  if (flags & PLSQR_ENGINE_SERVE) {
+    const int rc = serve_start(e);
+    if (rc != PLSQR_OK) {
+      delete e;
+      return rc;
+    }
+  }
   *out = e;
   return PLSQR_OK;
 }
@@ -542,6 +765,31 @@ int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, con
   if (prob->precision != PLSQR_PREC_FP32)
     return set_error(PLSQR_E_INVALID, "single requests run in PLSQR_PREC_FP32");
   std::lock_guard<std::mutex> lk(eng->mu);
+  if (eng->flags & PLSQR_ENGINE_SERVE) {
+    // serving: validate and queue; the scheduler thread admits and runs it
+    const Operator *op = (op_id >= 0 && op_id < (int)eng->ops.size()) ? &eng->ops[op_id] : nullptr;
+    if (!g_dev || !f_dev) return set_error(PLSQR_E_INVALID, "g_dev and f_dev must be device pointers");
+    int levels = 0;
+    std::string why;
+    const int rc = validate(*prob, op, &levels, &why);
+    if (rc != PLSQR_OK) return set_error(rc, why);
+    auto r = std::make_unique<Request>();
+    r->ticket = eng->next_ticket++;
+    r->group = (uint64_t)op_id;
+    r->pb = *prob;
+    r->g = g_dev;
+    r->f_out = f_dev;
+    r->lay = make_layout(*prob, op->op.n_y, levels, op->op.kind);
+    r->host.op_kind = op->op.kind;
+    if (eng->budget && r->lay.total > eng->budget)
+      return set_error(PLSQR_E_BUDGET, "request workspace exceeds the engine's HBM budget");
+    r->t_submit = now_ms();
+    *ticket = r->ticket;
+    eng->serve_queue.push_back(r->ticket);
+    eng->reqs.emplace(r->ticket, std::move(r));
+    eng->cv.notify_all();
+    return PLSQR_OK;
+  }
   DeviceGuard dg(eng->device);
   return submit_group(eng, op_id, 1, prob, &g_dev, &f_dev, ticket);
 }
@@ -550,6 +798,8 @@ int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const pls
                       const float *const *g_devs, float *const *f_devs, uint64_t *tickets) {
   if (!eng || !probs || !g_devs || !f_devs || !tickets) return set_error(PLSQR_E_INVALID, "null argument");
   if (count < 1) return set_error(PLSQR_E_INVALID, "count must be >= 1");
+  if (eng->flags & PLSQR_ENGINE_SERVE)
+    return set_error(PLSQR_E_INVALID, "a serving engine batches by itself: submit with plsqr_solve");
   std::lock_guard<std::mutex> lk(eng->mu);
   DeviceGuard dg(eng->device);
   return submit_group(eng, op_id, count, probs, g_devs, f_devs, tickets);
@@ -561,7 +811,7 @@ int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {
   DeviceGuard dg(eng->device);
   auto it = eng->reqs.find(ticket);
   if (it == eng->reqs.end()) return set_error(PLSQR_E_UNKNOWN_TICKET, "unknown or retired ticket");
-  progress(eng);
+  if (!(eng->flags & PLSQR_ENGINE_SERVE)) progress(eng);
   Request &r = *it->second;
   if (!r.done) return PLSQR_PENDING;
   if (out) *out = r.result;
@@ -578,6 +828,16 @@ int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {
 
 int plsqr_wait_all(plsqr_engine *eng) {
   if (!eng) return set_error(PLSQR_E_INVALID, "null engine");
+  if (eng->flags & PLSQR_ENGINE_SERVE) {
+    for (;;) {
+      {
+        std::lock_guard<std::mutex> lk(eng->mu);
+        if (eng->serve_queue.empty() && eng->resident.empty() && eng->finishing.empty()) break;
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    return PLSQR_OK;
+  }
   std::lock_guard<std::mutex> lk(eng->mu);
   DeviceGuard dg(eng->device);
   for (;;) {
@@ -590,6 +850,22 @@ int plsqr_wait_all(plsqr_engine *eng) {
 
 int plsqr_destroy(plsqr_engine *eng) {
   if (!eng) return PLSQR_OK;
+  if (eng->flags & PLSQR_ENGINE_SERVE) {
+    serve_stop(eng);
+    std::lock_guard<std::mutex> lk(eng->mu);
+    for (uint64_t t : eng->resident) {
+      Request &r = *eng->reqs[t];
+      if (r.ws) eng->pool.put(r.ws, r.lay.total);
+      r.ws = nullptr;
+    }
+    for (auto &kv : eng->reqs) {
+      Request &r = *kv.second;
+      if (r.pinned) hipHostFree(r.pinned);
+      if (r.ev_start) hipEventDestroy(r.ev_start);
+      if (r.ev_done) hipEventDestroy(r.ev_done);
+      r.pinned = nullptr;
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(eng->mu);
     DeviceGuard dg(eng->device);

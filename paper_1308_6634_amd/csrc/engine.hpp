@@ -71,7 +71,21 @@ struct Request {
   int status = PLSQR_OK;
   double t_submit = 0.0, t_done = 0.0;
   plsqr_result result{};
+  // serving mode: position in the fixed step schedule and completion event
+  int step = 0, steps_total = 0;
+  hipEvent_t ev_start = nullptr, ev_done = nullptr;
 };
+
+// Step types of the served schedule: BEGIN, then per outer iteration OUTER_START
+// (setup + MLSQR initialisation), `inner` x INNER, OUTER_END, and finally FINISH.
+enum StepType : int { ST_BEGIN = 0, ST_OUTER_START, ST_INNER, ST_OUTER_END, ST_FINISH };
+inline int step_count(const plsqr_problem &pb) { return 2 + pb.outer * (pb.inner + 2); }
+inline int step_type(const plsqr_problem &pb, int s) {
+  if (s == 0) return ST_BEGIN;
+  if (s == step_count(pb) - 1) return ST_FINISH;
+  const int q = (s - 1) % (pb.inner + 2);
+  return q == 0 ? ST_OUTER_START : (q <= pb.inner ? ST_INNER : ST_OUTER_END);
+}
 
 // Instances launched together in lockstep (a plain solve is a group of one).
 struct Group {
@@ -130,8 +144,22 @@ struct plsqr_engine {
   uint64_t next_ticket = 1;
   uint64_t next_group = 1;
   plsqr::Pool pool;
-  // serving mode
+  // serving mode (PLSQR_ENGINE_SERVE): scheduler thread state, all guarded by mu
   std::thread worker;
   std::condition_variable cv;
   bool stop_worker = false;
+  std::deque<uint64_t> serve_queue;   // submitted, waiting for memory
+  std::vector<uint64_t> resident;     // admitted, advancing one step per tick
+  std::vector<uint64_t> finishing;    // last step enqueued, waiting for the device
+  struct TickSlot {
+    hipEvent_t ev = nullptr;
+    char *pinned = nullptr;           // pointer arrays of the tick's subgroups (host)
+    char *dev = nullptr;              // ... and their device copy
+    size_t cap = 0;
+  };
+  std::vector<TickSlot> ring;
+  std::deque<int> inflight;           // ring slots whose ticks are on the device
+  int ring_next = 0;
+  uint64_t ticks = 0;
+  int max_inflight_ticks = 2;
 };

@@ -351,3 +351,68 @@ def test_full_size_c4_batch_first_iterations(engine):
         err = _rel(fs[i], f_ref)
         _say(f"[parity] c4 instance {i}: rel L2 = {err:.3e}")
         assert err <= 5e-3
+
+
+# ---- served form ----------------------------------------------------------------------
+
+def _c5_like(i, n, outer=2, inner=5):
+    """Small served-stream-style request: blur sigma U(1.5,3.5), radius ceil(3 sigma)."""
+    rng = np.random.default_rng(900 + i)
+    sigma = float(rng.uniform(1.5, 3.5))
+    reg = ("tikhonov", "stv", "pm_log")[i % 3]
+    return gen.small_blur_case(900 + i, (n, n, n), sigma=sigma, radius=int(math.ceil(3 * sigma)),
+                               reg=reg, T={"tikhonov": 1.0, "stv": 0.02, "pm_log": 0.05}[reg],
+                               tau=float(rng.uniform(10, 100)), outer=outer, inner=inner,
+                               levels=gen.auto_levels((n, n, n)))
+
+
+@pytest.mark.parametrize("budget_factor", [0.0, 1.2])
+def test_served_mix_equals_alone(engine, budget_factor):
+    """Requests of different sizes, taps, regularisers and tau submitted to a serving engine
+    while others run (continuous batching) give the same f as each run alone."""
+    import time as _time
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+    sizes = [16, 24, 16, 32, 24, 16, 32, 16]
+    probs = [_c5_like(i, n, inner=4 + (i % 3)) for i, n in enumerate(sizes)]
+    alone = []
+    for p in probs:
+        alone.append(__import__("paper_1308_6634_amd.engine", fromlist=["solve"]).solve(
+            p, engine=engine)[0])
+    budget = 0
+    if budget_factor:
+        biggest = max(P.plsqr_workspace_bytes(problem_struct(p), P.PLSQR_OP_BLUR, p.n_x)
+                      for p in probs)
+        budget = int(biggest * budget_factor)       # admits about one request at a time
+    _say(f"[serve] mix of {len(probs)}, budget {budget}")
+    with Engine(0, hbm_budget_bytes=budget, flags=P.PLSQR_ENGINE_SERVE) as srv:
+        ts, fs = [], []
+        for i, p in enumerate(probs):
+            op = srv.blur_operator(p.dims, p.taps)
+            g = torch.from_numpy(p.g.ravel().copy()).cuda()
+            f = torch.zeros(p.n_x, device="cuda")
+            ts.append(srv.submit(op, problem_struct(p), g, f))
+            fs.append(f)
+            if i % 3 == 2:
+                _time.sleep(0.01)                    # later requests arrive mid-flight
+        res = [srv.wait(t) for t in ts]
+        srv.wait_all()
+    for (st, r), p, a, f in zip(res, probs, alone, fs):
+        assert st == 0
+        got = f.cpu().numpy().reshape(a.shape)
+        err = _rel(got, a)
+        assert err <= 1e-6, (p.name, err)
+        assert r.submit_to_done_ms > 0.0
+
+
+def test_served_rejects_batch_calls(engine):
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+    p = _c5_like(0, 16)
+    with Engine(0, flags=P.PLSQR_ENGINE_SERVE) as srv:
+        op = srv.blur_operator(p.dims, p.taps)
+        g = torch.zeros(p.n_x, device="cuda")
+        with pytest.raises(P.PlsqrError):
+            srv.submit_batch(op, [problem_struct(p)], [g], [g.clone()])
