@@ -309,7 +309,7 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
-def _replay(eng, arrivals, reqs, poll_sleep=0.0005):
+def _replay(eng, arrivals, reqs, poll_sleep=0.002):
     """Submit reqs[i] at arrivals[i] seconds from now (one thread) while another thread
     polls; returns per-request (latency ms, status) and the wall span."""
     import threading
@@ -336,8 +336,9 @@ def _replay(eng, arrivals, reqs, poll_sleep=0.0005):
                 continue
             st, res = eng.poll(tickets[i])
             if st != 1:
-                done[i] = (res.submit_to_done_ms if res is not None else float("nan"), st,
-                           time.perf_counter())
+                # latency from the scheduled arrival (a late submit counts against the path)
+                t_end = t_sub[i] + (res.submit_to_done_ms / 1e3 if res is not None else 0.0)
+                done[i] = ((t_end - (t0 + arrivals[i])) * 1e3, st, t_end)
                 remaining.discard(i)
         time.sleep(poll_sleep)
     th.join()

@@ -128,6 +128,44 @@ __device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *
   return acc;
 }
 
+// (A_l x)_j where the values of x come from a functor X(index): used when the iterate is
+// formed on the fly (first Jacobi sweep from zero, prolongated correction).
+template <class XF>
+__device__ __forceinline__ float stencil_f(const InstDesc &D, int l, long long j, Coord c,
+                                           XF X) {
+  const LevelDesc &L = D.lv[l];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const float xj = X(j);
+  float acc = (float)L.eps * xj;
+  if (l == 0) {
+    const float *__restrict__ k = D.kappa;
+    const float kj = k[j];
+    if (c.x + 1 < nx) acc += kj * (xj - X(j + 1));
+    if (c.x > 0) acc += k[j - 1] * (xj - X(j - 1));
+    if (c.y + 1 < ny) acc += kj * (xj - X(j + sy));
+    if (c.y > 0) acc += k[j - sy] * (xj - X(j - sy));
+    if (c.z + 1 < nz) acc += kj * (xj - X(j + sz));
+    if (c.z > 0) acc += k[j - sz] * (xj - X(j - sz));
+  } else {
+    if (c.x + 1 < nx) acc += L.wx[j] * (xj - X(j + 1));
+    if (c.x > 0) acc += L.wx[j - 1] * (xj - X(j - 1));
+    if (c.y + 1 < ny) acc += L.wy[j] * (xj - X(j + sy));
+    if (c.y > 0) acc += L.wy[j - sy] * (xj - X(j - sy));
+    if (nz > 1) {
+      if (c.z + 1 < nz) acc += L.wz[j] * (xj - X(j + sz));
+      if (c.z > 0) acc += L.wz[j - sz] * (xj - X(j - sz));
+    }
+  }
+  return acc;
+}
+
+// Index of the coarse parent of fine cell (c) on level l (2:1 in x, y and, in 3D, z).
+__device__ __forceinline__ long long parent_of(const LevelDesc &F, const LevelDesc &Cl, Coord c) {
+  const int cz = (F.nz > 1) ? 2 : 1;
+  return (c.x >> 1) + (long long)Cl.nx * ((c.y >> 1) + (long long)Cl.ny * (c.z / cz));
+}
+
 __device__ __forceinline__ void epilogue(const InstDesc &D, int epi, long long j, float y,
                                          float *out, double &dot) {
   const double *sc = D.sc;

@@ -92,13 +92,17 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   const long long nb = (L.n + kBlock - 1) / kBlock;
   const long long mb = (L.m + kBlock - 1) / kBlock;
   const long long mr = (L.m + 3) / 4;
-  L.nparts = (int)std::max({nb, mb, mr, 1LL});
+  // the strip-tiled blur passes write one partial per tile (64 x-columns x 64 along y or z)
+  const long long txn = (pb.nx + 63) / 64;
+  const long long ty_tiles = txn * ((pb.ny + 63) / 64) * pb.nz;
+  const long long tz_tiles = txn * ((pb.nz + 63) / 64) * pb.ny;
+  L.nparts = (int)std::max({nb, mb, mr, ty_tiles, tz_tiles, 1LL});
   L.desc = take(sizeof(InstDesc));
   L.descptr = take(sizeof(void *));
   L.sc = take(SC_COUNT * sizeof(double));
   L.diag = take((size_t)(pb.outer + 1) * DG_COUNT * sizeof(double));
   L.part = take((size_t)L.nparts * sizeof(double));
-  L.cfac = take((size_t)L.nc * L.nc * sizeof(double));
+  L.cfac = take((size_t)3 * L.nc * L.nc * sizeof(double));   // factor, L^{-1}, A^{-1}
   const size_t vb = (size_t)L.n * sizeof(float);
   L.f = take(vb);
   L.p = take(vb);
@@ -165,7 +169,11 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
   for (int i = 0; i < na; ++i) {
     const bool last = (i == na - 1);
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
-    np = launch_blur_pass(st, bv.d_descs, bv.B, H.n, axes[i], cur, dst, adj, last ? epi : EPI_STORE);
+    const int e = last ? epi : EPI_STORE;
+    if (axes[i] == 0)
+      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, cur, dst, adj, e);
+    else
+      np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e);
     cur = dst;
   }
   return np;
@@ -209,6 +217,7 @@ static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
 // V-cycle: v = B p; returns the partial count of the alpha^2 = v.p reduction
 // ---------------------------------------------------------------------------------
 static int other(int s) { return s == LB_X ? LB_T : LB_X; }
+static int other_d(int s) { return s == LB_T ? LB_S : LB_T; }
 
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
@@ -216,66 +225,87 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const int L = H.levels;
   InstDesc *const *d = bv.d_descs;
   const int B = bv.B;
+  const int nchild = (H.nz > 1) ? 8 : 4;
   if (L == 1) {
     launch_coarse_solve(st, d, B);   // exact M^{-1} on a single grid
     return launch_dot_vp(st, d, B, H.n);
   }
   int np = 0;
+  const int nu = H.nu_pre;
   if (H.smoother == PLSQR_SMOOTH_JACOBI) {
-    const int nsw = H.nu_pre + H.nu_post;
+    // the first two pre-sweeps run as one kernel; the prolongation runs inside the first
+    // post-sweep; every sweep writes the other of the (x, t) pair, ending in x
+    const int pre_writes = (nu >= 2) ? nu - 1 : 1;
+    const int first_dst = ((pre_writes + nu) % 2) ? LB_X : LB_T;
     int cur_l[kMaxLevels];
     for (int l = 0; l < L - 1; ++l) {
-      int cur = -1;
-      for (int s = 0; s < H.nu_pre; ++s) {
-        const int dst = (s == 0) ? ((nsw % 2) ? LB_X : LB_T) : other(cur);
-        launch_jacobi(st, d, B, l, Ly.ln[l], s == 0, cur < 0 ? LB_X : cur, dst, 0);
-        cur = dst;
+      int cur;
+      if (nu >= 2) {
+        launch_jacobi_first2(st, d, B, l, Ly.ln[l], first_dst, 0);
+        cur = first_dst;
+        for (int s = 2; s < nu; ++s) {
+          launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, other(cur), 0);
+          cur = other(cur);
+        }
+      } else {
+        launch_jacobi(st, d, B, l, Ly.ln[l], 1, LB_X, first_dst, 0);
+        cur = first_dst;
       }
       cur_l[l] = cur;
-      launch_restrict(st, d, B, l, Ly.ln[l + 1], cur, 0);
+      launch_restrict_fine(st, d, B, l, Ly.ln[l + 1], nchild, cur, 0);
     }
     launch_coarse_solve(st, d, B);
     for (int l = L - 2; l >= 0; --l) {
       int cur = cur_l[l];
-      launch_prolong(st, d, B, l, Ly.ln[l], cur);
-      for (int s = 0; s < H.nu_post; ++s) {
-        const int dst = other(cur);
-        const bool last = (s == H.nu_post - 1);
-        const int r = launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, dst, (l == 0 && last) ? 1 : 0);
+      const bool last0 = (nu == 1);
+      int r = launch_jacobi_prolong(st, d, B, l, Ly.ln[l], cur, other(cur), (l == 0 && last0) ? 1 : 0);
+      if (l == 0 && last0) np = r;
+      cur = other(cur);
+      for (int s = 1; s < nu; ++s) {
+        const bool last = (s == nu - 1);
+        r = launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, other(cur), (l == 0 && last) ? 1 : 0);
         if (l == 0 && last) np = r;
-        cur = dst;
+        cur = other(cur);
       }
     }
   } else {
-    const int m = H.cheb_degree, nu = H.nu_pre;
+    const int m = H.cheb_degree;
     for (int l = 0; l < L - 1; ++l) {
       for (int a = 0; a < nu; ++a) {
-        const bool zero = (a == 0);
-        launch_cheb_start(st, d, B, l, Ly.ln[l], zero ? 1 : 0, LB_T);
         int dcur = LB_T;
-        for (int k = 0; k < m; ++k) {
+        int k0 = 0;
+        if (a == 0) {
+          // start and first step from x = 0 in one kernel
+          const bool last = (m == 1);
+          launch_cheb_first(st, d, B, l, Ly.ln[l], last ? 1 : 0, LB_T);
+          k0 = 1;
+        } else {
+          launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
+        }
+        for (int k = k0; k < m; ++k) {
           const bool last = (k == m - 1);
           const bool upd = !last || (a == nu - 1);
-          const int dn = (dcur == LB_T) ? LB_S : LB_T;
-          launch_cheb_step(st, d, B, l, Ly.ln[l], (zero && k == 0) ? 1 : 0, upd ? 1 : 0,
-                           last ? 1 : 0, dcur, dn, k, 0);
+          const int dn = other_d(dcur);
+          launch_cheb_step(st, d, B, l, Ly.ln[l], 0, upd ? 1 : 0, last ? 1 : 0, dcur, dn, k, 0, 0);
           dcur = dn;
         }
       }
-      launch_restrict(st, d, B, l, Ly.ln[l + 1], LB_X, 1);
+      launch_restrict_fine(st, d, B, l, Ly.ln[l + 1], nchild, LB_X, 1);
     }
     launch_coarse_solve(st, d, B);
     for (int l = L - 2; l >= 0; --l) {
-      launch_prolong(st, d, B, l, Ly.ln[l], LB_X);
       for (int a = 0; a < nu; ++a) {
-        launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
+        if (a == 0)
+          launch_cheb_start_prolong(st, d, B, l, Ly.ln[l], LB_T);
+        else
+          launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
         int dcur = LB_T;
         for (int k = 0; k < m; ++k) {
           const bool last = (k == m - 1);
-          const int dn = (dcur == LB_T) ? LB_S : LB_T;
+          const int dn = other_d(dcur);
           const bool want = (l == 0 && a == nu - 1 && last);
           const int r = launch_cheb_step(st, d, B, l, Ly.ln[l], 0, last ? 0 : 1, last ? 1 : 0, dcur,
-                                         dn, k, want ? 1 : 0);
+                                         dn, k, want ? 1 : 0, (a == 0 && k == 0) ? 1 : 0);
           if (want) np = r;
           dcur = dn;
         }

@@ -173,32 +173,44 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
     D.sc[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
     D.sc[SC_STOP] = 1.0;
   }
+  // Explicit inverse A^{-1} = L^{-T} L^{-1}, so that each V-cycle's coarsest solve is one
+  // parallel matrix-vector product. L^{-1} overwrites the strictly-upper part's mirror:
+  // it is formed column by column (one thread per column) into the second n x n block.
+  double *__restrict__ Li = A + (long long)n * n;
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+    for (int i = 0; i < j; ++i) Li[(long long)i * n + j] = 0.0;
+    for (int i = j; i < n; ++i) {
+      double sacc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) sacc -= A[(long long)i * n + k] * Li[(long long)k * n + j];
+      Li[(long long)i * n + j] = sacc / A[(long long)i * n + i];
+    }
+  }
+  __syncthreads();
+  // A^{-1}[i][j] = sum_{k >= max(i,j)} Li[k][i] Li[k][j], stored over the factor block
+  for (long long q = threadIdx.x; q < (long long)n * n; q += kBlock) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    const int k0 = i > j ? i : j;
+    double sacc = 0.0;
+    for (int k = k0; k < n; ++k) sacc += Li[(long long)k * n + i] * Li[(long long)k * n + j];
+    A[(long long)n * n * 2 + q] = sacc;
+  }
 }
 
-// Coarsest solve: x = L^{-T} L^{-1} b in FP64. One block per instance.
+// Coarsest solve: x = A_c^{-1} b with the FP64 inverse formed at setup (symmetric, so
+// thread i reads column i: coalesced). One block per instance.
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const LevelDesc &L = D.lv[D.levels - 1];
   const int n = (int)L.n;
-  const double *__restrict__ A = D.cfac;
-  __shared__ double y[PLSQR_MAX_COARSE];
-  for (int i = threadIdx.x; i < n; i += kBlock) y[i] = (double)L.b[i];
+  const double *__restrict__ Ai = D.cfac + (long long)n * n * 2;
+  __shared__ double bs[PLSQR_MAX_COARSE];
+  for (int i = threadIdx.x; i < n; i += kBlock) bs[i] = (double)L.b[i];
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double yk = y[k] / A[(long long)k * n + k];
-    __syncthreads();
-    if (threadIdx.x == 0) y[k] = yk;
-    for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) y[i] -= A[(long long)i * n + k] * yk;
-    __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += Ai[(long long)j * n + i] * bs[j];
+    L.x[i] = (float)acc;
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const double yk = y[k] / A[(long long)k * n + k];
-    __syncthreads();
-    if (threadIdx.x == 0) y[k] = yk;
-    for (int i = threadIdx.x; i < k; i += kBlock) y[i] -= A[(long long)k * n + i] * yk;
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < n; i += kBlock) L.x[i] = (float)y[i];
 }
 
 // ------------------------------------------------------------------------------------
@@ -233,6 +245,131 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l
   }
 }
 
+// First two damped Jacobi sweeps from x = 0 in one pass: x1 = omega D^{-1} b is formed on
+// the fly (also at the neighbours), dst = x1 + omega D^{-1} (b - A x1).
+__global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs, int l,
+                                                         int dst_sel, int want_dot) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < L.n) {
+    const float *__restrict__ b = L.b;
+    const float *__restrict__ dinv = L.dinv;
+    const float om = D.omega;
+    const Coord c = coord_of(j, L.nx, L.ny);
+    auto x1 = [&](long long q) { return om * dinv[q] * b[q]; };
+    const float ax = stencil_f(D, l, j, c, x1);
+    const float xn = x1(j) + om * dinv[j] * (b[j] - ax);
+    lvbuf(L, dst_sel)[j] = xn;
+    if (want_dot) dot = (double)xn * (double)b[j];
+  }
+  if (want_dot) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// Prolongation fused into the first post-smoothing Jacobi sweep: x' = x + P e (formed on
+// the fly at the neighbours), dst = x' + omega D^{-1} (b - A x').
+__global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *descs, int l,
+                                                          int src_sel, int dst_sel, int want_dot) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < L.n) {
+    const float *__restrict__ x = lvbuf(L, src_sel);
+    const float *__restrict__ e = Cl.x;
+    const Coord c = coord_of(j, L.nx, L.ny);
+    auto xp = [&](long long q) {
+      const Coord cq = coord_of(q, L.nx, L.ny);
+      return x[q] + e[parent_of(L, Cl, cq)];
+    };
+    const float ax = stencil_f(D, l, j, c, xp);
+    const float xn = xp(j) + D.omega * L.dinv[j] * (L.b[j] - ax);
+    lvbuf(L, dst_sel)[j] = xn;
+    if (want_dot) dot = (double)xn * (double)L.b[j];
+  }
+  if (want_dot) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// Chebyshev pre-smoothing start fused with its first step (x = 0): d0 = D^{-1} b / theta on
+// the fly, x1 = d0, r1 = b - A d0, and (unless the polynomial has degree 1) d1 -> dn_sel.
+__global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, int l, int last,
+                                                      int dn_sel) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= L.n) return;
+  const double rho0 = 1.0 / D.cheb_sigma;
+  const double rho1 = 1.0 / (2.0 * D.cheb_sigma - rho0);
+  const float c_dd = (float)(rho1 * rho0), c_dr = (float)(2.0 * rho1 / D.cheb_delta);
+  const float ith = (float)(1.0 / D.cheb_theta);
+  const float *__restrict__ b = L.b;
+  const float *__restrict__ dinv = L.dinv;
+  const Coord c = coord_of(j, L.nx, L.ny);
+  auto d0 = [&](long long q) { return ith * dinv[q] * b[q]; };
+  const float dj = d0(j);
+  L.x[j] = dj;
+  const float r = b[j] - stencil_f(D, l, j, c, d0);
+  L.r[j] = r;
+  if (!last) lvbuf(L, dn_sel)[j] = c_dd * dj + c_dr * dinv[j] * r;
+}
+
+// Chebyshev post-smoothing start fused with the prolongation: r = b - A x' with
+// x' = x + P e formed on the fly (x itself is left alone: other blocks still read it; the
+// first step adds P e pointwise), d = D^{-1} r / theta -> d_sel.
+__global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *descs, int l,
+                                                              int d_sel) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &L = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= L.n) return;
+  const float *__restrict__ x = L.x;
+  const float *__restrict__ e = Cl.x;
+  const Coord c = coord_of(j, L.nx, L.ny);
+  auto xp = [&](long long q) {
+    const Coord cq = coord_of(q, L.nx, L.ny);
+    return x[q] + e[parent_of(L, Cl, cq)];
+  };
+  const float r = L.b[j] - stencil_f(D, l, j, c, xp);
+  L.r[j] = r;
+  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * L.dinv[j] * r;
+}
+
+// Restriction of the residual with one thread per fine cell: the 2^d children of a coarse
+// cell sit in consecutive lanes and are summed with shuffles.
+// use_r: sum the stored residual r_l; otherwise form b - A_l x.
+__global__ void __launch_bounds__(kBlock) k_restrict_fine(InstDesc *const *descs, int l, int x_sel,
+                                                         int use_r) {
+  const InstDesc &D = inst(descs);
+  const LevelDesc &F = D.lv[l];
+  const LevelDesc &Cl = D.lv[l + 1];
+  const int nchild = (F.nz > 1) ? 8 : 4;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long J = t / nchild;
+  const int ch = (int)(t % nchild);
+  float v = 0.f;
+  if (J < Cl.n) {
+    const Coord cc = coord_of(J, Cl.nx, Cl.ny);
+    Coord fc;
+    fc.x = 2 * cc.x + (ch & 1);
+    fc.y = 2 * cc.y + ((ch >> 1) & 1);
+    fc.z = (F.nz > 1) ? 2 * cc.z + (ch >> 2) : 0;
+    const long long j = fc.x + (long long)F.nx * (fc.y + (long long)F.ny * fc.z);
+    v = use_r ? F.r[j] : F.b[j] - stencil(D, l, lvbuf(F, x_sel), j, fc);
+  }
+  // sum over the nchild consecutive lanes (groups never straddle a wave: 64 % 8 == 0)
+  for (int o = 1; o < nchild; o <<= 1) v += __shfl_xor(v, o, 64);
+  if (J < Cl.n && ch == 0) Cl.b[J] = v;
+}
+
 // Chebyshev start: r = b - A x (or r = b when x = 0), d = D^{-1} r / theta -> d buffer.
 __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, int l, int zero_x,
                                                       int d_sel) {
@@ -254,7 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, i
 // With want_dot, partial of sum x_j b_j after the update.
 __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, int l, int set_x,
                                                      int update_r, int last, int d_sel, int dn_sel,
-                                                     int step, int want_dot) {
+                                                     int step, int want_dot, int add_prolong) {
   const InstDesc &D = inst(descs);
   const LevelDesc &L = D.lv[l];
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -267,7 +404,12 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
   if (j < L.n) {
     const float *__restrict__ d = lvbuf(L, d_sel);
     const float dj = d[j];
-    const float xn = set_x ? dj : L.x[j] + dj;
+    float xo = set_x ? 0.f : L.x[j];
+    if (add_prolong) {      // pending coarse correction x += P e (pointwise)
+      const LevelDesc &Cl = D.lv[l + 1];
+      xo += Cl.x[parent_of(L, Cl, coord_of(j, L.nx, L.ny))];
+    }
+    const float xn = xo + dj;
     L.x[j] = xn;
     if (want_dot) dot = (double)xn * (double)L.b[j];
     if (update_r) {
@@ -347,6 +489,100 @@ __global__ void __launch_bounds__(kBlock) k_blur_pass(InstDesc *const *descs, in
       y += w * src[j + k * stride];
     }
     epilogue(D, epi, j, y, vec_of(D, dst_sel), dot);
+  }
+  if (epi == EPI_FWD || epi == EPI_RESID) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// LDS-tiled blur passes. Out-of-grid samples are loaded as zeros, which is exactly the
+// zero boundary of the operator, so the tap loops need no bounds tests.
+//
+// x pass: a block owns 256 consecutive voxels in linear order (rows of length nx back to
+// back) and stages [j0 - r, j0 + 256 + r) in LDS; a neighbour j + k belongs to the same row
+// iff 0 <= x + k < nx, which the tap range below enforces.
+__global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int src_sel, int dst_sel,
+                                                  int adj, int epi) {
+  const InstDesc &D = inst(descs);
+  __shared__ float tile[kBlock + 2 * PLSQR_MAX_RADIUS];
+  __shared__ float w[kMaxTaps];
+  const int r = D.radius;
+  const long long n = D.n;
+  const long long j0 = (long long)blockIdx.x * kBlock;
+  double dot = 0.0;
+  if (j0 < n) {
+    const float *__restrict__ src = vec_of(D, src_sel);
+    if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
+    for (int i = threadIdx.x; i < kBlock + 2 * r; i += kBlock) {
+      const long long q = j0 - r + i;
+      tile[i] = (q >= 0 && q < n) ? src[q] : 0.f;
+    }
+    __syncthreads();
+    const long long j = j0 + threadIdx.x;
+    if (j < n) {
+      const int x = (int)(j % D.nx);
+      const int klo = -min(r, x), khi = min(r, D.nx - 1 - x);
+      float y = 0.f;
+      for (int k = klo; k <= khi; ++k) y += w[r + k] * tile[threadIdx.x + r + k];
+      epilogue(D, epi, j, y, vec_of(D, dst_sel), dot);
+    }
+  } else {
+    __syncthreads();
+  }
+  if (epi == EPI_FWD || epi == EPI_RESID) {
+    dot = block_sum(dot);
+    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  }
+}
+
+// y or z pass: a block of 64 x 4 threads owns a strip of 64 x-columns and 64 outputs along
+// the axis (other coordinate fixed); it stages (64 + 2r) planes of the strip in LDS.
+constexpr int kStripX = 64, kStripA = 64;
+__global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, int axis,
+                                                      int src_sel, int dst_sel, int adj, int epi) {
+  const InstDesc &D = inst(descs);
+  __shared__ float tile[kStripA + 2 * PLSQR_MAX_RADIUS][kStripX];
+  __shared__ float w[kMaxTaps];
+  const int r = D.radius;
+  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const int na = (axis == 1) ? ny : nz;        // extent along the pass
+  const int no = (axis == 1) ? nz : ny;        // the remaining coordinate
+  const long long sa = (axis == 1) ? (long long)nx : (long long)nx * ny;
+  const long long so = (axis == 1) ? (long long)nx * ny : (long long)nx;
+  const int tx_n = (nx + kStripX - 1) / kStripX, ta_n = (na + kStripA - 1) / kStripA;
+  const long long tiles = (long long)tx_n * ta_n * no;
+  const long long t = blockIdx.x;
+  const int lx = threadIdx.x & (kStripX - 1), la = threadIdx.x / kStripX;   // 64 x 4
+  double dot = 0.0;
+  if (t < tiles) {
+    const int tx = (int)(t % tx_n);
+    const long long rest = t / tx_n;
+    const int ta = (int)(rest % ta_n);
+    const int o = (int)(rest / ta_n);
+    const int x = tx * kStripX + lx;
+    const int a0 = ta * kStripA;
+    const float *__restrict__ src = vec_of(D, src_sel);
+    if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
+    const long long base = (long long)x + (long long)o * so;
+    for (int i = la; i < kStripA + 2 * r; i += kBlock / kStripX) {
+      const int a = a0 - r + i;
+      tile[i][lx] = (x < nx && a >= 0 && a < na) ? src[base + (long long)a * sa] : 0.f;
+    }
+    __syncthreads();
+    if (x < nx) {
+      for (int q = la; q < kStripA; q += kBlock / kStripX) {
+        const int a = a0 + q;
+        if (a >= na) break;
+        float y = 0.f;
+        for (int k = 0; k <= 2 * r; ++k) y += w[k] * tile[q + k][lx];
+        double dq = 0.0;
+        epilogue(D, epi, base + (long long)a * sa, y, vec_of(D, dst_sel), dq);
+        dot += dq;
+      }
+    }
+  } else {
+    __syncthreads();
   }
   if (epi == EPI_FWD || epi == EPI_RESID) {
     dot = block_sum(dot);
@@ -668,10 +904,36 @@ void launch_cheb_start(hipStream_t st, InstDesc *const *d, int B, int l, long lo
   LAUNCH(k_cheb_start, blocks_for(n_l), B, d, l, zero_x, d_sel);
 }
 int launch_cheb_step(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
-                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot) {
+                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot,
+                     int add_prolong) {
   const unsigned g = blocks_for(n_l);
-  LAUNCH(k_cheb_step, g, B, d, l, set_x, update_r, last, d_sel, dn_sel, step, want_dot);
+  LAUNCH(k_cheb_step, g, B, d, l, set_x, update_r, last, d_sel, dn_sel, step, want_dot,
+         add_prolong);
   return (int)g;
+}
+int launch_jacobi_first2(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int dst,
+                         int want_dot) {
+  const unsigned g = blocks_for(n_l);
+  LAUNCH(k_jacobi_first2, g, B, d, l, dst, want_dot);
+  return (int)g;
+}
+int launch_jacobi_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int src,
+                          int dst, int want_dot) {
+  const unsigned g = blocks_for(n_l);
+  LAUNCH(k_jacobi_prolong, g, B, d, l, src, dst, want_dot);
+  return (int)g;
+}
+void launch_cheb_first(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int last,
+                       int dn_sel) {
+  LAUNCH(k_cheb_first, blocks_for(n_l), B, d, l, last, dn_sel);
+}
+void launch_cheb_start_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l,
+                               int d_sel) {
+  LAUNCH(k_cheb_start_prolong, blocks_for(n_l), B, d, l, d_sel);
+}
+void launch_restrict_fine(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
+                          int nchild, int x_sel, int use_r) {
+  LAUNCH(k_restrict_fine, blocks_for(n_coarse * nchild), B, d, l, x_sel, use_r);
 }
 void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
                      int x_sel, int use_r) {
@@ -685,6 +947,19 @@ int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int
   const unsigned g = blocks_for(n);
   LAUNCH(k_blur_pass, g, B, d, axis, src, dst, adj, epi);
   return (int)g;
+}
+int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
+                  int epi) {
+  const unsigned g = blocks_for(n);
+  LAUNCH(k_blur_x, g, B, d, src, dst, adj, epi);
+  return (int)g;
+}
+int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
+                      int src, int dst, int adj, int epi) {
+  const int na = (axis == 1) ? ny : nz, no = (axis == 1) ? nz : ny;
+  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((na + kStripA - 1) / kStripA) * no;
+  LAUNCH(k_blur_strip, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
+  return (int)tiles;
 }
 constexpr int kGemvRows = 4;
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi) {

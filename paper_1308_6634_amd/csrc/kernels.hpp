@@ -24,10 +24,25 @@ int launch_jacobi(hipStream_t st, InstDesc *const *d, int B, int l, long long n_
 void launch_cheb_start(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int zero_x,
                        int d_sel);
 int launch_cheb_step(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
-                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot);
+                     int update_r, int last, int d_sel, int dn_sel, int step, int want_dot,
+                     int add_prolong = 0);
 void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
                      int x_sel, int use_r);
 void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel);
+int launch_jacobi_first2(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int dst,
+                         int want_dot);
+int launch_jacobi_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int src,
+                          int dst, int want_dot);
+void launch_cheb_first(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int last,
+                       int dn_sel);
+void launch_cheb_start_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l,
+                               int d_sel);
+void launch_restrict_fine(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
+                          int nchild, int x_sel, int use_r);
+int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
+                  int epi);
+int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
+                      int src, int dst, int adj, int epi);
 int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
                      int dst, int adj, int epi);
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi);

@@ -65,7 +65,7 @@ struct InstDesc {
   float *out_f;                      // caller's output
   double *sc;                        // scalar block (SC_COUNT)
   double *part;                      // per-block reduction partials
-  double *cfac;                      // coarsest-level dense Cholesky factor (nc x nc, lower)
+  double *cfac;                      // coarsest level: Cholesky factor, L^{-1}, A^{-1} (3 x nc x nc)
   double *diag;                      // (outer + 1) x DG_COUNT records
   int nc, colchunks;
   LevelDesc lv[kMaxLevels];
