@@ -88,12 +88,15 @@ __device__ __forceinline__ double penalty_of(int reg, double t, double T) {
 }
 
 struct Coord { int x, y, z; };
+// Grid coordinates of linear index j (x fastest). Grids hold < 2^31 cells (checked at
+// submission), so 32-bit unsigned arithmetic suffices (64-bit division is emulated).
 __device__ __forceinline__ Coord coord_of(long long j, int nx, int ny) {
+  const unsigned u = (unsigned)j, ux = (unsigned)nx, uy = (unsigned)ny;
+  const unsigned q = u / ux;
   Coord c;
-  c.x = (int)(j % nx);
-  long long q = j / nx;
-  c.y = (int)(q % ny);
-  c.z = (int)(q / ny);
+  c.x = (int)(u - q * ux);
+  c.y = (int)(q % uy);
+  c.z = (int)(q / uy);
   return c;
 }
 
@@ -136,25 +139,32 @@ __device__ __forceinline__ float stencil_f(const InstDesc &D, int l, long long j
   const LevelDesc &L = D.lv[l];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const long long sy = nx, sz = (long long)nx * ny;
-  const float xj = X(j);
+  const float xj = X(j, c);
   float acc = (float)L.eps * xj;
+  auto nb = [&](int dx, int dy, int dz) {
+    Coord q = c;
+    q.x += dx;
+    q.y += dy;
+    q.z += dz;
+    return q;
+  };
   if (l == 0) {
     const float *__restrict__ k = D.kappa;
     const float kj = k[j];
-    if (c.x + 1 < nx) acc += kj * (xj - X(j + 1));
-    if (c.x > 0) acc += k[j - 1] * (xj - X(j - 1));
-    if (c.y + 1 < ny) acc += kj * (xj - X(j + sy));
-    if (c.y > 0) acc += k[j - sy] * (xj - X(j - sy));
-    if (c.z + 1 < nz) acc += kj * (xj - X(j + sz));
-    if (c.z > 0) acc += k[j - sz] * (xj - X(j - sz));
+    if (c.x + 1 < nx) acc += kj * (xj - X(j + 1, nb(1, 0, 0)));
+    if (c.x > 0) acc += k[j - 1] * (xj - X(j - 1, nb(-1, 0, 0)));
+    if (c.y + 1 < ny) acc += kj * (xj - X(j + sy, nb(0, 1, 0)));
+    if (c.y > 0) acc += k[j - sy] * (xj - X(j - sy, nb(0, -1, 0)));
+    if (c.z + 1 < nz) acc += kj * (xj - X(j + sz, nb(0, 0, 1)));
+    if (c.z > 0) acc += k[j - sz] * (xj - X(j - sz, nb(0, 0, -1)));
   } else {
-    if (c.x + 1 < nx) acc += L.wx[j] * (xj - X(j + 1));
-    if (c.x > 0) acc += L.wx[j - 1] * (xj - X(j - 1));
-    if (c.y + 1 < ny) acc += L.wy[j] * (xj - X(j + sy));
-    if (c.y > 0) acc += L.wy[j - sy] * (xj - X(j - sy));
+    if (c.x + 1 < nx) acc += L.wx[j] * (xj - X(j + 1, nb(1, 0, 0)));
+    if (c.x > 0) acc += L.wx[j - 1] * (xj - X(j - 1, nb(-1, 0, 0)));
+    if (c.y + 1 < ny) acc += L.wy[j] * (xj - X(j + sy, nb(0, 1, 0)));
+    if (c.y > 0) acc += L.wy[j - sy] * (xj - X(j - sy, nb(0, -1, 0)));
     if (nz > 1) {
-      if (c.z + 1 < nz) acc += L.wz[j] * (xj - X(j + sz));
-      if (c.z > 0) acc += L.wz[j - sz] * (xj - X(j - sz));
+      if (c.z + 1 < nz) acc += L.wz[j] * (xj - X(j + sz, nb(0, 0, 1)));
+      if (c.z > 0) acc += L.wz[j - sz] * (xj - X(j - sz, nb(0, 0, -1)));
     }
   }
   return acc;

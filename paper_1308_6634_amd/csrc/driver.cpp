@@ -24,6 +24,7 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   };
   if (!op) return bad("unknown operator id");
   if (pb.nx < 1 || pb.ny < 1 || pb.nz < 1) return bad("grid extents must be >= 1");
+  if ((long long)pb.nx * pb.ny * pb.nz >= (1LL << 31)) return bad("grids hold fewer than 2^31 cells");
   if (pb.nx != op->op.nx || pb.ny != op->op.ny || pb.nz != op->op.nz)
     return bad("problem grid differs from the operator's grid");
   if (pb.reg < PLSQR_REG_TIKHONOV || pb.reg > PLSQR_REG_PM_EXP) return bad("unknown regulariser");
@@ -93,9 +94,9 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   const long long mb = (L.m + kBlock - 1) / kBlock;
   const long long mr = (L.m + 3) / 4;
   // the strip-tiled blur passes write one partial per tile (64 x-columns x 64 along y or z)
-  const long long txn = (pb.nx + 63) / 64;
-  const long long ty_tiles = txn * ((pb.ny + 63) / 64) * pb.nz;
-  const long long tz_tiles = txn * ((pb.nz + 63) / 64) * pb.ny;
+  const long long txn = (pb.nx + 63) / 64;           // strip tiles: 64 x-columns x 32 deep
+  const long long ty_tiles = txn * ((pb.ny + 31) / 32) * pb.nz;
+  const long long tz_tiles = txn * ((pb.nz + 31) / 32) * pb.ny;
   L.nparts = (int)std::max({nb, mb, mr, ty_tiles, tz_tiles, 1LL});
   L.desc = take(sizeof(InstDesc));
   L.descptr = take(sizeof(void *));

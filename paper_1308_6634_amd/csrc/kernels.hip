@@ -258,9 +258,9 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs
     const float *__restrict__ dinv = L.dinv;
     const float om = D.omega;
     const Coord c = coord_of(j, L.nx, L.ny);
-    auto x1 = [&](long long q) { return om * dinv[q] * b[q]; };
+    auto x1 = [&](long long q, Coord) { return om * dinv[q] * b[q]; };
     const float ax = stencil_f(D, l, j, c, x1);
-    const float xn = x1(j) + om * dinv[j] * (b[j] - ax);
+    const float xn = x1(j, c) + om * dinv[j] * (b[j] - ax);
     lvbuf(L, dst_sel)[j] = xn;
     if (want_dot) dot = (double)xn * (double)b[j];
   }
@@ -283,12 +283,9 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *desc
     const float *__restrict__ x = lvbuf(L, src_sel);
     const float *__restrict__ e = Cl.x;
     const Coord c = coord_of(j, L.nx, L.ny);
-    auto xp = [&](long long q) {
-      const Coord cq = coord_of(q, L.nx, L.ny);
-      return x[q] + e[parent_of(L, Cl, cq)];
-    };
+    auto xp = [&](long long q, Coord cq) { return x[q] + e[parent_of(L, Cl, cq)]; };
     const float ax = stencil_f(D, l, j, c, xp);
-    const float xn = xp(j) + D.omega * L.dinv[j] * (L.b[j] - ax);
+    const float xn = xp(j, c) + D.omega * L.dinv[j] * (L.b[j] - ax);
     lvbuf(L, dst_sel)[j] = xn;
     if (want_dot) dot = (double)xn * (double)L.b[j];
   }
@@ -313,8 +310,8 @@ __global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, i
   const float *__restrict__ b = L.b;
   const float *__restrict__ dinv = L.dinv;
   const Coord c = coord_of(j, L.nx, L.ny);
-  auto d0 = [&](long long q) { return ith * dinv[q] * b[q]; };
-  const float dj = d0(j);
+  auto d0 = [&](long long q, Coord) { return ith * dinv[q] * b[q]; };
+  const float dj = d0(j, c);
   L.x[j] = dj;
   const float r = b[j] - stencil_f(D, l, j, c, d0);
   L.r[j] = r;
@@ -334,10 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *
   const float *__restrict__ x = L.x;
   const float *__restrict__ e = Cl.x;
   const Coord c = coord_of(j, L.nx, L.ny);
-  auto xp = [&](long long q) {
-    const Coord cq = coord_of(q, L.nx, L.ny);
-    return x[q] + e[parent_of(L, Cl, cq)];
-  };
+  auto xp = [&](long long q, Coord cq) { return x[q] + e[parent_of(L, Cl, cq)]; };
   const float r = L.b[j] - stencil_f(D, l, j, c, xp);
   L.r[j] = r;
   lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * L.dinv[j] * r;
@@ -499,33 +493,49 @@ __global__ void __launch_bounds__(kBlock) k_blur_pass(InstDesc *const *descs, in
 // LDS-tiled blur passes. Out-of-grid samples are loaded as zeros, which is exactly the
 // zero boundary of the operator, so the tap loops need no bounds tests.
 //
-// x pass: a block owns 256 consecutive voxels in linear order (rows of length nx back to
-// back) and stages [j0 - r, j0 + 256 + r) in LDS; a neighbour j + k belongs to the same row
-// iff 0 <= x + k < nx, which the tap range below enforces.
+// x pass: a block owns kXTile consecutive voxels in linear order (rows of length nx back to
+// back), 4 per thread, and stages [j0 - r, j0 + kXTile + r) in LDS; a neighbour j + k belongs
+// to the same row iff 0 <= x + k < nx, which the tap range below enforces.
+constexpr int kXTile = 4 * kBlock;
 __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int src_sel, int dst_sel,
                                                   int adj, int epi) {
   const InstDesc &D = inst(descs);
-  __shared__ float tile[kBlock + 2 * PLSQR_MAX_RADIUS];
+  __shared__ float tile[kXTile + 2 * PLSQR_MAX_RADIUS];
   __shared__ float w[kMaxTaps];
   const int r = D.radius;
   const long long n = D.n;
-  const long long j0 = (long long)blockIdx.x * kBlock;
+  const long long j0 = (long long)blockIdx.x * kXTile;
   double dot = 0.0;
   if (j0 < n) {
     const float *__restrict__ src = vec_of(D, src_sel);
     if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-    for (int i = threadIdx.x; i < kBlock + 2 * r; i += kBlock) {
+    float v[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int i = threadIdx.x + u * kBlock;
       const long long q = j0 - r + i;
-      tile[i] = (q >= 0 && q < n) ? src[q] : 0.f;
+      v[u] = (i < kXTile + 2 * r && q >= 0 && q < n) ? src[q] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      if (i < kXTile + 2 * r) tile[i] = v[u];
     }
     __syncthreads();
-    const long long j = j0 + threadIdx.x;
-    if (j < n) {
-      const int x = (int)(j % D.nx);
-      const int klo = -min(r, x), khi = min(r, D.nx - 1 - x);
-      float y = 0.f;
-      for (int k = klo; k <= khi; ++k) y += w[r + k] * tile[threadIdx.x + r + k];
-      epilogue(D, epi, j, y, vec_of(D, dst_sel), dot);
+    float *dst = vec_of(D, dst_sel);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      const long long j = j0 + i;
+      if (j < n) {
+        const int x = (int)((unsigned)j % (unsigned)D.nx);
+        const int klo = -min(r, x), khi = min(r, D.nx - 1 - x);
+        float y = 0.f;
+        for (int k = klo; k <= khi; ++k) y += w[r + k] * tile[i + r + k];
+        double dq = 0.0;
+        epilogue(D, epi, j, y, dst, dq);
+        dot += dq;
+      }
     }
   } else {
     __syncthreads();
@@ -538,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
 
 // y or z pass: a block of 64 x 4 threads owns a strip of 64 x-columns and 64 outputs along
 // the axis (other coordinate fixed); it stages (64 + 2r) planes of the strip in LDS.
-constexpr int kStripX = 64, kStripA = 64;
+constexpr int kStripX = 64, kStripA = 32;
 __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, int axis,
                                                       int src_sel, int dst_sel, int adj, int epi) {
   const InstDesc &D = inst(descs);
@@ -565,9 +575,22 @@ __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, i
     const float *__restrict__ src = vec_of(D, src_sel);
     if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
     const long long base = (long long)x + (long long)o * so;
-    for (int i = la; i < kStripA + 2 * r; i += kBlock / kStripX) {
-      const int a = a0 - r + i;
-      tile[i][lx] = (x < nx && a >= 0 && a < na) ? src[base + (long long)a * sa] : 0.f;
+    // fill the tile: 8 independent loads in flight per thread before the LDS stores
+    constexpr int kStep = kBlock / kStripX;   // 4 planes per pass of the block
+    const int rows = kStripA + 2 * r;
+    for (int i0 = la; i0 < rows; i0 += 8 * kStep) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * kStep;
+        const int a = a0 - r + i;
+        v[u] = (i < rows && x < nx && a >= 0 && a < na) ? src[base + (long long)a * sa] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * kStep;
+        if (i < rows) tile[i][lx] = v[u];
+      }
     }
     __syncthreads();
     if (x < nx) {
@@ -827,17 +850,31 @@ __global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
   D.w[j] = stop ? 0.f : (float)D.sc[SC_SV] * D.v[j];
 }
 
-// f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step).
+// f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step); 4 voxels
+// per thread when n is a multiple of 4.
 __global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
-  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= D.n) return;
   const double *sc = D.sc;
   if (sc[SC_STOP] != 0.0) return;
   const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
-  const float wj = D.w[j];
-  D.f[j] += cf * wj;
-  D.w[j] = sv * D.v[j] - cw * wj;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if ((D.n & 3) == 0) {
+    if (t * 4 >= D.n) return;
+    float4 wv = reinterpret_cast<const float4 *>(D.w)[t];
+    float4 fv = reinterpret_cast<const float4 *>(D.f)[t];
+    const float4 vv = reinterpret_cast<const float4 *>(D.v)[t];
+    fv.x += cf * wv.x; fv.y += cf * wv.y; fv.z += cf * wv.z; fv.w += cf * wv.w;
+    wv.x = sv * vv.x - cw * wv.x; wv.y = sv * vv.y - cw * wv.y;
+    wv.z = sv * vv.z - cw * wv.z; wv.w = sv * vv.w - cw * wv.w;
+    reinterpret_cast<float4 *>(D.f)[t] = fv;
+    reinterpret_cast<float4 *>(D.w)[t] = wv;
+  } else {
+    for (long long j = t * 4; j < t * 4 + 4 && j < D.n; ++j) {
+      const float wj = D.w[j];
+      D.f[j] += cf * wj;
+      D.w[j] = sv * D.v[j] - cw * wj;
+    }
+  }
 }
 
 // partial of v . p (alpha^2 when the V-cycle is a single exact solve)
@@ -950,7 +987,7 @@ int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int
 }
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
                   int epi) {
-  const unsigned g = blocks_for(n);
+  const unsigned g = (unsigned)((n + kXTile - 1) / kXTile);
   LAUNCH(k_blur_x, g, B, d, src, dst, adj, epi);
   return (int)g;
 }
@@ -986,7 +1023,7 @@ void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n) {
   LAUNCH(k_init_wf, blocks_for(n), B, d);
 }
 void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n) {
-  LAUNCH(k_update_fw, blocks_for(n), B, d);
+  LAUNCH(k_update_fw, blocks_for((n + 3) / 4), B, d);
 }
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n) {
   const unsigned g = blocks_for(n);
