@@ -71,8 +71,10 @@ enum {
 
 /* problem flags */
 enum {
-  PLSQR_FLAG_TIME_PRODUCTS = 1u << 0  /* time every launch of the forward/adjoint product
+  PLSQR_FLAG_TIME_PRODUCTS = 1u << 0, /* time every launch of the forward/adjoint product
                                          kernels with HIP events; totals in plsqr_result */
+  PLSQR_FLAG_NO_GRAPHS = 1u << 1      /* launch every kernel eagerly instead of replaying the
+                                         inner iteration as a captured HIP graph */
 };
 
 #define PLSQR_MAX_LEVELS 12

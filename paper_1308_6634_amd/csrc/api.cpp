@@ -223,6 +223,7 @@ void release_group(plsqr_engine *eng, Group &G) {
   }
   if (G.gws) eng->pool.put(G.gws, G.gws_bytes);
   G.gws = nullptr;
+  G.graphs.reset();
   if (G.pinned) hipHostFree(G.pinned);
   G.pinned = nullptr;
   if (G.state == Group::RUNNING) eng->used -= G.bytes;
@@ -280,7 +281,8 @@ int start_group_impl(plsqr_engine *eng, Group &G) {
                          eng->stream));
   BatchView bv{G.d_descs, B, &r0.host, &r0.lay, G.timed ? &G.fwd_events : nullptr,
                G.timed ? &G.adj_events : nullptr, G.use_gemm ? &G.gemm : nullptr};
-  enqueue_whole_solve(eng->stream, bv, r0.pb.outer, r0.pb.inner);
+  if (!(r0.pb.flags & PLSQR_FLAG_NO_GRAPHS)) G.graphs = std::make_unique<GraphCache>();
+  enqueue_whole_solve(eng->stream, bv, r0.pb.outer, r0.pb.inner, G.graphs.get());
   HIP_TRY(hipGetLastError());
   for (int b = 0; b < B; ++b) {
     Request &r = *eng->reqs[G.members[b]];

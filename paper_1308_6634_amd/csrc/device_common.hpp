@@ -131,6 +131,34 @@ __device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *
   return acc;
 }
 
+// (A_l x)_j together with 1/diag(A_l)_j. On level 0 the diagonal eps + sum of the face
+// weights is assembled from the kappa values the stencil loads anyway (same order of
+// additions as the stored level-0 diagonal), so the level-0 smoother kernels need not read
+// a diagonal array; coarser levels read their stored 1/diag.
+__device__ __forceinline__ float stencil_dinv(const InstDesc &D, int l, const float *__restrict__ x,
+                                              long long j, Coord c, float &dinv_j) {
+  if (l != 0) {
+    dinv_j = D.lv[l].dinv[j];
+    return stencil(D, l, x, j, c);
+  }
+  const LevelDesc &L = D.lv[0];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const float *__restrict__ k = D.kappa;
+  const float xj = x[j];
+  const float kj = k[j];
+  float acc = (float)L.eps * xj;
+  float dg = (float)L.eps;
+  if (c.x + 1 < nx) { acc += kj * (xj - x[j + 1]); dg += kj; }
+  if (c.x > 0) { const float kk = k[j - 1]; acc += kk * (xj - x[j - 1]); dg += kk; }
+  if (c.y + 1 < ny) { acc += kj * (xj - x[j + sy]); dg += kj; }
+  if (c.y > 0) { const float kk = k[j - sy]; acc += kk * (xj - x[j - sy]); dg += kk; }
+  if (c.z + 1 < nz) { acc += kj * (xj - x[j + sz]); dg += kj; }
+  if (c.z > 0) { const float kk = k[j - sz]; acc += kk * (xj - x[j - sz]); dg += kk; }
+  dinv_j = 1.0f / dg;
+  return acc;
+}
+
 // (A_l x)_j where the values of x come from a functor X(index): used when the iterate is
 // formed on the fly (first Jacobi sweep from zero, prolongated correction).
 template <class XF>

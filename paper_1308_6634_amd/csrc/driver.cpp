@@ -370,12 +370,71 @@ void enqueue_request_end(hipStream_t st, const BatchView &bv) {
   launch_copy_out(st, bv.d_descs, bv.B, bv.h->n);
 }
 
-void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner) {
+GraphCache::~GraphCache() {
+  for (hipGraphExec_t e : execs) hipGraphExecDestroy(e);
+  if (cap) hipStreamDestroy(cap);
+}
+
+// Capture `body` (kernel launches only) into an executable graph.
+template <class F>
+static hipGraphExec_t capture_graph(hipStream_t cap, F body) {
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  body(cap);
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(cap, &g) != hipSuccess || !g) return nullptr;
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e == hipSuccess ? ex : nullptr;
+}
+
+// The inner iteration through graphs. With product timing the two products stay eager
+// (each bracketed by events on the engine stream) and only the kernels after the adjoint
+// product (V-cycle, alpha reduction and rotations, update) replay as a graph; otherwise the
+// whole iteration is one graph. Returns false if capture is unavailable.
+static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
+  if (!gc.execs.empty()) return true;
+  if (!gc.cap && hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking) != hipSuccess) return false;
+  const InstDesc &H = *bv.h;
+  BatchView quiet = bv;
+  quiet.prod_events = nullptr;
+  quiet.adj_events = nullptr;
+  const bool timed = bv.prod_events != nullptr;
+  hipGraphExec_t ex;
+  if (timed) {
+    ex = capture_graph(gc.cap, [&](hipStream_t s) {
+      const int np = enqueue_vcycle(s, quiet);
+      launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
+      launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
+    });
+  } else {
+    ex = capture_graph(gc.cap, [&](hipStream_t s) { enqueue_inner(s, quiet); });
+  }
+  if (!ex) return false;
+  gc.execs.push_back(ex);
+  return true;
+}
+
+void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner,
+                         GraphCache *graphs) {
+  const bool use_graphs = graphs && prepare_inner_graphs(bv, *graphs);
+  const bool timed = bv.prod_events != nullptr;
   enqueue_request_begin(st, bv);
   for (int k = 1; k <= outer; ++k) {
     enqueue_outer_setup(st, bv);
     enqueue_mlsqr_init(st, bv);
-    for (int i = 0; i < inner; ++i) enqueue_inner(st, bv);
+    for (int i = 0; i < inner; ++i) {
+      if (!use_graphs) {
+        enqueue_inner(st, bv);
+      } else if (!timed) {
+        hipGraphLaunch(graphs->execs[0], st);
+      } else {
+        const int np = enqueue_forward(st, bv, V_V, EPI_FWD);
+        launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
+        enqueue_adjoint(st, bv, EPI_ADJ);
+        hipGraphLaunch(graphs->execs[0], st);
+      }
+    }
     enqueue_outer_end(st, bv);
   }
   enqueue_request_end(st, bv);

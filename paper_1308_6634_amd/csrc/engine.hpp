@@ -55,6 +55,13 @@ class Pool {
 
 using EventList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
 
+// Replayable HIP graphs of the inner iteration (plain and lockstep groups): captured once on
+// a private stream, launched on the engine stream for every inner step.
+struct GraphCache {
+  hipStream_t cap = nullptr;                 // capture stream (non-blocking, default priority)
+  std::vector<hipGraphExec_t> execs;
+  ~GraphCache();
+};
 // One reconstruction.
 struct Request {
   uint64_t ticket = 0;
@@ -104,6 +111,7 @@ struct Group {
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   EventList fwd_events, adj_events;
   bool timed = false;
+  std::unique_ptr<GraphCache> graphs;      // captured inner iteration (null: eager launches)
 };
 
 // A view of B same-shaped instances launched together.
@@ -124,7 +132,8 @@ void enqueue_mlsqr_init(hipStream_t st, const BatchView &bv);
 void enqueue_inner(hipStream_t st, const BatchView &bv);
 void enqueue_outer_end(hipStream_t st, const BatchView &bv);
 void enqueue_request_end(hipStream_t st, const BatchView &bv);
-void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner);
+void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner,
+                         GraphCache *graphs);
 
 double now_ms();
 

@@ -233,8 +233,9 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l
     } else {
       const float *__restrict__ src = lvbuf(L, src_sel);
       const Coord c = coord_of(j, L.nx, L.ny);
-      const float ax = stencil(D, l, src, j, c);
-      xn = src[j] + D.omega * L.dinv[j] * (b[j] - ax);
+      float dv;
+      const float ax = stencil_dinv(D, l, src, j, c, dv);
+      xn = src[j] + D.omega * dv * (b[j] - ax);
     }
     dst[j] = xn;
     if (want_dot) dot = (double)xn * (double)b[j];
@@ -372,12 +373,15 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, i
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
   float r = L.b[j];
+  float dv;
+  const Coord c = coord_of(j, L.nx, L.ny);
   if (!zero_x) {
-    const Coord c = coord_of(j, L.nx, L.ny);
-    r -= stencil(D, l, L.x, j, c);
+    r -= stencil_dinv(D, l, L.x, j, c, dv);
+  } else {
+    dv = L.dinv[j];
   }
   L.r[j] = r;
-  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * L.dinv[j] * r;
+  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * dv * r;
 }
 
 // One Chebyshev step: x += d (x = d when set_x); r -= A d (if update_r);
@@ -408,9 +412,10 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
     if (want_dot) dot = (double)xn * (double)L.b[j];
     if (update_r) {
       const Coord c = coord_of(j, L.nx, L.ny);
-      const float r = L.r[j] - stencil(D, l, d, j, c);
+      float dv;
+      const float r = L.r[j] - stencil_dinv(D, l, d, j, c, dv);
       L.r[j] = r;
-      if (!last) lvbuf(L, dn_sel)[j] = c_dd * dj + c_dr * L.dinv[j] * r;
+      if (!last) lvbuf(L, dn_sel)[j] = c_dd * dj + c_dr * dv * r;
     }
   }
   if (want_dot) {

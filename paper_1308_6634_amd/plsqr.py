@@ -35,6 +35,7 @@ PLSQR_SMOOTH_JACOBI, PLSQR_SMOOTH_CHEBYSHEV = 0, 1
 PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED, PLSQR_PREC_BF16 = 0, 1, 2
 PLSQR_ENGINE_SERVE = 1
 PLSQR_FLAG_TIME_PRODUCTS = 1
+PLSQR_FLAG_NO_GRAPHS = 2
 PLSQR_MAX_LEVELS = 12
 PLSQR_MAX_OUTER = 64
 PLSQR_MAX_RADIUS = 16
