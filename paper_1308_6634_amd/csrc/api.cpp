@@ -488,6 +488,10 @@ void serve_collect(plsqr_engine *eng) {
     r.ev_start = r.ev_done = nullptr;
     hipHostFree(r.pinned);
     r.pinned = nullptr;
+    // the request's kernels ran on worker streams: its memory returns only now
+    eng->pool.put(r.ws, r.lay.total);
+    r.ws = nullptr;
+    eng->used -= r.lay.total;
     r.status = res.status;
     r.done = true;
     eng->finishing[i] = eng->finishing.back();
@@ -560,36 +564,52 @@ void serve_tick(plsqr_engine *eng) {
     off += kv.second.size() * sizeof(void *);
   }
   hipMemcpyAsync(slot.dev, slot.pinned, off, hipMemcpyHostToDevice, eng->stream);
+  hipEventRecord(eng->ev_upload, eng->stream);
+  // subgroups run concurrently on the worker streams; each waits for the upload (which is
+  // ordered after the previous tick and after new admissions on the engine stream)
+  const int nl = (int)eng->lanes.size();
+  std::vector<bool> used(nl, false);
   std::vector<Request *> finished;
+  int gi = 0;
   for (auto &pl : plan) {
+    const int li = gi++ % nl;
+    hipStream_t ls = eng->lanes[li];
+    if (!used[li]) {
+      hipStreamWaitEvent(ls, eng->ev_upload, 0);
+      used[li] = true;
+    }
     std::vector<Request *> &mem = *pl.second;
     Request &r0 = *mem[0];
     BatchView bv{reinterpret_cast<InstDesc *const *>(slot.dev + pl.first), (int)mem.size(),
                  &r0.host, &r0.lay, nullptr, nullptr, nullptr};
     switch (step_type(r0.pb, r0.step)) {
-      case ST_BEGIN: enqueue_request_begin(eng->stream, bv); break;
+      case ST_BEGIN: enqueue_request_begin(ls, bv); break;
       case ST_OUTER_START:
-        enqueue_outer_setup(eng->stream, bv);
-        enqueue_mlsqr_init(eng->stream, bv);
+        enqueue_outer_setup(ls, bv);
+        enqueue_mlsqr_init(ls, bv);
         break;
-      case ST_INNER: enqueue_inner(eng->stream, bv); break;
-      case ST_OUTER_END: enqueue_outer_end(eng->stream, bv); break;
-      default: enqueue_request_end(eng->stream, bv); break;
+      case ST_INNER: enqueue_inner(ls, bv); break;
+      case ST_OUTER_END: enqueue_outer_end(ls, bv); break;
+      default: enqueue_request_end(ls, bv); break;
     }
-    for (Request *r : mem)
-      if (++r->step == r->steps_total) finished.push_back(r);
+    for (Request *r : mem) {
+      if (++r->step == r->steps_total) {
+        hipMemcpyAsync(r->pinned + pin_sc_off(), r->ws + r->lay.sc, SC_COUNT * sizeof(double),
+                       hipMemcpyDeviceToHost, ls);
+        hipMemcpyAsync(r->pinned + pin_dg_off(), r->ws + r->lay.diag,
+                       (size_t)(r->pb.outer + 1) * DG_COUNT * sizeof(double),
+                       hipMemcpyDeviceToHost, ls);
+        hipEventRecord(r->ev_done, ls);
+        finished.push_back(r);
+      }
+    }
+  }
+  for (int li = 0; li < nl; ++li) {
+    if (!used[li]) continue;
+    hipEventRecord(eng->lane_done[li], eng->lanes[li]);
+    hipStreamWaitEvent(eng->stream, eng->lane_done[li], 0);
   }
   for (Request *r : finished) {
-    hipMemcpyAsync(r->pinned + pin_sc_off(), r->ws + r->lay.sc, SC_COUNT * sizeof(double),
-                   hipMemcpyDeviceToHost, eng->stream);
-    hipMemcpyAsync(r->pinned + pin_dg_off(), r->ws + r->lay.diag,
-                   (size_t)(r->pb.outer + 1) * DG_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                   eng->stream);
-    hipEventRecord(r->ev_done, eng->stream);
-    // stream order makes the workspace reusable by any later admission right away
-    eng->pool.put(r->ws, r->lay.total);
-    r->ws = nullptr;
-    eng->used -= r->lay.total;
     eng->resident.erase(std::find(eng->resident.begin(), eng->resident.end(), r->ticket));
     eng->finishing.push_back(r->ticket);
   }
@@ -639,6 +659,16 @@ int serve_start(plsqr_engine *eng) {
   eng->ring.resize(4);
   for (auto &s : eng->ring)
     if (hipEventCreate(&s.ev) != hipSuccess) return set_error(PLSQR_E_HIP, "hipEventCreate failed");
+  if (hipEventCreateWithFlags(&eng->ev_upload, hipEventDisableTiming) != hipSuccess)
+    return set_error(PLSQR_E_HIP, "hipEventCreate failed");
+  constexpr int kLanes = 4;   // default-priority streams (the box exposes 4 hardware queues)
+  eng->lanes.resize(kLanes, nullptr);
+  eng->lane_done.resize(kLanes, nullptr);
+  for (int i = 0; i < kLanes; ++i) {
+    if (hipStreamCreateWithFlags(&eng->lanes[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&eng->lane_done[i], hipEventDisableTiming) != hipSuccess)
+      return set_error(PLSQR_E_HIP, "worker stream creation failed");
+  }
   eng->worker = std::thread(serve_loop, eng);
   return PLSQR_OK;
 }
@@ -650,12 +680,22 @@ void serve_stop(plsqr_engine *eng) {
   }
   eng->cv.notify_all();
   if (eng->worker.joinable()) eng->worker.join();
+  for (hipStream_t l : eng->lanes)
+    if (l) hipStreamSynchronize(l);
   for (auto &s : eng->ring) {
     if (s.ev) hipEventDestroy(s.ev);
     if (s.pinned) hipHostFree(s.pinned);
     if (s.dev) hipFree(s.dev);
   }
   eng->ring.clear();
+  for (size_t i = 0; i < eng->lanes.size(); ++i) {
+    if (eng->lane_done[i]) hipEventDestroy(eng->lane_done[i]);
+    if (eng->lanes[i]) hipStreamDestroy(eng->lanes[i]);
+  }
+  eng->lanes.clear();
+  eng->lane_done.clear();
+  if (eng->ev_upload) hipEventDestroy(eng->ev_upload);
+  eng->ev_upload = nullptr;
 }
 
 }  // namespace

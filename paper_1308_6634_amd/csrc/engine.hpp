@@ -168,6 +168,9 @@ struct plsqr_engine {
   };
   std::vector<TickSlot> ring;
   std::deque<int> inflight;           // ring slots whose ticks are on the device
+  std::vector<hipStream_t> lanes;     // worker streams: a tick's subgroups run concurrently
+  std::vector<hipEvent_t> lane_done;  // per-lane end-of-tick events (joined on `stream`)
+  hipEvent_t ev_upload = nullptr;     // pointer arrays of the tick are on the device
   int ring_next = 0;
   uint64_t ticks = 0;
   int max_inflight_ticks = 2;
