@@ -135,7 +135,13 @@ typedef struct {
   int32_t precision;
   double cheb_lo, cheb_hi;
   uint32_t flags;
-  int32_t reserved0;
+  /* performance knobs (0 = library default); they never change the method, only tiling:
+   *  tune_gemv_rows   rows of A per block of the dense forward product (1, 2, 4 or 8)
+   *  tune_col_chunks  row chunks of the dense adjoint product (1..64)
+   *  tune_strip_depth outputs per block along y/z in the blur passes (16, 32 or 64) */
+  int32_t tune_gemv_rows;
+  int32_t tune_col_chunks;
+  int32_t tune_strip_depth;
 } plsqr_problem;
 
 /* Completion record of one request (filled by plsqr_poll). */

@@ -89,6 +89,8 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.tmp2 = Ly.tmp2 ? F(Ly.tmp2) : nullptr;
   D.colpart = Ly.colpart ? F(Ly.colpart) : nullptr;
   D.colchunks = Ly.colchunks;
+  D.gemv_rows = pb.tune_gemv_rows ? pb.tune_gemv_rows : 4;
+  D.strip_depth = pb.tune_strip_depth ? pb.tune_strip_depth : 32;
   D.out_f = r.f_out;
   D.sc = reinterpret_cast<double *>(ws + Ly.sc);
   D.part = reinterpret_cast<double *>(ws + Ly.part);
@@ -399,7 +401,9 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
     const plsqr_problem &a = probs[0], &c = probs[b];
     if (c.outer != a.outer || c.inner != a.inner || lays[b].levels != lays[0].levels ||
         c.smoother != a.smoother || c.nu_pre != a.nu_pre || c.cheb_degree != a.cheb_degree ||
-        c.precision != a.precision || c.flags != a.flags)
+        c.precision != a.precision || c.flags != a.flags ||
+        c.tune_gemv_rows != a.tune_gemv_rows || c.tune_col_chunks != a.tune_col_chunks ||
+        c.tune_strip_depth != a.tune_strip_depth)
       return set_error(PLSQR_E_INVALID,
                        "a batch must share counts, levels, smoother schedule, precision and flags");
   }

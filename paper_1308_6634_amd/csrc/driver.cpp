@@ -48,6 +48,13 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   if (pb.precision != PLSQR_PREC_FP32 && pb.precision != PLSQR_PREC_BF16_REFINED &&
       pb.precision != PLSQR_PREC_BF16)
     return bad("unknown precision");
+  if (pb.tune_gemv_rows && pb.tune_gemv_rows != 1 && pb.tune_gemv_rows != 2 &&
+      pb.tune_gemv_rows != 4 && pb.tune_gemv_rows != 8)
+    return bad("tune_gemv_rows must be 0, 1, 2, 4 or 8");
+  if (pb.tune_col_chunks < 0 || pb.tune_col_chunks > 64) return bad("tune_col_chunks must be in [0, 64]");
+  if (pb.tune_strip_depth && pb.tune_strip_depth != 16 && pb.tune_strip_depth != 32 &&
+      pb.tune_strip_depth != 64)
+    return bad("tune_strip_depth must be 0, 16, 32 or 64");
   int levels = pb.mg_levels;
   if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
   if (levels < 1 || levels > kMaxLevels) return bad("mg_levels out of range");
@@ -94,10 +101,11 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   const long long mb = (L.m + kBlock - 1) / kBlock;
   const long long mr = (L.m + 3) / 4;
   // the strip-tiled blur passes write one partial per tile (64 x-columns x 64 along y or z)
-  const long long txn = (pb.nx + 63) / 64;           // strip tiles: 64 x-columns x 32 deep
-  const long long ty_tiles = txn * ((pb.ny + 31) / 32) * pb.nz;
-  const long long tz_tiles = txn * ((pb.nz + 31) / 32) * pb.ny;
-  L.nparts = (int)std::max({nb, mb, mr, ty_tiles, tz_tiles, 1LL});
+  const long long txn = (pb.nx + 63) / 64;           // strip tiles: 64 x-columns x >= 16 deep
+  const long long ty_tiles = txn * ((pb.ny + 15) / 16) * pb.nz;
+  const long long tz_tiles = txn * ((pb.nz + 15) / 16) * pb.ny;
+  const long long mr1 = L.m;                          // one row per block at the finest tiling
+  L.nparts = (int)std::max({nb, mb, mr, mr1, ty_tiles, tz_tiles, 1LL});
   L.desc = take(sizeof(InstDesc));
   L.descptr = take(sizeof(void *));
   L.sc = take(SC_COUNT * sizeof(double));
@@ -118,7 +126,7 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   } else {
     // dense adjoint row chunks: aim for >= 2048 blocks in total
     const long long colblocks = (L.n + 4 * kBlock - 1) / (4 * kBlock);
-    long long ch = (2048 + colblocks - 1) / colblocks;
+    long long ch = pb.tune_col_chunks ? pb.tune_col_chunks : (2048 + colblocks - 1) / colblocks;
     ch = std::max(1LL, std::min({ch, 64LL, L.m}));
     L.colchunks = (int)ch;
     L.colpart = take((size_t)ch * vb);
@@ -174,7 +182,8 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
     if (axes[i] == 0)
       np = launch_blur_x(st, bv.d_descs, bv.B, H.n, cur, dst, adj, e);
     else
-      np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e);
+      np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
+                             H.strip_depth);
     cur = dst;
   }
   return np;
@@ -192,7 +201,7 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   else if (bv.gemm)
     np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, epi);
   else
-    np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi);
+    np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi, H.gemv_rows);
   time_end(st, ev, a);
   return np;
 }

@@ -553,7 +553,8 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
 
 // y or z pass: a block of 64 x 4 threads owns a strip of 64 x-columns and 64 outputs along
 // the axis (other coordinate fixed); it stages (64 + 2r) planes of the strip in LDS.
-constexpr int kStripX = 64, kStripA = 32;
+constexpr int kStripX = 64;
+template <int kStripA>
 __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, int axis,
                                                       int src_sel, int dst_sel, int adj, int epi) {
   const InstDesc &D = inst(descs);
@@ -997,16 +998,26 @@ int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int sr
   return (int)g;
 }
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                      int src, int dst, int adj, int epi) {
+                      int src, int dst, int adj, int epi, int depth) {
   const int na = (axis == 1) ? ny : nz, no = (axis == 1) ? nz : ny;
-  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((na + kStripA - 1) / kStripA) * no;
-  LAUNCH(k_blur_strip, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
+  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((na + depth - 1) / depth) * no;
+  if (depth == 16)
+    LAUNCH(k_blur_strip<16>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
+  else if (depth == 64)
+    LAUNCH(k_blur_strip<64>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
+  else
+    LAUNCH(k_blur_strip<32>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
   return (int)tiles;
 }
-constexpr int kGemvRows = 4;
-int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi) {
-  const unsigned g = (unsigned)((m + kGemvRows - 1) / kGemvRows);
-  LAUNCH(k_gemv_rows<kGemvRows>, g, B, d, src, epi);
+int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
+                     int rows) {
+  const unsigned g = (unsigned)((m + rows - 1) / rows);
+  switch (rows) {
+    case 1: LAUNCH(k_gemv_rows<1>, g, B, d, src, epi); break;
+    case 2: LAUNCH(k_gemv_rows<2>, g, B, d, src, epi); break;
+    case 8: LAUNCH(k_gemv_rows<8>, g, B, d, src, epi); break;
+    default: LAUNCH(k_gemv_rows<4>, g, B, d, src, epi); break;
+  }
   return (int)g;
 }
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks) {

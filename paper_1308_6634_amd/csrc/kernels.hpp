@@ -42,10 +42,11 @@ void launch_restrict_fine(hipStream_t st, InstDesc *const *d, int B, int l, long
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
                   int epi);
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                      int src, int dst, int adj, int epi);
+                      int src, int dst, int adj, int epi, int depth);
 int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
                      int dst, int adj, int epi);
-int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi);
+int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
+                     int rows);
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
 void launch_colsum(hipStream_t st, InstDesc *const *d, int B, long long n, int epi);
 int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m);

@@ -68,6 +68,7 @@ struct InstDesc {
   double *cfac;                      // coarsest level: Cholesky factor, L^{-1}, A^{-1} (3 x nc x nc)
   double *diag;                      // (outer + 1) x DG_COUNT records
   int nc, colchunks;
+  int gemv_rows, strip_depth;        // tiling of the dense forward product / blur passes
   LevelDesc lv[kMaxLevels];
 };
 

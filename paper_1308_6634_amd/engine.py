@@ -11,13 +11,18 @@ import torch
 from . import plsqr as P
 
 
-def problem_struct(p, flags=0, precision=P.PLSQR_PREC_FP32):
+def problem_struct(p, flags=0, precision=P.PLSQR_PREC_FP32, knobs=None):
     """plsqr_problem from any object with the problem fields (dims, reg, T, tau, eps, outer,
-    inner, levels, smoother, nu_pre, nu_post, omega, cheb_degree, cheb_lo, cheb_hi)."""
-    return P.make_problem(tuple(p.dims), reg=p.reg, T=p.T, tau=p.tau, eps=p.eps, outer=p.outer,
-                          inner=p.inner, levels=p.levels, smoother=p.smoother, nu_pre=p.nu_pre,
-                          nu_post=p.nu_post, omega=p.omega, cheb_degree=p.cheb_degree,
-                          cheb_lo=p.cheb_lo, cheb_hi=p.cheb_hi, precision=precision, flags=flags)
+    inner, levels, smoother, nu_pre, nu_post, omega, cheb_degree, cheb_lo, cheb_hi);
+    ``knobs`` sets tiling fields (tune_*)."""
+    pb = P.make_problem(tuple(p.dims), reg=p.reg, T=p.T, tau=p.tau, eps=p.eps, outer=p.outer,
+                        inner=p.inner, levels=p.levels, smoother=p.smoother, nu_pre=p.nu_pre,
+                        nu_post=p.nu_post, omega=p.omega, cheb_degree=p.cheb_degree,
+                        cheb_lo=p.cheb_lo, cheb_hi=p.cheb_hi, precision=precision, flags=flags)
+    for k, v in (knobs or {}).items():
+        if k.startswith("tune_"):
+            setattr(pb, k, int(v))
+    return pb
 
 
 class Engine:

@@ -66,7 +66,8 @@ class plsqr_problem(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("cheb_degree", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("reserved0", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("tune_gemv_rows", ctypes.c_int32),
+                ("tune_col_chunks", ctypes.c_int32), ("tune_strip_depth", ctypes.c_int32)]
 
 
 class plsqr_result(ctypes.Structure):

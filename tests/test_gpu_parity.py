@@ -436,3 +436,24 @@ def test_graph_replay_equals_eager(engine, kind):
         np.testing.assert_array_equal(got, eager)
         if flags:
             assert res.forward_launches == p.outer * p.inner
+
+
+def test_autotuned_chebyshev_problem_matches_oracle(engine):
+    """The autotuner's tiling knobs do not change results beyond rounding, and its chosen
+    Chebyshev interval, given to the oracle too, keeps parity."""
+    from paper_1308_6634_amd import autotune
+    from paper_1308_6634_amd.engine import problem_struct, solve
+    p = gen.config_c3(n=32, outer=2, inner=10)
+    settings, report = autotune.tune(p, engine, inner=3, repeats=1)
+    _say(f"[tune] c3 n=32: {settings}")
+    q = autotune.apply(p, settings)
+    import torch
+    op = engine.blur_operator(q.dims, q.taps)
+    g = torch.from_numpy(q.g.ravel().copy()).cuda()
+    f = torch.zeros(q.n_x, device="cuda")
+    st, _ = engine.wait(engine.submit(op, problem_struct(q, knobs=settings), g, f))
+    assert st == 0
+    f_ref, _ = lagged.solve_problem(q)
+    assert _rel(f.cpu().numpy().reshape(f_ref.shape), f_ref) <= TOL
+    f_default, _ = solve(q, engine=engine)
+    assert _rel(f.cpu().numpy().reshape(f_ref.shape), f_default) <= 1e-5
