@@ -198,6 +198,90 @@ __device__ __forceinline__ float stencil_f(const InstDesc &D, int l, long long j
   return acc;
 }
 
+// ---- 4-wide stencils (x-vectorised: thread owns voxels j..j+3, x0 = c.x % 4 == 0) -------
+struct V4 {
+  float v[4];
+};
+__device__ __forceinline__ V4 ld4(const float *p) {
+  const float4 t = *reinterpret_cast<const float4 *>(p);
+  V4 r;
+  r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+  return r;
+}
+__device__ __forceinline__ void st4(float *p, const V4 &a) {
+  *reinterpret_cast<float4 *>(p) = make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+}
+
+// (A_l x) and 1/diag(A_l) for the 4 voxels j..j+3 of one x-row (c.x % 4 == 0, nx % 4 == 0).
+// xc is the iterate at j..j+3; X4(idx, coord) returns it at idx..idx+3 (coord of idx) for the
+// y and z neighbours, X1(idx, coord) one value (the two x-neighbours). Face weights and
+// diagonals are accumulated in the same order as the one-voxel stencils above, so both give
+// the same values.
+template <class F4, class F1>
+__device__ __forceinline__ V4 stencil4(const InstDesc &D, int l, long long j, Coord c,
+                                       const V4 &xc, F4 X4, F1 X1, V4 &dinv) {
+  const LevelDesc &L = D.lv[l];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const long long sy = nx, sz = (long long)nx * ny;
+  Coord cl = c, cr = c;
+  cl.x -= 1;
+  cr.x += 4;
+  const float xl = (c.x > 0) ? X1(j - 1, cl) : 0.f;
+  const float xr = (c.x + 4 < nx) ? X1(j + 4, cr) : 0.f;
+  Coord cyp = c, cym = c, czp = c, czm = c;
+  cyp.y += 1; cym.y -= 1; czp.z += 1; czm.z -= 1;
+  V4 yp = {}, ym = {}, zp = {}, zm = {};
+  const bool hyp = c.y + 1 < ny, hym = c.y > 0, hzp = c.z + 1 < nz, hzm = c.z > 0;
+  if (hyp) yp = X4(j + sy, cyp);
+  if (hym) ym = X4(j - sy, cym);
+  if (hzp) zp = X4(j + sz, czp);
+  if (hzm) zm = X4(j - sz, czm);
+  // face weights: wxp[e] (to e+1), wxm0 (from x0-1), wy/wym, wz/wzm
+  V4 wxp, wyp, wym = {}, wzp = {}, wzm = {};
+  float wxm0;
+  if (l == 0) {
+    const V4 k = ld4(D.kappa + j);
+    wxp = k; wyp = k; wzp = k;
+    wxm0 = (c.x > 0) ? D.kappa[j - 1] : 0.f;
+    if (hym) wym = ld4(D.kappa + j - sy);
+    if (hzm) wzm = ld4(D.kappa + j - sz);
+  } else {
+    wxp = ld4(L.wx + j);
+    wyp = ld4(L.wy + j);
+    wxm0 = (c.x > 0) ? L.wx[j - 1] : 0.f;
+    if (hym) wym = ld4(L.wy + j - sy);
+    if (nz > 1) {
+      wzp = ld4(L.wz + j);
+      if (hzm) wzm = ld4(L.wz + j - sz);
+    }
+  }
+  V4 out;
+  const float eps = (float)L.eps;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float xj = xc.v[e];
+    float acc = eps * xj;
+    float dg = eps;
+    const bool hxp = c.x + e + 1 < nx;
+    const bool hxm = c.x + e > 0;
+    const float xnext = (e < 3) ? xc.v[e < 3 ? e + 1 : 3] : xr;
+    const float xprev = (e > 0) ? xc.v[e > 0 ? e - 1 : 0] : xl;
+    const float wm = (e > 0) ? wxp.v[e > 0 ? e - 1 : 0] : wxm0;
+    if (hxp) { acc += wxp.v[e] * (xj - xnext); dg += wxp.v[e]; }
+    if (hxm) { acc += wm * (xj - xprev); dg += wm; }
+    if (hyp) { acc += wyp.v[e] * (xj - yp.v[e]); dg += wyp.v[e]; }
+    if (hym) { acc += wym.v[e] * (xj - ym.v[e]); dg += wym.v[e]; }
+    if (nz > 1 || l == 0) {
+      if (hzp) { acc += wzp.v[e] * (xj - zp.v[e]); dg += wzp.v[e]; }
+      if (hzm) { acc += wzm.v[e] * (xj - zm.v[e]); dg += wzm.v[e]; }
+    }
+    out.v[e] = acc;
+    dinv.v[e] = 1.0f / dg;
+  }
+  if (l != 0) dinv = ld4(L.dinv + j);
+  return out;
+}
+
 // Index of the coarse parent of fine cell (c) on level l (2:1 in x, y and, in 3D, z).
 __device__ __forceinline__ long long parent_of(const LevelDesc &F, const LevelDesc &Cl, Coord c) {
   const int cz = (F.nz > 1) ? 2 : 1;

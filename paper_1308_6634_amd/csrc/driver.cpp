@@ -229,13 +229,62 @@ static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
 static int other(int s) { return s == LB_X ? LB_T : LB_X; }
 static int other_d(int s) { return s == LB_T ? LB_S : LB_T; }
 
+// Level kernels: the four-voxel-per-thread forms where the level's rows split into 16-byte
+// groups (nx % 4 == 0), the one-voxel forms otherwise; both compute the same values.
+namespace {
+struct LevelLaunch {
+  hipStream_t st;
+  InstDesc *const *d;
+  int B;
+  const Layout &Ly;
+  bool v4(int l) const { return Ly.lnx[l] % 4 == 0; }
+  long long n(int l) const { return Ly.ln[l]; }
+  int jacobi(int l, int first, int src, int dst, int want) const {
+    return v4(l) ? launch_jacobi4(st, d, B, l, n(l), first, src, dst, want)
+                 : launch_jacobi(st, d, B, l, n(l), first, src, dst, want);
+  }
+  int jacobi_first2(int l, int dst, int want) const {
+    return v4(l) ? launch_jacobi_first2_4(st, d, B, l, n(l), dst, want)
+                 : launch_jacobi_first2(st, d, B, l, n(l), dst, want);
+  }
+  int jacobi_prolong(int l, int src, int dst, int want) const {
+    return v4(l) ? launch_jacobi_prolong4(st, d, B, l, n(l), src, dst, want)
+                 : launch_jacobi_prolong(st, d, B, l, n(l), src, dst, want);
+  }
+  void cheb_first(int l, int last, int dn) const {
+    if (v4(l)) launch_cheb_first4(st, d, B, l, n(l), last, dn);
+    else launch_cheb_first(st, d, B, l, n(l), last, dn);
+  }
+  void cheb_start(int l, int zero_x, int dsel) const {
+    if (v4(l)) launch_cheb_start4(st, d, B, l, n(l), zero_x, dsel);
+    else launch_cheb_start(st, d, B, l, n(l), zero_x, dsel);
+  }
+  void cheb_start_prolong(int l, int dsel) const {
+    if (v4(l)) launch_cheb_start_prolong4(st, d, B, l, n(l), dsel);
+    else launch_cheb_start_prolong(st, d, B, l, n(l), dsel);
+  }
+  int cheb_step(int l, int set_x, int upd, int last, int dsel, int dn, int step, int want,
+                int add_prolong) const {
+    return v4(l) ? launch_cheb_step4(st, d, B, l, n(l), set_x, upd, last, dsel, dn, step, want,
+                                     add_prolong)
+                 : launch_cheb_step(st, d, B, l, n(l), set_x, upd, last, dsel, dn, step, want,
+                                    add_prolong);
+  }
+  void restrict_to(int l, int x_sel, int use_r) const {
+    const int nchild = (Ly.lnz[0] > 1) ? 8 : 4;
+    if (v4(l)) launch_restrict4(st, d, B, l, n(l + 1), x_sel, use_r);
+    else launch_restrict_fine(st, d, B, l, n(l + 1), nchild, x_sel, use_r);
+  }
+};
+}  // namespace
+
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
   const Layout &Ly = *bv.lay;
   const int L = H.levels;
   InstDesc *const *d = bv.d_descs;
   const int B = bv.B;
-  const int nchild = (H.nz > 1) ? 8 : 4;
+  const LevelLaunch K{st, d, B, Ly};
   if (L == 1) {
     launch_coarse_solve(st, d, B);   // exact M^{-1} on a single grid
     return launch_dot_vp(st, d, B, H.n);
@@ -251,29 +300,29 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
     for (int l = 0; l < L - 1; ++l) {
       int cur;
       if (nu >= 2) {
-        launch_jacobi_first2(st, d, B, l, Ly.ln[l], first_dst, 0);
+        K.jacobi_first2(l, first_dst, 0);
         cur = first_dst;
         for (int s = 2; s < nu; ++s) {
-          launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, other(cur), 0);
+          K.jacobi(l, 0, cur, other(cur), 0);
           cur = other(cur);
         }
       } else {
-        launch_jacobi(st, d, B, l, Ly.ln[l], 1, LB_X, first_dst, 0);
+        K.jacobi(l, 1, LB_X, first_dst, 0);
         cur = first_dst;
       }
       cur_l[l] = cur;
-      launch_restrict_fine(st, d, B, l, Ly.ln[l + 1], nchild, cur, 0);
+      K.restrict_to(l, cur, 0);
     }
     launch_coarse_solve(st, d, B);
     for (int l = L - 2; l >= 0; --l) {
       int cur = cur_l[l];
       const bool last0 = (nu == 1);
-      int r = launch_jacobi_prolong(st, d, B, l, Ly.ln[l], cur, other(cur), (l == 0 && last0) ? 1 : 0);
+      int r = K.jacobi_prolong(l, cur, other(cur), (l == 0 && last0) ? 1 : 0);
       if (l == 0 && last0) np = r;
       cur = other(cur);
       for (int s = 1; s < nu; ++s) {
         const bool last = (s == nu - 1);
-        r = launch_jacobi(st, d, B, l, Ly.ln[l], 0, cur, other(cur), (l == 0 && last) ? 1 : 0);
+        r = K.jacobi(l, 0, cur, other(cur), (l == 0 && last) ? 1 : 0);
         if (l == 0 && last) np = r;
         cur = other(cur);
       }
@@ -287,35 +336,35 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
         if (a == 0) {
           // start and first step from x = 0 in one kernel
           const bool last = (m == 1);
-          launch_cheb_first(st, d, B, l, Ly.ln[l], last ? 1 : 0, LB_T);
+          K.cheb_first(l, last ? 1 : 0, LB_T);
           k0 = 1;
         } else {
-          launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
+          K.cheb_start(l, 0, LB_T);
         }
         for (int k = k0; k < m; ++k) {
           const bool last = (k == m - 1);
           const bool upd = !last || (a == nu - 1);
           const int dn = other_d(dcur);
-          launch_cheb_step(st, d, B, l, Ly.ln[l], 0, upd ? 1 : 0, last ? 1 : 0, dcur, dn, k, 0, 0);
+          K.cheb_step(l, 0, upd ? 1 : 0, last ? 1 : 0, dcur, dn, k, 0, 0);
           dcur = dn;
         }
       }
-      launch_restrict_fine(st, d, B, l, Ly.ln[l + 1], nchild, LB_X, 1);
+      K.restrict_to(l, LB_X, 1);
     }
     launch_coarse_solve(st, d, B);
     for (int l = L - 2; l >= 0; --l) {
       for (int a = 0; a < nu; ++a) {
         if (a == 0)
-          launch_cheb_start_prolong(st, d, B, l, Ly.ln[l], LB_T);
+          K.cheb_start_prolong(l, LB_T);
         else
-          launch_cheb_start(st, d, B, l, Ly.ln[l], 0, LB_T);
+          K.cheb_start(l, 0, LB_T);
         int dcur = LB_T;
         for (int k = 0; k < m; ++k) {
           const bool last = (k == m - 1);
           const int dn = other_d(dcur);
           const bool want = (l == 0 && a == nu - 1 && last);
-          const int r = launch_cheb_step(st, d, B, l, Ly.ln[l], 0, last ? 0 : 1, last ? 1 : 0, dcur,
-                                         dn, k, want ? 1 : 0, (a == 0 && k == 0) ? 1 : 0);
+          const int r = K.cheb_step(l, 0, last ? 0 : 1, last ? 1 : 0, dcur, dn, k, want ? 1 : 0,
+                                    (a == 0 && k == 0) ? 1 : 0);
           if (want) np = r;
           dcur = dn;
         }

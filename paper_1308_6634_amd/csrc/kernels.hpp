@@ -39,6 +39,25 @@ void launch_cheb_start_prolong(hipStream_t st, InstDesc *const *d, int B, int l,
                                int d_sel);
 void launch_restrict_fine(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
                           int nchild, int x_sel, int use_r);
+// four-voxel-per-thread forms of the level kernels (smooth_vec.hip): the level's nx must be a
+// multiple of 4
+int launch_jacobi4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int first,
+                   int src, int dst, int want_dot);
+int launch_jacobi_first2_4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int dst,
+                           int want_dot);
+int launch_jacobi_prolong4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int src,
+                           int dst, int want_dot);
+void launch_cheb_first4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int last,
+                        int dn_sel);
+void launch_cheb_start_prolong4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l,
+                                int d_sel);
+void launch_cheb_start4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int zero_x,
+                        int d_sel);
+int launch_cheb_step4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
+                      int update_r, int last, int d_sel, int dn_sel, int step, int want_dot,
+                      int add_prolong);
+void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
+                      int x_sel, int use_r);
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
                   int epi);
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
