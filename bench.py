@@ -29,10 +29,16 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash():
+# Sources that determine the code of the dense forward-product kernel (the dominant kernel of
+# the dense workloads): HBM traffic counted for it stays valid while these are unchanged.
+DENSE_KERNEL_SOURCES = ("dense.hip", "device_common.hpp", "plsqr_internal.hpp", "kernels.hpp")
+
+
+def kernel_source_hash(files=DENSE_KERNEL_SOURCES):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1308_6634_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in files:
+        with open(os.path.join(ROOT, "paper_1308_6634_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -63,8 +69,11 @@ def dominant_bytes(p):
     if p.op_kind == "dense":
         m = p.A.shape[0]
         return 4 * m * n + 4 * n + 8 * m, "k_gemv_rows (dense forward product A v, u update)"
-    # blur: one 1D pass reads and writes one vector (halo re-reads come from cache)
-    return 8 * n, "k_blur_pass (forward blur pass)"
+    # blur: the forward product is one 1D pass per axis of extent > 1; each pass reads and
+    # writes one vector (halo re-reads come from cache) and the last one also reads u
+    # (u <- sv A v - alpha su u), so 2 na + 1 vectors move per product
+    na = max(1, sum(1 for e in (nx, ny, nz) if e > 1))
+    return 4 * n * (2 * na + 1), f"k_blur_x + k_blur_strip ({na}-pass forward blur product)"
 
 
 def cpu_baseline(p, target_s=15.0):
@@ -98,6 +107,69 @@ def cpu_baseline(p, target_s=15.0):
                       f"{t:.1f} s, FP64 NumPy/SciPy, host cores: {len(os.sched_getaffinity(0))}"}, S, f
 
 
+def _counter_per_dispatch(folder, counter, match):
+    """Per-dispatch values of one rocprofv3 counter for kernels whose name satisfies match."""
+    import csv
+    import glob
+    vals = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter or not match(row.get("Kernel_Name", "")):
+                    continue
+                key = (fn, row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+    return list(vals.values())
+
+
+def write_traffic(args, out=TRAFFIC_FILE):
+    """HBM bytes per launch of one kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per
+    dispatch), each scaled so that a plain 1 GiB device copy reads and writes 1 GiB."""
+    import re
+    if not args.traffic_kernel:
+        raise SystemExit("--write-traffic needs --traffic-kernel")
+    name = args.traffic_kernel
+    base = name.split("<")[0]
+
+    def is_kernel(k):
+        k = k.replace(" ", "")
+        return re.search(r"(^|[:\s])" + re.escape(name.replace(" ", "")) + r"(\(|$)", k) is not None
+
+    def is_copy(k):
+        return "copyBuffer" in k
+
+    fdir, wdir, cfdir, cwdir = args.write_traffic
+    fetch = _counter_per_dispatch(fdir, "FETCH_SIZE", is_kernel)
+    write = _counter_per_dispatch(wdir, "WRITE_SIZE", is_kernel)
+    cfetch = _counter_per_dispatch(cfdir, "FETCH_SIZE", is_copy)
+    cwrite = _counter_per_dispatch(cwdir, "WRITE_SIZE", is_copy)
+    if not (fetch and write and cfetch and cwrite):
+        raise SystemExit("a counter pass holds no matching dispatch")
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / (sum(cfetch) / len(cfetch))
+    wscale = gib_kib / (sum(cwrite) / len(cwrite))
+    f_kib = sum(fetch) / len(fetch)
+    w_kib = sum(write) / len(write)
+    fb, wb = f_kib * 1024 * fscale, w_kib * 1024 * wscale
+    m = re.search(r"<(\d+)>", name)
+    rec = {"workload": args.workload, "kernel": name, "gemv_rows": int(m.group(1)) if m else None,
+           "source_sha": kernel_source_hash(), "source_files": list(DENSE_KERNEL_SOURCES),
+           "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
+           "launches": len(fetch),
+           "copy_calibration": {"bytes": 1 << 30, "fetch_kib_raw": sum(cfetch) / len(cfetch),
+                                "write_kib_raw": sum(cwrite) / len(cwrite), "fetch_scale": fscale,
+                                "write_scale": wscale, "launches": len(cfetch)},
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"{base}: {len(fetch)} launches; FETCH_SIZE {f_kib:.1f} KiB raw x {fscale:.5f}, "
+          f"WRITE_SIZE {w_kib:.1f} KiB raw x {wscale:.5f} -> {(fb + wb) / 1e9:.4f} GB per launch")
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +190,15 @@ def main():
                     help="skip the (untimed) autotuning of tiling knobs before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (HBM counter calibration)")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
+                    help="host only: turn four rocprofv3 --pmc CSV output folders (FETCH_SIZE and "
+                         "WRITE_SIZE of a bench run, then of --copy-calibration) into the HBM "
+                         "traffic record of --traffic-kernel read by later bench runs")
+    ap.add_argument("--traffic-kernel", default=None,
+                    help="exact kernel name for --write-traffic, e.g. 'k_gemv_rows<2>'")
     args = ap.parse_args()
+    if args.write_traffic:
+        return write_traffic(args)
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -188,7 +268,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("kernels_hip_sha") == kernel_source_hash() and tr.get("workload") == args.workload:
+            if (tr.get("source_sha") == kernel_source_hash() and tr.get("workload") == args.workload
+                    and tr.get("gemv_rows") == settings.get("tune_gemv_rows")):
                 traffic = tr.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None

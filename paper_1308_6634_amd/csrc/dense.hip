@@ -1,0 +1,135 @@
+// Dense products of the forward operator A (n_Y x n_X, row-major FP32 in HBM) in FP32:
+// y = A x one block per kRows rows (each row streamed once with 16-byte loads), and
+// x = A^T u as column partial sums over row chunks followed by a chunk sum. Both apply the
+// Krylov epilogues of the bidiagonalization (section 2, Algorithm 2) to their outputs.
+// These are the HBM-bound kernels of the dense-operator path; a batch of instances that
+// shares A uses the MFMA kernels in gemm_bf16.hip instead.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace plsqr {
+
+// Dense forward product y = A x for kRows rows per block, epilogue per row.
+template <int kRows>
+__global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, int src_sel, int epi) {
+  const InstDesc &D = inst(descs);
+  const long long row0 = (long long)blockIdx.x * kRows;
+  const long long n = D.n;
+  const float *__restrict__ x = vec_of(D, src_sel);
+  const float *__restrict__ A = D.A;
+  float acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+  const int nrows = (int)min((long long)kRows, max(0LL, D.m - row0));
+  if ((n & 3) == 0) {
+    const long long n4 = n >> 2;
+    const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
+    for (long long c = threadIdx.x; c < n4; c += kBlock) {
+      const float4 xv = x4[c];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        if (r < nrows) {
+          const float4 a = reinterpret_cast<const float4 *>(A + (row0 + r) * n)[c];
+          acc[r] += a.x * xv.x + a.y * xv.y + a.z * xv.z + a.w * xv.w;
+        }
+      }
+    }
+  } else {
+    for (long long c = threadIdx.x; c < n; c += kBlock) {
+      const float xv = x[c];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r)
+        if (r < nrows) acc[r] += A[(row0 + r) * n + c] * xv;
+    }
+  }
+  __shared__ float ys[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const float s = block_sum_f(acc[r]);
+    if (threadIdx.x == 0) ys[r] = s;
+  }
+  __syncthreads();
+  double dot = 0.0;
+  if (threadIdx.x < nrows) {
+    const long long i = row0 + threadIdx.x;
+    epilogue(D, epi, i, ys[threadIdx.x], nullptr, dot);
+  }
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+}
+
+// Dense adjoint, stage 1: column partial sums over a chunk of rows.
+// grid (ceil(n/(4*kBlock)), B, chunks); colpart[chunk][col] = sum_{rows in chunk} A[row][col] u[row]
+__global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long n = D.n, m = D.m;
+  const int chunks = D.colchunks;
+  const int ch = blockIdx.z;
+  if (ch >= chunks) return;
+  const long long rc = (m + chunks - 1) / chunks;
+  const long long r0 = ch * rc, r1 = min(m, r0 + rc);
+  const float *__restrict__ A = D.A;
+  const float *__restrict__ u = D.u;
+  float *__restrict__ out = D.colpart + (long long)ch * n;
+  if ((n & 3) == 0) {
+    const long long c4 = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c4 * 4 >= n) return;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (long long r = r0; r < r1; ++r) {
+      const float ur = u[r];
+      const float4 a = reinterpret_cast<const float4 *>(A + r * n)[c4];
+      acc.x += a.x * ur;
+      acc.y += a.y * ur;
+      acc.z += a.z * ur;
+      acc.w += a.w * ur;
+    }
+    reinterpret_cast<float4 *>(out)[c4] = acc;
+  } else {
+    const long long c0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4;
+    for (int q = 0; q < 4; ++q) {
+      const long long c = c0 + q;
+      if (c >= n) break;
+      float acc = 0.f;
+      for (long long r = r0; r < r1; ++r) acc += A[r * n + c] * u[r];
+      out[c] = acc;
+    }
+  }
+}
+
+// Dense adjoint, stage 2: sum the chunk partials and apply the epilogue.
+__global__ void __launch_bounds__(kBlock) k_colsum(InstDesc *const *descs, int epi) {
+  const InstDesc &D = inst(descs);
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= D.n) return;
+  float y = 0.f;
+  for (int ch = 0; ch < D.colchunks; ++ch) y += D.colpart[(long long)ch * D.n + c];
+  double dot = 0.0;
+  epilogue(D, epi, c, y, nullptr, dot);
+}
+
+static inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+#define LAUNCH(kern, gx, gy, ...) \
+  hipLaunchKernelGGL(kern, dim3(gx, gy), dim3(kBlock), 0, st, __VA_ARGS__)
+
+int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
+                     int rows) {
+  const unsigned g = (unsigned)((m + rows - 1) / rows);
+  switch (rows) {
+    case 1: LAUNCH(k_gemv_rows<1>, g, B, d, src, epi); break;
+    case 2: LAUNCH(k_gemv_rows<2>, g, B, d, src, epi); break;
+    case 8: LAUNCH(k_gemv_rows<8>, g, B, d, src, epi); break;
+    default: LAUNCH(k_gemv_rows<4>, g, B, d, src, epi); break;
+  }
+  return (int)g;
+}
+void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks) {
+  const unsigned gx = (unsigned)((n + 4 * kBlock - 1) / (4 * kBlock));
+  hipLaunchKernelGGL(k_gemv_cols, dim3(gx, B, chunks), dim3(kBlock), 0, st, d);
+}
+void launch_colsum(hipStream_t st, InstDesc *const *d, int B, long long n, int epi) {
+  LAUNCH(k_colsum, blocks_for(n), B, d, epi);
+}
+}  // namespace plsqr

@@ -1,0 +1,71 @@
+"""Host-side pieces of bench.py: the HBM traffic record built from rocprofv3 counter CSVs,
+the algorithmic byte counts of the dominant kernels and the one-GPU guard."""
+
+import argparse
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _csv(folder, rows):
+    os.makedirs(folder, exist_ok=True)
+    with open(os.path.join(folder, "x_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(FIELDS, r)))
+
+
+def test_write_traffic_scales_by_copy(tmp_path):
+    k2 = "void plsqr::k_gemv_rows<2>(plsqr::InstDesc* const*, int, int)"
+    k4 = "void plsqr::k_gemv_rows<4>(plsqr::InstDesc* const*, int, int)"
+    # two dispatches of the kernel (one of them split over two rows), one of another variant
+    _csv(tmp_path / "f", [(1, k2, "FETCH_SIZE", 1000.0), (2, k2, "FETCH_SIZE", 600.0),
+                          (2, k2, "FETCH_SIZE", 600.0), (3, k4, "FETCH_SIZE", 9e9)])
+    _csv(tmp_path / "w", [(1, k2, "WRITE_SIZE", 10.0), (2, k2, "WRITE_SIZE", 30.0)])
+    cp = "__amd_rocclr_copyBuffer"
+    _csv(tmp_path / "cf", [(1, cp, "FETCH_SIZE", 524288.0), (2, cp, "FETCH_SIZE", 524288.0)])
+    _csv(tmp_path / "cw", [(1, cp, "WRITE_SIZE", 1048576.0)])
+    args = argparse.Namespace(write_traffic=[str(tmp_path / d) for d in ("f", "w", "cf", "cw")],
+                              traffic_kernel="k_gemv_rows<2>", workload="c2")
+    out = tmp_path / "traffic.json"
+    bench.write_traffic(args, out=str(out))
+    rec = json.load(open(out))
+    assert rec["launches"] == 2 and rec["gemv_rows"] == 2
+    assert rec["copy_calibration"]["fetch_scale"] == pytest.approx(2.0)
+    assert rec["copy_calibration"]["write_scale"] == pytest.approx(1.0)
+    assert rec["fetch_bytes_per_launch"] == pytest.approx(1100.0 * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
+    assert rec["source_sha"] == bench.kernel_source_hash()
+
+
+def test_dominant_bytes():
+    class P:
+        pass
+
+    p = P()
+    p.dims, p.op_kind = (8, 8, 8), "blur"
+    assert bench.dominant_bytes(p)[0] == 4 * 512 * 7        # 3 passes: 3 reads + u, 3 writes
+    p.dims = (16, 8, 1)
+    assert bench.dominant_bytes(p)[0] == 4 * 128 * 5
+    import numpy as np
+    p.dims, p.op_kind, p.A = (4, 4, 2), "dense", np.zeros((10, 32), np.float32)
+    assert bench.dominant_bytes(p)[0] == 4 * 10 * 32 + 4 * 32 + 8 * 10
+
+
+def test_more_than_one_gpu_exits():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
