@@ -306,6 +306,7 @@ void fail_group(plsqr_engine *eng, Group &G, int rc) {
     std::memset(&r.result, 0, sizeof(r.result));
     r.result.status = rc;
     r.status = rc;
+    r.err = g_last_error;
     r.done = true;
   }
   G.state = Group::DONE;
@@ -862,11 +863,13 @@ int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {
   if (!r.done) return PLSQR_PENDING;
   if (out) *out = r.result;
   const int st = r.status;
+  const std::string err = r.err;
   eng->reqs.erase(it);
   if (st != PLSQR_OK) {
-    const char *m = st == PLSQR_E_NOT_SPD ? "preconditioner not positive definite"
-                    : st == PLSQR_E_NONFINITE ? "non-finite value in the Krylov scalars"
-                                              : "request failed";
+    const std::string m = st == PLSQR_E_NOT_SPD ? "preconditioner not positive definite"
+                          : st == PLSQR_E_NONFINITE ? "non-finite value in the Krylov scalars"
+                          : !err.empty()            ? err
+                                                    : "request failed";
     set_error(st, m);
   }
   return st;

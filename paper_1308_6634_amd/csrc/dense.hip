@@ -1,7 +1,7 @@
 // Dense products of the forward operator A (n_Y x n_X, row-major FP32 in HBM) in FP32:
 // y = A x one block per kRows rows (each row streamed once with 16-byte loads), and
 // x = A^T u as column partial sums over row chunks followed by a chunk sum. Both apply the
-// Krylov epilogues of the bidiagonalization (section 2, Algorithm 2) to their outputs.
+// Krylov epilogues of the bidiagonalization (section 3.2, Algorithm 2) to their outputs.
 // These are the HBM-bound kernels of the dense-operator path; a batch of instances that
 // shares A uses the MFMA kernels in gemm_bf16.hip instead.
 #include <hip/hip_runtime.h>

@@ -217,10 +217,11 @@ __device__ __forceinline__ void st4(float *p, const V4 &a) {
 // y and z neighbours, X1(idx, coord) one value (the two x-neighbours). Face weights and
 // diagonals are accumulated in the same order as the one-voxel stencils above, so both give
 // the same values.
+// L is level l's view (normally D.lv[l]; the V-cycle tail passes a copy whose vectors live
+// in LDS).
 template <class F4, class F1>
-__device__ __forceinline__ V4 stencil4(const InstDesc &D, int l, long long j, Coord c,
-                                       const V4 &xc, F4 X4, F1 X1, V4 &dinv) {
-  const LevelDesc &L = D.lv[l];
+__device__ __forceinline__ V4 stencil4(const InstDesc &D, const LevelDesc &L, int l, long long j,
+                                       Coord c, const V4 &xc, F4 X4, F1 X1, V4 &dinv) {
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const long long sy = nx, sz = (long long)nx * ny;
   Coord cl = c, cr = c;

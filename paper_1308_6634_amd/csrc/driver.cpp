@@ -180,7 +180,7 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
     const int e = last ? epi : EPI_STORE;
     if (axes[i] == 0)
-      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, cur, dst, adj, e);
+      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e);
     else
       np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
                              H.strip_depth);
@@ -278,6 +278,18 @@ struct LevelLaunch {
 };
 }  // namespace
 
+// First level of the V-cycle tail (one workgroup per instance, see k_vcycle_tail): the first
+// level l >= 1 with at most kTailCells cells such that every level l .. L-2 has nx % 4 == 0;
+// L - 1 (only the coarsest solve) when there is none.
+static int tail_start(const Layout &Ly, int L) {
+  int t = L - 1;
+  for (int l = L - 2; l >= 1; --l) {
+    if (Ly.ln[l] > kTailCells || Ly.lnx[l] % 4 != 0) break;
+    t = l;
+  }
+  return t;
+}
+
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
   const Layout &Ly = *bv.lay;
@@ -291,13 +303,14 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   }
   int np = 0;
   const int nu = H.nu_pre;
+  const int t = tail_start(Ly, L);
   if (H.smoother == PLSQR_SMOOTH_JACOBI) {
     // the first two pre-sweeps run as one kernel; the prolongation runs inside the first
     // post-sweep; every sweep writes the other of the (x, t) pair, ending in x
     const int pre_writes = (nu >= 2) ? nu - 1 : 1;
     const int first_dst = ((pre_writes + nu) % 2) ? LB_X : LB_T;
     int cur_l[kMaxLevels];
-    for (int l = 0; l < L - 1; ++l) {
+    for (int l = 0; l < t; ++l) {
       int cur;
       if (nu >= 2) {
         K.jacobi_first2(l, first_dst, 0);
@@ -313,8 +326,8 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
       cur_l[l] = cur;
       K.restrict_to(l, cur, 0);
     }
-    launch_coarse_solve(st, d, B);
-    for (int l = L - 2; l >= 0; --l) {
+    launch_vcycle_tail(st, d, B, t);
+    for (int l = t - 1; l >= 0; --l) {
       int cur = cur_l[l];
       const bool last0 = (nu == 1);
       int r = K.jacobi_prolong(l, cur, other(cur), (l == 0 && last0) ? 1 : 0);
@@ -329,7 +342,7 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
     }
   } else {
     const int m = H.cheb_degree;
-    for (int l = 0; l < L - 1; ++l) {
+    for (int l = 0; l < t; ++l) {
       for (int a = 0; a < nu; ++a) {
         int dcur = LB_T;
         int k0 = 0;
@@ -351,8 +364,8 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
       }
       K.restrict_to(l, LB_X, 1);
     }
-    launch_coarse_solve(st, d, B);
-    for (int l = L - 2; l >= 0; --l) {
+    launch_vcycle_tail(st, d, B, t);
+    for (int l = t - 1; l >= 0; --l) {
       for (int a = 0; a < nu; ++a) {
         if (a == 0)
           K.cheb_start_prolong(l, LB_T);

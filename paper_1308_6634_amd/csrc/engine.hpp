@@ -76,6 +76,7 @@ struct Request {
   char *pinned = nullptr;            // pinned staging: descriptor up, scalars/records down
   bool done = false;
   int status = PLSQR_OK;
+  std::string err;   // why the request failed (set with a failing status)
   double t_submit = 0.0, t_done = 0.0;
   plsqr_result result{};
   // serving mode: position in the fixed step schedule and completion event

@@ -15,7 +15,7 @@
 namespace plsqr {
 
 // ------------------------------------------------------------------------------------
-// a1: |grad f|, kappa and R(f)
+// Lagged diffusivity: |grad f|, c_f = r'(t)/t of eqs. (1.12)-(1.13) and R(f) (section 4.1)
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, int write_kappa) {
   const InstDesc &D = inst(descs);
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, 
 }
 
 // ------------------------------------------------------------------------------------
-// a2: multigrid hierarchy (Galerkin face sums), diagonals, coarsest Cholesky
+// Multigrid hierarchy (Galerkin face sums), diagonals, coarsest Cholesky (section 4.2)
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_level0_dinv(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs)
 }
 
 // ------------------------------------------------------------------------------------
-// a6: V-cycle pieces
+// V-cycle pieces (section 4.2)
 // ------------------------------------------------------------------------------------
 // Damped Jacobi sweep dst = src + omega D^{-1} (b - A src)  (first: src = 0).
 // With want_dot, also the partial of sum_j dst_j b_j (alpha^2 on level 0).
@@ -464,163 +464,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int 
 }
 
 // ------------------------------------------------------------------------------------
-// a4/a5/a10: forward and adjoint products
-// ------------------------------------------------------------------------------------
-// One 1D correlation pass of the separable blur along `axis`, zero outside the grid.
-// adj selects the reversed taps (the adjoint). The last pass applies the epilogue.
-__global__ void __launch_bounds__(kBlock) k_blur_pass(InstDesc *const *descs, int axis,
-                                                     int src_sel, int dst_sel, int adj, int epi) {
-  const InstDesc &D = inst(descs);
-  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  double dot = 0.0;
-  if (j < D.n) {
-    const int nx = D.nx, ny = D.ny;
-    const Coord c = coord_of(j, nx, ny);
-    const int pos = (axis == 0) ? c.x : (axis == 1) ? c.y : c.z;
-    const int ext = (axis == 0) ? nx : (axis == 1) ? ny : D.nz;
-    const long long stride = (axis == 0) ? 1 : (axis == 1) ? (long long)nx : (long long)nx * ny;
-    const int r = D.radius;
-    const float *__restrict__ src = vec_of(D, src_sel);
-    const int klo = -min(r, pos), khi = min(r, ext - 1 - pos);
-    float y = 0.f;
-    for (int k = klo; k <= khi; ++k) {
-      const float w = D.taps[adj ? (r - k) : (r + k)];
-      y += w * src[j + k * stride];
-    }
-    epilogue(D, epi, j, y, vec_of(D, dst_sel), dot);
-  }
-  if (epi == EPI_FWD || epi == EPI_RESID) {
-    dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
-  }
-}
-
-// LDS-tiled blur passes. Out-of-grid samples are loaded as zeros, which is exactly the
-// zero boundary of the operator, so the tap loops need no bounds tests.
-//
-// x pass: a block owns kXTile consecutive voxels in linear order (rows of length nx back to
-// back), 4 per thread, and stages [j0 - r, j0 + kXTile + r) in LDS; a neighbour j + k belongs
-// to the same row iff 0 <= x + k < nx, which the tap range below enforces.
-constexpr int kXTile = 4 * kBlock;
-__global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int src_sel, int dst_sel,
-                                                  int adj, int epi) {
-  const InstDesc &D = inst(descs);
-  __shared__ float tile[kXTile + 2 * PLSQR_MAX_RADIUS];
-  __shared__ float w[kMaxTaps];
-  const int r = D.radius;
-  const long long n = D.n;
-  const long long j0 = (long long)blockIdx.x * kXTile;
-  double dot = 0.0;
-  if (j0 < n) {
-    const float *__restrict__ src = vec_of(D, src_sel);
-    if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-    float v[5];
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      const int i = threadIdx.x + u * kBlock;
-      const long long q = j0 - r + i;
-      v[u] = (i < kXTile + 2 * r && q >= 0 && q < n) ? src[q] : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      const int i = threadIdx.x + u * kBlock;
-      if (i < kXTile + 2 * r) tile[i] = v[u];
-    }
-    __syncthreads();
-    float *dst = vec_of(D, dst_sel);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = threadIdx.x + u * kBlock;
-      const long long j = j0 + i;
-      if (j < n) {
-        const int x = (int)((unsigned)j % (unsigned)D.nx);
-        const int klo = -min(r, x), khi = min(r, D.nx - 1 - x);
-        float y = 0.f;
-        for (int k = klo; k <= khi; ++k) y += w[r + k] * tile[i + r + k];
-        double dq = 0.0;
-        epilogue(D, epi, j, y, dst, dq);
-        dot += dq;
-      }
-    }
-  } else {
-    __syncthreads();
-  }
-  if (epi == EPI_FWD || epi == EPI_RESID) {
-    dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
-  }
-}
-
-// y or z pass: a block of 64 x 4 threads owns a strip of 64 x-columns and 64 outputs along
-// the axis (other coordinate fixed); it stages (64 + 2r) planes of the strip in LDS.
-constexpr int kStripX = 64;
-template <int kStripA>
-__global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, int axis,
-                                                      int src_sel, int dst_sel, int adj, int epi) {
-  const InstDesc &D = inst(descs);
-  __shared__ float tile[kStripA + 2 * PLSQR_MAX_RADIUS][kStripX];
-  __shared__ float w[kMaxTaps];
-  const int r = D.radius;
-  const int nx = D.nx, ny = D.ny, nz = D.nz;
-  const int na = (axis == 1) ? ny : nz;        // extent along the pass
-  const int no = (axis == 1) ? nz : ny;        // the remaining coordinate
-  const long long sa = (axis == 1) ? (long long)nx : (long long)nx * ny;
-  const long long so = (axis == 1) ? (long long)nx * ny : (long long)nx;
-  const int tx_n = (nx + kStripX - 1) / kStripX, ta_n = (na + kStripA - 1) / kStripA;
-  const long long tiles = (long long)tx_n * ta_n * no;
-  const long long t = blockIdx.x;
-  const int lx = threadIdx.x & (kStripX - 1), la = threadIdx.x / kStripX;   // 64 x 4
-  double dot = 0.0;
-  if (t < tiles) {
-    const int tx = (int)(t % tx_n);
-    const long long rest = t / tx_n;
-    const int ta = (int)(rest % ta_n);
-    const int o = (int)(rest / ta_n);
-    const int x = tx * kStripX + lx;
-    const int a0 = ta * kStripA;
-    const float *__restrict__ src = vec_of(D, src_sel);
-    if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-    const long long base = (long long)x + (long long)o * so;
-    // fill the tile: 8 independent loads in flight per thread before the LDS stores
-    constexpr int kStep = kBlock / kStripX;   // 4 planes per pass of the block
-    const int rows = kStripA + 2 * r;
-    for (int i0 = la; i0 < rows; i0 += 8 * kStep) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * kStep;
-        const int a = a0 - r + i;
-        v[u] = (i < rows && x < nx && a >= 0 && a < na) ? src[base + (long long)a * sa] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * kStep;
-        if (i < rows) tile[i][lx] = v[u];
-      }
-    }
-    __syncthreads();
-    if (x < nx) {
-      for (int q = la; q < kStripA; q += kBlock / kStripX) {
-        const int a = a0 + q;
-        if (a >= na) break;
-        float y = 0.f;
-        for (int k = 0; k <= 2 * r; ++k) y += w[k] * tile[q + k][lx];
-        double dq = 0.0;
-        epilogue(D, epi, base + (long long)a * sa, y, vec_of(D, dst_sel), dq);
-        dot += dq;
-      }
-    }
-  } else {
-    __syncthreads();
-  }
-  if (epi == EPI_FWD || epi == EPI_RESID) {
-    dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
-  }
-}
-
-// ------------------------------------------------------------------------------------
-// a3/a7/a8/a9: copies, reductions, rotations, updates
+// Krylov recurrences: copies, reductions, rotations, updates (section 3.2, Algorithm 2)
 // ------------------------------------------------------------------------------------
 // Start of outer step k: reset the per-step Krylov flags.
 __global__ void k_outer_begin(InstDesc *const *descs, int nblocks_unused) {
@@ -886,30 +730,6 @@ void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long
 }
 void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel) {
   LAUNCH(k_prolong, blocks_for(n_l), B, d, l, x_sel);
-}
-int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
-                     int dst, int adj, int epi) {
-  const unsigned g = blocks_for(n);
-  LAUNCH(k_blur_pass, g, B, d, axis, src, dst, adj, epi);
-  return (int)g;
-}
-int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
-                  int epi) {
-  const unsigned g = (unsigned)((n + kXTile - 1) / kXTile);
-  LAUNCH(k_blur_x, g, B, d, src, dst, adj, epi);
-  return (int)g;
-}
-int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                      int src, int dst, int adj, int epi, int depth) {
-  const int na = (axis == 1) ? ny : nz, no = (axis == 1) ? nz : ny;
-  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((na + depth - 1) / depth) * no;
-  if (depth == 16)
-    LAUNCH(k_blur_strip<16>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
-  else if (depth == 64)
-    LAUNCH(k_blur_strip<64>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
-  else
-    LAUNCH(k_blur_strip<32>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
-  return (int)tiles;
 }
 int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m) {
   const unsigned g = blocks_for(m);

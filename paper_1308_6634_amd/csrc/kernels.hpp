@@ -11,6 +11,10 @@ namespace plsqr {
 // level buffer selectors
 enum LevelBuf : int { LB_X = 0, LB_B, LB_R, LB_T, LB_S };
 
+// One-workgroup V-cycle tail: threads, and the largest level it takes over.
+constexpr int kTailBlock = 512;
+constexpr long long kTailCells = 4096;
+
 void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n);
 void launch_outer_begin(hipStream_t st, InstDesc *const *d, int B);
 int launch_diffusivity(hipStream_t st, InstDesc *const *d, int B, long long n, int write_kappa);
@@ -58,12 +62,14 @@ int launch_cheb_step4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
                       int add_prolong);
 void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
                       int x_sel, int use_r);
-int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int src, int dst, int adj,
-                  int epi);
+// levels t .. coarsest of a V-cycle in one workgroup per instance (t >= 1; levels t .. L-2 with
+// nx % 4 == 0)
+void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
+// separable blur passes (blur.hip); the x pass takes 16-byte windows when nx % 4 == 0
+int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
+                  int adj, int epi);
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
                       int src, int dst, int adj, int epi, int depth);
-int launch_blur_pass(hipStream_t st, InstDesc *const *d, int B, long long n, int axis, int src,
-                     int dst, int adj, int epi);
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
                      int rows);
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
