@@ -17,27 +17,29 @@ namespace {
 // epilogue()); u, p and out are workspace vectors (256-byte aligned), g is read per voxel.
 __device__ __forceinline__ void epilogue4(const InstDesc &D, int epi, long long j, const V4 &y,
                                           float *out, double &dot) {
-  const double *sc = D.sc;
+  const double *sc = sld(D.sc);
   switch (epi) {
     case EPI_FWD: {
+      float *du = sld(D.u);
       const float c1 = (float)sc[SC_SV], c2 = (float)(sc[SC_ALPHA] * sc[SC_SU]);
-      const V4 u = ld4(D.u + j);
+      const V4 u = ld4(du + j);
       V4 un;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         un.v[e] = c1 * y.v[e] - c2 * u.v[e];
         dot += (double)un.v[e] * (double)un.v[e];
       }
-      st4(D.u + j, un);
+      st4(du + j, un);
       break;
     }
     case EPI_ADJ: {
       const float c1 = (float)sc[SC_SU], c2 = (float)(sc[SC_BETA] * sc[SC_SV]);
-      const V4 p = ld4(D.p + j);
+      float *dp = sld(D.p);
+      const V4 p = ld4(dp + j);
       V4 pn;
 #pragma unroll
       for (int e = 0; e < 4; ++e) pn.v[e] = c1 * y.v[e] - c2 * p.v[e];
-      st4(D.p + j, pn);
+      st4(dp + j, pn);
       break;
     }
     case EPI_ADJ_INIT: {
@@ -45,13 +47,14 @@ __device__ __forceinline__ void epilogue4(const InstDesc &D, int epi, long long 
       V4 pn;
 #pragma unroll
       for (int e = 0; e < 4; ++e) pn.v[e] = su * y.v[e];
-      st4(D.p + j, pn);
+      st4(sld(D.p) + j, pn);
       break;
     }
     case EPI_RESID: {
+      const float *g = sld(D.g);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double r = (double)D.g[j + e] - (double)y.v[e];
+        const double r = (double)g[j + e] - (double)y.v[e];
         dot += r * r;
       }
       break;
@@ -63,7 +66,7 @@ __device__ __forceinline__ void epilogue4(const InstDesc &D, int epi, long long 
 __device__ __forceinline__ void block_partial(const InstDesc &D, int epi, double dot) {
   if (epi == EPI_FWD || epi == EPI_RESID) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -91,8 +94,8 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
   const InstDesc &D = inst(descs);
   __shared__ float tile[kXTile + 2 * PLSQR_MAX_RADIUS];
   __shared__ float w[kMaxTaps];
-  const int r = D.radius;
-  const long long n = D.n;
+  const int r = sld(D.radius);
+  const long long n = sld(D.n);
   const long long j0 = (long long)blockIdx.x * kXTile;
   double dot = 0.0;
   if (j0 < n) {
@@ -117,8 +120,9 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
       const int i = threadIdx.x + u * kBlock;
       const long long j = j0 + i;
       if (j < n) {
-        const int x = (int)((unsigned)j % (unsigned)D.nx);
-        const int klo = -min(r, x), khi = min(r, D.nx - 1 - x);
+        const int nx = sld(D.nx);
+        const int x = (int)((unsigned)j % (unsigned)nx);
+        const int klo = -min(r, x), khi = min(r, nx - 1 - x);
         float y = 0.f;
         for (int k = klo; k <= khi; ++k) y += w[r + k] * tile[i + r + k];
         double dq = 0.0;
@@ -131,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
   }
   if (epi == EPI_FWD || epi == EPI_RESID) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -178,13 +182,13 @@ __global__ void __launch_bounds__(kBlock) k_blur_x4(InstDesc *const *descs, int 
                                                    int dst_sel, int adj, int epi) {
   const InstDesc &D = inst(descs);
   __shared__ float w[kMaxTaps];
-  const int r = D.radius;
+  const int r = sld(D.radius);
   if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
   __syncthreads();
   const long long j = 4 * ((long long)blockIdx.x * kBlock + threadIdx.x);
   double dot = 0.0;
-  if (j < D.n) {
-    const int nx = D.nx;
+  if (j < sld(D.n)) {
+    const int nx = sld(D.nx);
     const int x0 = (int)((unsigned)j % (unsigned)nx);
     const float *__restrict__ src = vec_of(D, src_sel);
     V4 y;
@@ -212,8 +216,8 @@ __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, i
   const InstDesc &D = inst(descs);
   __shared__ float tile[kStripA + 2 * PLSQR_MAX_RADIUS][kStripX];
   __shared__ float w[kMaxTaps];
-  const int r = D.radius;
-  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const int r = sld(D.radius);
+  const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
   const int na = (axis == 1) ? ny : nz;        // extent along the pass
   const int no = (axis == 1) ? nz : ny;        // the remaining coordinate
   const long long sa = (axis == 1) ? (long long)nx : (long long)nx * ny;

@@ -16,13 +16,13 @@ template <int kRows>
 __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, int src_sel, int epi) {
   const InstDesc &D = inst(descs);
   const long long row0 = (long long)blockIdx.x * kRows;
-  const long long n = D.n;
+  const long long n = sld(D.n);
   const float *__restrict__ x = vec_of(D, src_sel);
-  const float *__restrict__ A = D.A;
+  const float *__restrict__ A = sld(D.A);
   float acc[kRows];
 #pragma unroll
   for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
-  const int nrows = (int)min((long long)kRows, max(0LL, D.m - row0));
+  const int nrows = (int)min((long long)kRows, max(0LL, sld(D.m) - row0));
   if ((n & 3) == 0) {
     const long long n4 = n >> 2;
     const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
@@ -57,22 +57,22 @@ __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, in
     epilogue(D, epi, i, ys[threadIdx.x], nullptr, dot);
   }
   dot = block_sum(dot);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
 // Dense adjoint, stage 1: column partial sums over a chunk of rows.
 // grid (ceil(n/(4*kBlock)), B, chunks); colpart[chunk][col] = sum_{rows in chunk} A[row][col] u[row]
 __global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
-  const long long n = D.n, m = D.m;
-  const int chunks = D.colchunks;
+  const long long n = sld(D.n), m = sld(D.m);
+  const int chunks = sld(D.colchunks);
   const int ch = blockIdx.z;
   if (ch >= chunks) return;
   const long long rc = (m + chunks - 1) / chunks;
   const long long r0 = ch * rc, r1 = min(m, r0 + rc);
-  const float *__restrict__ A = D.A;
-  const float *__restrict__ u = D.u;
-  float *__restrict__ out = D.colpart + (long long)ch * n;
+  const float *__restrict__ A = sld(D.A);
+  const float *__restrict__ u = sld(D.u);
+  float *__restrict__ out = sld(D.colpart) + (long long)ch * n;
   if ((n & 3) == 0) {
     const long long c4 = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (c4 * 4 >= n) return;
@@ -102,9 +102,9 @@ __global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
 __global__ void __launch_bounds__(kBlock) k_colsum(InstDesc *const *descs, int epi) {
   const InstDesc &D = inst(descs);
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= D.n) return;
+  if (c >= sld(D.n)) return;
   float y = 0.f;
-  for (int ch = 0; ch < D.colchunks; ++ch) y += D.colpart[(long long)ch * D.n + c];
+  for (int ch = 0; ch < sld(D.colchunks); ++ch) y += sld(D.colpart)[(long long)ch * sld(D.n) + c];
   double dot = 0.0;
   epilogue(D, epi, c, y, nullptr, dot);
 }

@@ -17,16 +17,48 @@ __device__ __forceinline__ const InstDesc &inst(InstDesc *const *descs) {
   return *descs[blockIdx.y];
 }
 
+// Uniform read of a descriptor field through the scalar cache. Descriptors are written by the
+// host before the kernels that read them and never by a kernel, so they can be read as
+// constant memory: one scalar load into SGPRs instead of a vector load per lane (which would
+// sit on every kernel's critical path ahead of its first data load). Only descriptor fields
+// go through here, never data that kernels write.
+template <class T>
+__device__ __forceinline__ T sld(const T &field) {
+  return *(const __attribute__((address_space(4))) T *)(&field);
+}
+
+// Level l's descriptor, field by field through the scalar cache.
+__device__ __forceinline__ LevelDesc level_of(const InstDesc &D, int l) {
+  const LevelDesc &g = D.lv[l];
+  LevelDesc L;
+  L.nx = sld(g.nx);
+  L.ny = sld(g.ny);
+  L.nz = sld(g.nz);
+  L.pad = 0;
+  L.n = sld(g.n);
+  L.x = sld(g.x);
+  L.b = sld(g.b);
+  L.r = sld(g.r);
+  L.t = sld(g.t);
+  L.s = sld(g.s);
+  L.wx = sld(g.wx);
+  L.wy = sld(g.wy);
+  L.wz = sld(g.wz);
+  L.dinv = sld(g.dinv);
+  L.eps = sld(g.eps);
+  return L;
+}
+
 __device__ __forceinline__ float *vec_of(const InstDesc &D, int sel) {
   switch (sel) {
-    case V_F: return D.f;
-    case V_U: return D.u;
-    case V_P: return D.p;
-    case V_V: return D.v;
-    case V_W: return D.w;
-    case V_TMP1: return D.tmp1;
-    case V_TMP2: return D.tmp2;
-    default: return const_cast<float *>(D.g);
+    case V_F: return sld(D.f);
+    case V_U: return sld(D.u);
+    case V_P: return sld(D.p);
+    case V_V: return sld(D.v);
+    case V_W: return sld(D.w);
+    case V_TMP1: return sld(D.tmp1);
+    case V_TMP2: return sld(D.tmp2);
+    default: return const_cast<float *>(sld(D.g));
   }
 }
 
@@ -104,13 +136,13 @@ __device__ __forceinline__ Coord coord_of(long long j, int nx, int ny) {
 // Level 0 face weight to the +a neighbour is kappa_j; coarser levels store them.
 __device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *__restrict__ x,
                                          long long j, Coord c) {
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const long long sx = 1, sy = nx, sz = (long long)nx * ny;
   const float xj = x[j];
   float acc = (float)L.eps * xj;
   if (l == 0) {
-    const float *__restrict__ k = D.kappa;
+    const float *__restrict__ k = sld(D.kappa);
     const float kj = k[j];
     if (c.x + 1 < nx) acc += kj * (xj - x[j + sx]);
     if (c.x > 0) acc += k[j - sx] * (xj - x[j - sx]);
@@ -138,13 +170,13 @@ __device__ __forceinline__ float stencil(const InstDesc &D, int l, const float *
 __device__ __forceinline__ float stencil_dinv(const InstDesc &D, int l, const float *__restrict__ x,
                                               long long j, Coord c, float &dinv_j) {
   if (l != 0) {
-    dinv_j = D.lv[l].dinv[j];
+    dinv_j = sld(D.lv[l].dinv)[j];
     return stencil(D, l, x, j, c);
   }
-  const LevelDesc &L = D.lv[0];
+  const LevelDesc L = level_of(D, 0);
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const long long sy = nx, sz = (long long)nx * ny;
-  const float *__restrict__ k = D.kappa;
+  const float *__restrict__ k = sld(D.kappa);
   const float xj = x[j];
   const float kj = k[j];
   float acc = (float)L.eps * xj;
@@ -164,7 +196,7 @@ __device__ __forceinline__ float stencil_dinv(const InstDesc &D, int l, const fl
 template <class XF>
 __device__ __forceinline__ float stencil_f(const InstDesc &D, int l, long long j, Coord c,
                                            XF X) {
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const long long sy = nx, sz = (long long)nx * ny;
   const float xj = X(j, c);
@@ -177,7 +209,7 @@ __device__ __forceinline__ float stencil_f(const InstDesc &D, int l, long long j
     return q;
   };
   if (l == 0) {
-    const float *__restrict__ k = D.kappa;
+    const float *__restrict__ k = sld(D.kappa);
     const float kj = k[j];
     if (c.x + 1 < nx) acc += kj * (xj - X(j + 1, nb(1, 0, 0)));
     if (c.x > 0) acc += k[j - 1] * (xj - X(j - 1, nb(-1, 0, 0)));
@@ -217,8 +249,7 @@ __device__ __forceinline__ void st4(float *p, const V4 &a) {
 // y and z neighbours, X1(idx, coord) one value (the two x-neighbours). Face weights and
 // diagonals are accumulated in the same order as the one-voxel stencils above, so both give
 // the same values.
-// L is level l's view (normally D.lv[l]; the V-cycle tail passes a copy whose vectors live
-// in LDS).
+// L is level l's view (level_of(D, l)).
 template <class F4, class F1>
 __device__ __forceinline__ V4 stencil4(const InstDesc &D, const LevelDesc &L, int l, long long j,
                                        Coord c, const V4 &xc, F4 X4, F1 X1, V4 &dinv) {
@@ -241,11 +272,12 @@ __device__ __forceinline__ V4 stencil4(const InstDesc &D, const LevelDesc &L, in
   V4 wxp, wyp, wym = {}, wzp = {}, wzm = {};
   float wxm0;
   if (l == 0) {
-    const V4 k = ld4(D.kappa + j);
+    const float *kappa = sld(D.kappa);
+    const V4 k = ld4(kappa + j);
     wxp = k; wyp = k; wzp = k;
-    wxm0 = (c.x > 0) ? D.kappa[j - 1] : 0.f;
-    if (hym) wym = ld4(D.kappa + j - sy);
-    if (hzm) wzm = ld4(D.kappa + j - sz);
+    wxm0 = (c.x > 0) ? kappa[j - 1] : 0.f;
+    if (hym) wym = ld4(kappa + j - sy);
+    if (hzm) wzm = ld4(kappa + j - sz);
   } else {
     wxp = ld4(L.wx + j);
     wyp = ld4(L.wy + j);
@@ -291,23 +323,25 @@ __device__ __forceinline__ long long parent_of(const LevelDesc &F, const LevelDe
 
 __device__ __forceinline__ void epilogue(const InstDesc &D, int epi, long long j, float y,
                                          float *out, double &dot) {
-  const double *sc = D.sc;
+  const double *sc = sld(D.sc);
   switch (epi) {
     case EPI_FWD: {
+      float *u = sld(D.u);
       const float c1 = (float)sc[SC_SV], c2 = (float)(sc[SC_ALPHA] * sc[SC_SU]);
-      const float un = c1 * y - c2 * D.u[j];
-      D.u[j] = un;
+      const float un = c1 * y - c2 * u[j];
+      u[j] = un;
       dot = (double)un * (double)un;
       break;
     }
     case EPI_ADJ: {
+      float *p = sld(D.p);
       const float c1 = (float)sc[SC_SU], c2 = (float)(sc[SC_BETA] * sc[SC_SV]);
-      D.p[j] = c1 * y - c2 * D.p[j];
+      p[j] = c1 * y - c2 * p[j];
       break;
     }
-    case EPI_ADJ_INIT: D.p[j] = (float)sc[SC_SU] * y; break;
+    case EPI_ADJ_INIT: sld(D.p)[j] = (float)sc[SC_SU] * y; break;
     case EPI_RESID: {
-      const double e = (double)D.g[j] - (double)y;
+      const double e = (double)sld(D.g)[j] - (double)y;
       dot = e * e;
       break;
     }

@@ -21,20 +21,20 @@ __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, 
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double r = 0.0;
-  if (j < D.n) {
-    const int nx = D.nx, ny = D.ny, nz = D.nz;
+  if (j < sld(D.n)) {
+    const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
     const Coord c = coord_of(j, nx, ny);
-    const float *__restrict__ f = D.f;
+    const float *__restrict__ f = sld(D.f);
     const float fj = f[j];
     const float gx = (c.x + 1 < nx) ? f[j + 1] - fj : 0.f;
     const float gy = (c.y + 1 < ny) ? f[j + nx] - fj : 0.f;
     const float gz = (c.z + 1 < nz) ? f[j + (long long)nx * ny] - fj : 0.f;
     const float t = sqrtf(gx * gx + gy * gy + gz * gz);
-    if (write_kappa) D.kappa[j] = kappa_of(D.reg, t, D.T);
-    r = penalty_of(D.reg, (double)t, (double)D.T);
+    if (write_kappa) sld(D.kappa)[j] = kappa_of(sld(D.reg), t, sld(D.T));
+    r = penalty_of(sld(D.reg), (double)t, (double)sld(D.T));
   }
   r = block_sum(r);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = r;
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = r;
 }
 
 // ------------------------------------------------------------------------------------
@@ -43,28 +43,28 @@ __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, 
 __global__ void __launch_bounds__(kBlock) k_level0_dinv(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= D.n) return;
-  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  if (j >= sld(D.n)) return;
+  const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
   const Coord c = coord_of(j, nx, ny);
-  const float *__restrict__ k = D.kappa;
+  const float *__restrict__ k = sld(D.kappa);
   const long long sy = nx, sz = (long long)nx * ny;
   const float kj = k[j];
-  float d = (float)D.lv[0].eps;
+  float d = (float)sld(D.lv[0].eps);
   if (c.x + 1 < nx) d += kj;
   if (c.x > 0) d += k[j - 1];
   if (c.y + 1 < ny) d += kj;
   if (c.y > 0) d += k[j - sy];
   if (c.z + 1 < nz) d += kj;
   if (c.z > 0) d += k[j - sz];
-  D.lv[0].dinv[j] = 1.0f / d;
+  sld(D.lv[0].dinv)[j] = 1.0f / d;
 }
 
 // Face weight of the fine level l from cell j to its +a neighbour (0 outside the grid).
 __device__ __forceinline__ float face_w(const InstDesc &D, int l, int a, long long j, Coord c) {
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   if (l == 0) {
     const bool in = (a == 0) ? (c.x + 1 < L.nx) : (a == 1) ? (c.y + 1 < L.ny) : (c.z + 1 < L.nz);
-    return in ? D.kappa[j] : 0.f;
+    return in ? sld(D.kappa)[j] : 0.f;
   }
   return (a == 0) ? L.wx[j] : (a == 1) ? L.wy[j] : L.wz[j];
 }
@@ -73,8 +73,8 @@ __device__ __forceinline__ float face_w(const InstDesc &D, int l, int a, long lo
 // (J, J+e_a) is the sum of the fine face weights crossing it.
 __global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int l) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &F = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc F = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (J >= Cl.n) return;
   const Coord cc = coord_of(J, Cl.nx, Cl.ny);
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int 
 
 __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, int l) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
   const Coord c = coord_of(j, L.nx, L.ny);
@@ -119,10 +119,10 @@ __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, i
 // place). One block per instance.
 __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
-  const int l = D.levels - 1;
-  const LevelDesc &L = D.lv[l];
+  const int l = sld(D.levels) - 1;
+  const LevelDesc L = level_of(D, l);
   const int n = (int)L.n;
-  double *__restrict__ A = D.cfac;
+  double *__restrict__ A = sld(D.cfac);
   for (long long i = threadIdx.x; i < (long long)n * n; i += kBlock) A[i] = 0.0;
   __syncthreads();
   for (int J = threadIdx.x; J < n; J += kBlock) {
@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
     __syncthreads();
   }
   if (threadIdx.x == 0 && bad) {
-    D.sc[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
-    D.sc[SC_STOP] = 1.0;
+    sld(D.sc)[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
+    sld(D.sc)[SC_STOP] = 1.0;
   }
   // Explicit inverse A^{-1} = L^{-T} L^{-1}, so that each V-cycle's coarsest solve is one
   // parallel matrix-vector product. L^{-1} overwrites the strictly-upper part's mirror:
@@ -200,9 +200,9 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
 // thread i reads column i: coalesced). One block per instance.
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[D.levels - 1];
+  const LevelDesc L = level_of(D, sld(D.levels) - 1);
   const int n = (int)L.n;
-  const double *__restrict__ Ai = D.cfac + (long long)n * n * 2;
+  const double *__restrict__ Ai = sld(D.cfac) + (long long)n * n * 2;
   __shared__ double bs[PLSQR_MAX_COARSE];
   for (int i = threadIdx.x; i < n; i += kBlock) bs[i] = (double)L.b[i];
   __syncthreads();
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs)
 __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l, int first,
                                                   int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
   if (j < L.n) {
@@ -229,20 +229,20 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l
     float *dst = lvbuf(L, dst_sel);
     float xn;
     if (first) {
-      xn = D.omega * L.dinv[j] * b[j];
+      xn = sld(D.omega) * L.dinv[j] * b[j];
     } else {
       const float *__restrict__ src = lvbuf(L, src_sel);
       const Coord c = coord_of(j, L.nx, L.ny);
       float dv;
       const float ax = stencil_dinv(D, l, src, j, c, dv);
-      xn = src[j] + D.omega * dv * (b[j] - ax);
+      xn = src[j] + sld(D.omega) * dv * (b[j] - ax);
     }
     dst[j] = xn;
     if (want_dot) dot = (double)xn * (double)b[j];
   }
   if (want_dot) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -251,13 +251,13 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l
 __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs, int l,
                                                          int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
   if (j < L.n) {
     const float *__restrict__ b = L.b;
     const float *__restrict__ dinv = L.dinv;
-    const float om = D.omega;
+    const float om = sld(D.omega);
     const Coord c = coord_of(j, L.nx, L.ny);
     auto x1 = [&](long long q, Coord) { return om * dinv[q] * b[q]; };
     const float ax = stencil_f(D, l, j, c, x1);
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs
   }
   if (want_dot) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -276,8 +276,8 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs
 __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *descs, int l,
                                                           int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc L = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
   if (j < L.n) {
@@ -286,13 +286,13 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *desc
     const Coord c = coord_of(j, L.nx, L.ny);
     auto xp = [&](long long q, Coord cq) { return x[q] + e[parent_of(L, Cl, cq)]; };
     const float ax = stencil_f(D, l, j, c, xp);
-    const float xn = xp(j, c) + D.omega * L.dinv[j] * (L.b[j] - ax);
+    const float xn = xp(j, c) + sld(D.omega) * L.dinv[j] * (L.b[j] - ax);
     lvbuf(L, dst_sel)[j] = xn;
     if (want_dot) dot = (double)xn * (double)L.b[j];
   }
   if (want_dot) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -301,13 +301,13 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *desc
 __global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, int l, int last,
                                                       int dn_sel) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
-  const double rho0 = 1.0 / D.cheb_sigma;
-  const double rho1 = 1.0 / (2.0 * D.cheb_sigma - rho0);
-  const float c_dd = (float)(rho1 * rho0), c_dr = (float)(2.0 * rho1 / D.cheb_delta);
-  const float ith = (float)(1.0 / D.cheb_theta);
+  const double rho0 = 1.0 / sld(D.cheb_sigma);
+  const double rho1 = 1.0 / (2.0 * sld(D.cheb_sigma) - rho0);
+  const float c_dd = (float)(rho1 * rho0), c_dr = (float)(2.0 * rho1 / sld(D.cheb_delta));
+  const float ith = (float)(1.0 / sld(D.cheb_theta));
   const float *__restrict__ b = L.b;
   const float *__restrict__ dinv = L.dinv;
   const Coord c = coord_of(j, L.nx, L.ny);
@@ -325,8 +325,8 @@ __global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, i
 __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *descs, int l,
                                                               int d_sel) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc L = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
   const float *__restrict__ x = L.x;
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *
   auto xp = [&](long long q, Coord cq) { return x[q] + e[parent_of(L, Cl, cq)]; };
   const float r = L.b[j] - stencil_f(D, l, j, c, xp);
   L.r[j] = r;
-  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * L.dinv[j] * r;
+  lvbuf(L, d_sel)[j] = (float)(1.0 / sld(D.cheb_theta)) * L.dinv[j] * r;
 }
 
 // Restriction of the residual with one thread per fine cell: the 2^d children of a coarse
@@ -344,8 +344,8 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *
 __global__ void __launch_bounds__(kBlock) k_restrict_fine(InstDesc *const *descs, int l, int x_sel,
                                                          int use_r) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &F = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc F = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const int nchild = (F.nz > 1) ? 8 : 4;
   const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
   const long long J = t / nchild;
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_fine(InstDesc *const *descs
 __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, int l, int zero_x,
                                                       int d_sel) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
   float r = L.b[j];
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, i
     dv = L.dinv[j];
   }
   L.r[j] = r;
-  lvbuf(L, d_sel)[j] = (float)(1.0 / D.cheb_theta) * dv * r;
+  lvbuf(L, d_sel)[j] = (float)(1.0 / sld(D.cheb_theta)) * dv * r;
 }
 
 // One Chebyshev step: x += d (x = d when set_x); r -= A d (if update_r);
@@ -391,20 +391,20 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
                                                      int update_r, int last, int d_sel, int dn_sel,
                                                      int step, int want_dot, int add_prolong) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &L = D.lv[l];
+  const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   // rho_0 = 1/sigma, rho_{k+1} = 1/(2 sigma - rho_k); d' = rho_{k+1} rho_k d + 2 rho_{k+1}/delta D^{-1} r
-  double rho = 1.0 / D.cheb_sigma;
-  for (int i = 0; i < step; ++i) rho = 1.0 / (2.0 * D.cheb_sigma - rho);
-  const double rho_next = 1.0 / (2.0 * D.cheb_sigma - rho);
-  const float c_dd = (float)(rho_next * rho), c_dr = (float)(2.0 * rho_next / D.cheb_delta);
+  double rho = 1.0 / sld(D.cheb_sigma);
+  for (int i = 0; i < step; ++i) rho = 1.0 / (2.0 * sld(D.cheb_sigma) - rho);
+  const double rho_next = 1.0 / (2.0 * sld(D.cheb_sigma) - rho);
+  const float c_dd = (float)(rho_next * rho), c_dr = (float)(2.0 * rho_next / sld(D.cheb_delta));
   double dot = 0.0;
   if (j < L.n) {
     const float *__restrict__ d = lvbuf(L, d_sel);
     const float dj = d[j];
     float xo = set_x ? 0.f : L.x[j];
     if (add_prolong) {      // pending coarse correction x += P e (pointwise)
-      const LevelDesc &Cl = D.lv[l + 1];
+      const LevelDesc Cl = level_of(D, l + 1);
       xo += Cl.x[parent_of(L, Cl, coord_of(j, L.nx, L.ny))];
     }
     const float xn = xo + dj;
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
   }
   if (want_dot) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
   }
 }
 
@@ -429,8 +429,8 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
 __global__ void __launch_bounds__(kBlock) k_restrict(InstDesc *const *descs, int l, int x_sel,
                                                     int use_r) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &F = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc F = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (J >= Cl.n) return;
   const Coord cc = coord_of(J, Cl.nx, Cl.ny);
@@ -453,8 +453,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict(InstDesc *const *descs, int
 // Prolongation: x_l[j] += x_{l+1}[parent(j)].
 __global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int l, int x_sel) {
   const InstDesc &D = inst(descs);
-  const LevelDesc &F = D.lv[l];
-  const LevelDesc &Cl = D.lv[l + 1];
+  const LevelDesc F = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= F.n) return;
   const Coord c = coord_of(j, F.nx, F.ny);
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int 
 __global__ void k_outer_begin(InstDesc *const *descs, int nblocks_unused) {
   const InstDesc &D = inst(descs);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double *sc = D.sc;
+    double *sc = sld(D.sc);
     sc[SC_OUTER] += 1.0;
     sc[SC_STOP] = (sc[SC_STATUS] != 0.0) ? 1.0 : 0.0;
     sc[SC_DONE] = 0.0;
@@ -486,9 +486,9 @@ __global__ void k_outer_begin(InstDesc *const *descs, int nblocks_unused) {
 __global__ void __launch_bounds__(kBlock) k_request_begin(InstDesc *const *descs, float tau_unused) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j < D.n) D.f[j] = 0.f;
+  if (j < sld(D.n)) sld(D.f)[j] = 0.f;
   if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) {
-    D.sc[threadIdx.x] = (threadIdx.x == SC_LAMBDA) ? sqrt(D.tau) : 0.0;
+    sld(D.sc)[threadIdx.x] = (threadIdx.x == SC_LAMBDA) ? sqrt(sld(D.tau)) : 0.0;
   }
   (void)tau_unused;
 }
@@ -498,25 +498,25 @@ __global__ void __launch_bounds__(kBlock) k_copy_g_u(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
-  if (j < D.m) {
-    const float gj = D.g[j];
-    D.u[j] = gj;
+  if (j < sld(D.m)) {
+    const float gj = sld(D.g)[j];
+    sld(D.u)[j] = gj;
     dot = (double)gj * (double)gj;
   }
   dot = block_sum(dot);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
 // Deterministic sum of the partials, then the scalar recurrences.
 __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int nparts, int what) {
   const InstDesc &D = inst(descs);
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) s += D.part[i];
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += sld(D.part)[i];
   s = block_sum(s);
   if (threadIdx.x != 0) return;
-  double *sc = D.sc;
+  double *sc = sld(D.sc);
   const int k = (int)sc[SC_OUTER];
-  double *dg = D.diag + (long long)k * DG_COUNT;
+  double *dg = sld(D.diag) + (long long)k * DG_COUNT;
   auto fail = [&](int code) {
     if (sc[SC_STATUS] == 0.0) sc[SC_STATUS] = (double)code;
     sc[SC_STOP] = 1.0;
@@ -596,35 +596,35 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
 __global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= D.n) return;
-  const bool stop = D.sc[SC_STOP] != 0.0;
-  D.f[j] = 0.f;
-  D.w[j] = stop ? 0.f : (float)D.sc[SC_SV] * D.v[j];
+  if (j >= sld(D.n)) return;
+  const bool stop = sld(D.sc)[SC_STOP] != 0.0;
+  sld(D.f)[j] = 0.f;
+  sld(D.w)[j] = stop ? 0.f : (float)sld(D.sc)[SC_SV] * sld(D.v)[j];
 }
 
 // f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step); 4 voxels
 // per thread when n is a multiple of 4.
 __global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
-  const double *sc = D.sc;
+  const double *sc = sld(D.sc);
   if (sc[SC_STOP] != 0.0) return;
   const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
   const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if ((D.n & 3) == 0) {
-    if (t * 4 >= D.n) return;
-    float4 wv = reinterpret_cast<const float4 *>(D.w)[t];
-    float4 fv = reinterpret_cast<const float4 *>(D.f)[t];
-    const float4 vv = reinterpret_cast<const float4 *>(D.v)[t];
+  if ((sld(D.n) & 3) == 0) {
+    if (t * 4 >= sld(D.n)) return;
+    float4 wv = reinterpret_cast<const float4 *>(sld(D.w))[t];
+    float4 fv = reinterpret_cast<const float4 *>(sld(D.f))[t];
+    const float4 vv = reinterpret_cast<const float4 *>(sld(D.v))[t];
     fv.x += cf * wv.x; fv.y += cf * wv.y; fv.z += cf * wv.z; fv.w += cf * wv.w;
     wv.x = sv * vv.x - cw * wv.x; wv.y = sv * vv.y - cw * wv.y;
     wv.z = sv * vv.z - cw * wv.z; wv.w = sv * vv.w - cw * wv.w;
-    reinterpret_cast<float4 *>(D.f)[t] = fv;
-    reinterpret_cast<float4 *>(D.w)[t] = wv;
+    reinterpret_cast<float4 *>(sld(D.f))[t] = fv;
+    reinterpret_cast<float4 *>(sld(D.w))[t] = wv;
   } else {
-    for (long long j = t * 4; j < t * 4 + 4 && j < D.n; ++j) {
-      const float wj = D.w[j];
-      D.f[j] += cf * wj;
-      D.w[j] = sv * D.v[j] - cw * wj;
+    for (long long j = t * 4; j < t * 4 + 4 && j < sld(D.n); ++j) {
+      const float wj = sld(D.w)[j];
+      sld(D.f)[j] += cf * wj;
+      sld(D.w)[j] = sv * sld(D.v)[j] - cw * wj;
     }
   }
 }
@@ -634,18 +634,18 @@ __global__ void __launch_bounds__(kBlock) k_dot_vp(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
-  if (j < D.n) dot = (double)D.v[j] * (double)D.p[j];
+  if (j < sld(D.n)) dot = (double)sld(D.v)[j] * (double)sld(D.p)[j];
   dot = block_sum(dot);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
 // Copy f^K to the caller's buffer if the request succeeded.
 __global__ void __launch_bounds__(kBlock) k_copy_out(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= D.n) return;
-  if (D.sc[SC_STATUS] != 0.0) return;
-  D.out_f[j] = D.f[j];
+  if (j >= sld(D.n)) return;
+  if (sld(D.sc)[SC_STATUS] != 0.0) return;
+  sld(D.out_f)[j] = sld(D.f)[j];
 }
 
 // ------------------------------------------------------------------------------------

@@ -53,7 +53,7 @@ __device__ __forceinline__ V4 prolonged4(const LevelDesc &F, const LevelDesc &Cl
 
 __device__ __forceinline__ void write_dot(const InstDesc &D, double dot) {
   dot = block_sum(dot);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = dot;
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
 }  // namespace
@@ -75,7 +75,7 @@ __device__ __forceinline__ double body_jacobi(const InstDesc &D, const LevelDesc
   if (first) {
     const V4 dv = ld4(L.dinv + j);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xn.v[e] = D.omega * dv.v[e] * b.v[e];
+    for (int e = 0; e < 4; ++e) xn.v[e] = sld(D.omega) * dv.v[e] * b.v[e];
   } else {
     const float *__restrict__ src = lvbuf(L, src_sel);
     const Coord c = coord_of(j, L.nx, L.ny);
@@ -85,7 +85,7 @@ __device__ __forceinline__ double body_jacobi(const InstDesc &D, const LevelDesc
     V4 dv;
     const V4 ax = stencil4(D, L, l, j, c, xc, X4, X1, dv);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xn.v[e] = xc.v[e] + D.omega * dv.v[e] * (b.v[e] - ax.v[e]);
+    for (int e = 0; e < 4; ++e) xn.v[e] = xc.v[e] + sld(D.omega) * dv.v[e] * (b.v[e] - ax.v[e]);
   }
   st4(lvbuf(L, dst_sel) + j, xn);
   return want_dot ? dot4(xn, b) : 0.0;
@@ -97,7 +97,7 @@ __device__ __forceinline__ double body_jacobi_first2(const InstDesc &D, const Le
                                                      long long j, int dst_sel, int want_dot) {
   const float *__restrict__ b = L.b;
   const float *__restrict__ dinv = L.dinv;
-  const float om = D.omega;
+  const float om = sld(D.omega);
   const Coord c = coord_of(j, L.nx, L.ny);
   auto X4 = [&](long long q, Coord) {
     const V4 bb = ld4(b + q), dd = ld4(dinv + q);
@@ -134,7 +134,7 @@ __device__ __forceinline__ double body_jacobi_prolong(const InstDesc &D, const L
   const V4 bj = ld4(L.b + j), dj = ld4(L.dinv + j);
   V4 xn;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) xn.v[e] = xc.v[e] + D.omega * dj.v[e] * (bj.v[e] - ax.v[e]);
+  for (int e = 0; e < 4; ++e) xn.v[e] = xc.v[e] + sld(D.omega) * dj.v[e] * (bj.v[e] - ax.v[e]);
   st4(lvbuf(L, dst_sel) + j, xn);
   return want_dot ? dot4(xn, bj) : 0.0;
 }
@@ -142,11 +142,11 @@ __device__ __forceinline__ double body_jacobi_prolong(const InstDesc &D, const L
 // Chebyshev recurrence coefficients of step `step`: rho_0 = 1/sigma,
 // rho_{k+1} = 1/(2 sigma - rho_k); d' = rho_{k+1} rho_k d + 2 rho_{k+1}/delta D^{-1} r.
 __device__ __forceinline__ void cheb_coefs(const InstDesc &D, int step, float &c_dd, float &c_dr) {
-  double rho = 1.0 / D.cheb_sigma;
-  for (int i = 0; i < step; ++i) rho = 1.0 / (2.0 * D.cheb_sigma - rho);
-  const double rho_next = 1.0 / (2.0 * D.cheb_sigma - rho);
+  double rho = 1.0 / sld(D.cheb_sigma);
+  for (int i = 0; i < step; ++i) rho = 1.0 / (2.0 * sld(D.cheb_sigma) - rho);
+  const double rho_next = 1.0 / (2.0 * sld(D.cheb_sigma) - rho);
   c_dd = (float)(rho_next * rho);
-  c_dr = (float)(2.0 * rho_next / D.cheb_delta);
+  c_dr = (float)(2.0 * rho_next / sld(D.cheb_delta));
 }
 
 // Chebyshev pre-smoothing start fused with its first step (x = 0): d0 = D^{-1} b / theta on
@@ -154,7 +154,7 @@ __device__ __forceinline__ void cheb_coefs(const InstDesc &D, int step, float &c
 __device__ __forceinline__ void body_cheb_first(const InstDesc &D, const LevelDesc &L, int l,
                                                 long long j, int last, int dn_sel, float c_dd,
                                                 float c_dr) {
-  const float ith = (float)(1.0 / D.cheb_theta);
+  const float ith = (float)(1.0 / sld(D.cheb_theta));
   const float *__restrict__ b = L.b;
   const float *__restrict__ dinv = L.dinv;
   const Coord c = coord_of(j, L.nx, L.ny);
@@ -196,7 +196,7 @@ __device__ __forceinline__ void body_cheb_start_prolong(const InstDesc &D, const
   const V4 r = sub4(ld4(L.b + j), stencil4(D, L, l, j, c, xc, X4, X1, unused));
   st4(L.r + j, r);
   const V4 dj = ld4(L.dinv + j);
-  const float ith = (float)(1.0 / D.cheb_theta);
+  const float ith = (float)(1.0 / sld(D.cheb_theta));
   V4 d;
 #pragma unroll
   for (int e = 0; e < 4; ++e) d.v[e] = ith * dj.v[e] * r.v[e];
@@ -218,7 +218,7 @@ __device__ __forceinline__ void body_cheb_start(const InstDesc &D, const LevelDe
     dv = ld4(L.dinv + j);
   }
   st4(L.r + j, r);
-  const float ith = (float)(1.0 / D.cheb_theta);
+  const float ith = (float)(1.0 / sld(D.cheb_theta));
   V4 d;
 #pragma unroll
   for (int e = 0; e < 4; ++e) d.v[e] = ith * dv.v[e] * r.v[e];
@@ -309,53 +309,58 @@ __device__ __forceinline__ void body_restrict(const InstDesc &D, const LevelDesc
 __global__ void __launch_bounds__(kBlock) k_jacobi4(InstDesc *const *descs, int l, int first,
                                                    int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   double dot = 0.0;
-  if (j < D.lv[l].n) dot = body_jacobi(D, D.lv[l], l, j, first, src_sel, dst_sel, want_dot);
+  if (j < L.n) dot = body_jacobi(D, L, l, j, first, src_sel, dst_sel, want_dot);
   if (want_dot) write_dot(D, dot);
 }
 
 __global__ void __launch_bounds__(kBlock) k_jacobi_first2_4(InstDesc *const *descs, int l,
                                                            int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   double dot = 0.0;
-  if (j < D.lv[l].n) dot = body_jacobi_first2(D, D.lv[l], l, j, dst_sel, want_dot);
+  if (j < L.n) dot = body_jacobi_first2(D, L, l, j, dst_sel, want_dot);
   if (want_dot) write_dot(D, dot);
 }
 
 __global__ void __launch_bounds__(kBlock) k_jacobi_prolong4(InstDesc *const *descs, int l,
                                                            int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
   double dot = 0.0;
-  if (j < D.lv[l].n)
-    dot = body_jacobi_prolong(D, D.lv[l], D.lv[l + 1], l, j, src_sel, dst_sel, want_dot);
+  if (j < L.n) dot = body_jacobi_prolong(D, L, Cl, l, j, src_sel, dst_sel, want_dot);
   if (want_dot) write_dot(D, dot);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cheb_first4(InstDesc *const *descs, int l, int last,
                                                        int dn_sel) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
-  if (j >= D.lv[l].n) return;
+  if (j >= L.n) return;
   float c_dd, c_dr;
   cheb_coefs(D, 0, c_dd, c_dr);
-  body_cheb_first(D, D.lv[l], l, j, last, dn_sel, c_dd, c_dr);
+  body_cheb_first(D, L, l, j, last, dn_sel, c_dd, c_dr);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong4(InstDesc *const *descs, int l,
                                                                int d_sel) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
-  if (j < D.lv[l].n) body_cheb_start_prolong(D, D.lv[l], D.lv[l + 1], l, j, d_sel);
+  if (j < L.n) body_cheb_start_prolong(D, L, Cl, l, j, d_sel);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cheb_start4(InstDesc *const *descs, int l, int zero_x,
                                                        int d_sel) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
-  if (j < D.lv[l].n) body_cheb_start(D, D.lv[l], l, j, zero_x, d_sel);
+  if (j < L.n) body_cheb_start(D, L, l, j, zero_x, d_sel);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cheb_step4(InstDesc *const *descs, int l, int set_x,
@@ -363,21 +368,23 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step4(InstDesc *const *descs, i
                                                       int dn_sel, int step, int want_dot,
                                                       int add_prolong) {
   const InstDesc &D = inst(descs);
+  const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
   float c_dd, c_dr;
   cheb_coefs(D, step, c_dd, c_dr);
   double dot = 0.0;
-  if (j < D.lv[l].n)
-    dot = body_cheb_step(D, D.lv[l], D.lv[l + 1], l, j, set_x, update_r, last, d_sel, dn_sel,
-                         want_dot, add_prolong, c_dd, c_dr);
+  if (j < L.n)
+    dot = body_cheb_step(D, L, Cl, l, j, set_x, update_r, last, d_sel, dn_sel, want_dot,
+                         add_prolong, c_dd, c_dr);
   if (want_dot) write_dot(D, dot);
 }
 
 __global__ void __launch_bounds__(kBlock) k_restrict4(InstDesc *const *descs, int l, int x_sel,
                                                      int use_r) {
   const InstDesc &D = inst(descs);
+  const LevelDesc F = level_of(D, l), Cl = level_of(D, l + 1);
   const long long J = 2 * ((long long)blockIdx.x * kBlock + threadIdx.x);
-  if (J < D.lv[l + 1].n) body_restrict(D, D.lv[l], D.lv[l + 1], l, J, x_sel, use_r);
+  if (J < Cl.n) body_restrict(D, F, Cl, l, J, x_sel, use_r);
 }
 
 // ------------------------------------------------------------------------------------
@@ -404,7 +411,7 @@ __device__ __forceinline__ int other_d(int s) { return s == LB_T ? LB_S : LB_T; 
 
 __device__ void tail_coarse_solve(const InstDesc &D, const LevelDesc &L, double *bs) {
   const int n = (int)L.n;
-  const double *__restrict__ Ai = D.cfac + (long long)n * n * 2;
+  const double *__restrict__ Ai = sld(D.cfac) + (long long)n * n * 2;
   for (int i = threadIdx.x; i < n; i += kTailBlock) bs[i] = (double)L.b[i];
   __syncthreads();
   int g = 1;   // lanes per row: the largest power of two <= min(64, kTailBlock / n)
@@ -427,14 +434,14 @@ __device__ void tail_coarse_solve(const InstDesc &D, const LevelDesc &L, double 
 __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail(InstDesc *const *descs, int t) {
   const InstDesc &D = inst(descs);
   __shared__ double bs[PLSQR_MAX_COARSE];
-  const int Lv = D.levels;
-  const int nu = D.nu_pre;
-  if (D.smoother == PLSQR_SMOOTH_JACOBI) {
+  const int Lv = sld(D.levels);
+  const int nu = sld(D.nu_pre);
+  if (sld(D.smoother) == PLSQR_SMOOTH_JACOBI) {
     const int pre_writes = (nu >= 2) ? nu - 1 : 1;
     const int first_dst = ((pre_writes + nu) % 2) ? LB_X : LB_T;
     unsigned cur_is_x = 0;   // bit l: level l's pre-smoothed iterate is in x (else in t)
     for (int l = t; l < Lv - 1; ++l) {
-      const LevelDesc &L = D.lv[l];
+      const LevelDesc L = level_of(D, l);
       int cur = first_dst;
       if (nu >= 2) {
         tail_rows(L.n, [&](long long j) { body_jacobi_first2(D, L, l, j, first_dst, 0); });
@@ -447,16 +454,16 @@ __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail(InstDesc *const *des
         tail_rows(L.n, [&](long long j) { body_jacobi(D, L, l, j, 1, LB_X, first_dst, 0); });
       }
       if (cur == LB_X) cur_is_x |= 1u << l;
-      const LevelDesc &C = D.lv[l + 1];
+      const LevelDesc C = level_of(D, l + 1);
       const int xs = cur;
       for (long long g = threadIdx.x; 2 * g < C.n; g += kTailBlock)
         body_restrict(D, L, C, l, 2 * g, xs, 0);
       __syncthreads();
     }
-    tail_coarse_solve(D, D.lv[Lv - 1], bs);
+    tail_coarse_solve(D, level_of(D, Lv - 1), bs);
     for (int l = Lv - 2; l >= t; --l) {
-      const LevelDesc &L = D.lv[l];
-      const LevelDesc &C = D.lv[l + 1];
+      const LevelDesc L = level_of(D, l);
+      const LevelDesc C = level_of(D, l + 1);
       int cur = ((cur_is_x >> l) & 1u) ? LB_X : LB_T;
       {
         const int src = cur, dst = other_x(cur);
@@ -470,10 +477,10 @@ __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail(InstDesc *const *des
       }
     }
   } else {
-    const int m = D.cheb_degree;
+    const int m = sld(D.cheb_degree);
     for (int l = t; l < Lv - 1; ++l) {
-      const LevelDesc &L = D.lv[l];
-      const LevelDesc &C = D.lv[l + 1];
+      const LevelDesc L = level_of(D, l);
+      const LevelDesc C = level_of(D, l + 1);
       for (int a = 0; a < nu; ++a) {
         int dcur = LB_T;
         int k0 = 0;
@@ -502,10 +509,10 @@ __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail(InstDesc *const *des
         body_restrict(D, L, C, l, 2 * g, LB_X, 1);
       __syncthreads();
     }
-    tail_coarse_solve(D, D.lv[Lv - 1], bs);
+    tail_coarse_solve(D, level_of(D, Lv - 1), bs);
     for (int l = Lv - 2; l >= t; --l) {
-      const LevelDesc &L = D.lv[l];
-      const LevelDesc &C = D.lv[l + 1];
+      const LevelDesc L = level_of(D, l);
+      const LevelDesc C = level_of(D, l + 1);
       for (int a = 0; a < nu; ++a) {
         if (a == 0)
           tail_rows(L.n, [&](long long j) { body_cheb_start_prolong(D, L, C, l, j, LB_T); });
