@@ -11,6 +11,8 @@
 
 namespace plsqr {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Dense forward product y = A x for kRows rows per block, epilogue per row.
 template <int kRows>
 __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, int src_sel, int epi) {
@@ -24,16 +26,41 @@ __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, in
   for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
   const int nrows = (int)min((long long)kRows, max(0LL, sld(D.m) - row0));
   if ((n & 3) == 0) {
+    // Each thread walks its columns c = tid, tid + kBlock, ... in order; kUnroll column
+    // groups are loaded (x once, every row of A) before any is used, so that many 16-byte
+    // loads are in flight per thread. A's rows stream through once (non-temporal); x is
+    // re-read by every block and stays cached. Rows past m read row m - 1 and are dropped.
+    constexpr int kUnroll = kRows <= 2 ? 4 : (kRows == 4 ? 2 : 1);
     const long long n4 = n >> 2;
-    const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
-    for (long long c = threadIdx.x; c < n4; c += kBlock) {
-      const float4 xv = x4[c];
+    const f32x4 *__restrict__ x4 = reinterpret_cast<const f32x4 *>(x);
+    const f32x4 *a4[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const long long row = min(row0 + r, sld(D.m) - 1);
+      a4[r] = reinterpret_cast<const f32x4 *>(A + row * n);
+    }
+    long long c = threadIdx.x;
+    for (; c + (long long)(kUnroll - 1) * kBlock < n4; c += (long long)kUnroll * kBlock) {
+      f32x4 xv[kUnroll], av[kRows][kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) xv[u] = x4[c + u * kBlock];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) av[r][u] = __builtin_nontemporal_load(&a4[r][c + u * kBlock]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+          acc[r] += av[r][u].x * xv[u].x + av[r][u].y * xv[u].y + av[r][u].z * xv[u].z +
+                    av[r][u].w * xv[u].w;
+    }
+    for (; c < n4; c += kBlock) {
+      const f32x4 xv = x4[c];
 #pragma unroll
       for (int r = 0; r < kRows; ++r) {
-        if (r < nrows) {
-          const float4 a = reinterpret_cast<const float4 *>(A + (row0 + r) * n)[c];
-          acc[r] += a.x * xv.x + a.y * xv.y + a.z * xv.z + a.w * xv.w;
-        }
+        const f32x4 a = __builtin_nontemporal_load(&a4[r][c]);
+        acc[r] += a.x * xv.x + a.y * xv.y + a.z * xv.z + a.w * xv.w;
       }
     }
   } else {
@@ -74,18 +101,40 @@ __global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
   const float *__restrict__ u = sld(D.u);
   float *__restrict__ out = sld(D.colpart) + (long long)ch * n;
   if ((n & 3) == 0) {
+    // Rows are taken in order, kRowUnroll at a time with all their loads issued first; u[r] is
+    // uniform across the block (scalar loads).
+    constexpr int kRowUnroll = 8;
     const long long c4 = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (c4 * 4 >= n) return;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (long long r = r0; r < r1; ++r) {
+    const long long n4 = n >> 2;
+    const f32x4 *__restrict__ a4 = reinterpret_cast<const f32x4 *>(A) + c4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    long long r = r0;
+    for (; r + kRowUnroll <= r1; r += kRowUnroll) {
+      f32x4 av[kRowUnroll];
+      float ur[kRowUnroll];
+#pragma unroll
+      for (int q = 0; q < kRowUnroll; ++q) {
+        av[q] = __builtin_nontemporal_load(a4 + (r + q) * n4);
+        ur[q] = u[r + q];
+      }
+#pragma unroll
+      for (int q = 0; q < kRowUnroll; ++q) {
+        acc.x += av[q].x * ur[q];
+        acc.y += av[q].y * ur[q];
+        acc.z += av[q].z * ur[q];
+        acc.w += av[q].w * ur[q];
+      }
+    }
+    for (; r < r1; ++r) {
+      const f32x4 a = __builtin_nontemporal_load(a4 + r * n4);
       const float ur = u[r];
-      const float4 a = reinterpret_cast<const float4 *>(A + r * n)[c4];
       acc.x += a.x * ur;
       acc.y += a.y * ur;
       acc.z += a.z * ur;
       acc.w += a.w * ur;
     }
-    reinterpret_cast<float4 *>(out)[c4] = acc;
+    reinterpret_cast<f32x4 *>(out)[c4] = acc;
   } else {
     const long long c0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4;
     for (int q = 0; q < 4; ++q) {
