@@ -77,7 +77,9 @@ def dominant_bytes(p):
 
 
 def cpu_baseline(p, target_s=15.0):
-    """The FP64 oracle on a bounded sample: the first outer iteration with S inner steps."""
+    """The FP64 oracle on a bounded sample of about target_s seconds: the first K outer
+    iterations with all their inner iterations when one outer iteration fits the budget,
+    otherwise the first outer iteration with S inner iterations. Returns (record, K, S, f)."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import lagged
@@ -90,25 +92,31 @@ def cpu_baseline(p, target_s=15.0):
                             p.cheb_hi)
     g = np.asarray(p.g, dtype=np.float64).reshape(shape if p.op_kind == "blur" else (-1,))
 
-    def run(inner):
+    def run(outer, inner):
         t0 = time.perf_counter()
-        f, _ = lagged.solve(shape, op, g, p.reg, p.T, p.tau, p.eps, 1, inner, p.levels, sm)
+        f, _ = lagged.solve(shape, op, g, p.reg, p.T, p.tau, p.eps, outer, inner, p.levels, sm)
         return time.perf_counter() - t0, f
 
-    t2, _ = run(2)
+    t2, _ = run(1, 2)
     per_iter = max(t2 / 3.0, 1e-3)
-    S = int(min(p.inner, max(4, target_s / per_iter)))
-    t, f = run(S)
+    if per_iter * p.inner <= target_s / 2:
+        K, S = int(min(p.outer, max(1, round(target_s / (per_iter * p.inner))))), p.inner
+    else:
+        K, S = 1, int(min(p.inner, max(4, target_s / per_iter)))
+    t, f = run(K, S)
     threads = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
     cores = max(threads) if threads else 1
     n = nx * ny * nz
-    return {"value": n * S / t, "unit": "voxel-iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first outer iteration with {S} inner iterations (setup included), "
-                      f"{t:.1f} s, FP64 NumPy/SciPy, host cores: {len(os.sched_getaffinity(0))}"}, S, f
+    what = (f"first {K} outer iterations x {S} inner iterations" if K > 1
+            else f"first outer iteration with {S} inner iterations")
+    return {"value": n * K * S / t, "unit": "voxel-iter/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{what} (setup included), {t:.1f} s, FP64 NumPy/SciPy, "
+                      f"host cores: {len(os.sched_getaffinity(0))}"}, K, S, f
 
 
 def _counter_per_dispatch(folder, counter, match):
-    """Per-dispatch values of one rocprofv3 counter for kernels whose name satisfies match."""
+    """{kernel name: per-dispatch values} of one rocprofv3 counter, for kernels whose (short)
+    name satisfies match."""
     import csv
     import glob
     vals = {}
@@ -118,55 +126,63 @@ def _counter_per_dispatch(folder, counter, match):
     for fn in files:
         with open(fn, newline="") as fh:
             for row in csv.DictReader(fh):
-                if row.get("Counter_Name") != counter or not match(row.get("Kernel_Name", "")):
+                name = _short_kernel(row.get("Kernel_Name", ""))
+                if row.get("Counter_Name") != counter or not match(name):
                     continue
                 key = (fn, row.get("Dispatch_Id") or row.get("Correlation_Id"))
-                vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
-    return list(vals.values())
+                d = vals.setdefault(name, {})
+                d[key] = d.get(key, 0.0) + float(row["Counter_Value"])
+    return {k: list(v.values()) for k, v in vals.items()}
+
+
+def _short_kernel(full):
+    """'void plsqr::k_gemv_rows<2>(plsqr::InstDesc* const*, int, int)' -> 'k_gemv_rows<2>'."""
+    s = full.split("(")[0].replace("void ", "").strip()
+    return s.split("::")[-1] if "::" in s.split("<")[0] else s
 
 
 def write_traffic(args, out=TRAFFIC_FILE):
-    """HBM bytes per launch of one kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per
-    dispatch), each scaled so that a plain 1 GiB device copy reads and writes 1 GiB."""
+    """HBM bytes per launch of each template variant of one kernel (e.g. every k_gemv_rows<R>
+    the autotuner ran) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), each
+    scaled so that a plain 1 GiB device copy reads and writes 1 GiB."""
     import re
     if not args.traffic_kernel:
         raise SystemExit("--write-traffic needs --traffic-kernel")
-    name = args.traffic_kernel
-    base = name.split("<")[0]
+    base = args.traffic_kernel.split("<")[0]
 
     def is_kernel(k):
-        k = k.replace(" ", "")
-        return re.search(r"(^|[:\s])" + re.escape(name.replace(" ", "")) + r"(\(|$)", k) is not None
-
-    def is_copy(k):
-        return "copyBuffer" in k
+        return k == base or k.startswith(base + "<")
 
     fdir, wdir, cfdir, cwdir = args.write_traffic
     fetch = _counter_per_dispatch(fdir, "FETCH_SIZE", is_kernel)
     write = _counter_per_dispatch(wdir, "WRITE_SIZE", is_kernel)
-    cfetch = _counter_per_dispatch(cfdir, "FETCH_SIZE", is_copy)
-    cwrite = _counter_per_dispatch(cwdir, "WRITE_SIZE", is_copy)
+    cfetch = sum(_counter_per_dispatch(cfdir, "FETCH_SIZE", lambda k: "copyBuffer" in k).values(), [])
+    cwrite = sum(_counter_per_dispatch(cwdir, "WRITE_SIZE", lambda k: "copyBuffer" in k).values(), [])
     if not (fetch and write and cfetch and cwrite):
         raise SystemExit("a counter pass holds no matching dispatch")
     gib_kib = float(1 << 20)
     fscale = gib_kib / (sum(cfetch) / len(cfetch))
     wscale = gib_kib / (sum(cwrite) / len(cwrite))
-    f_kib = sum(fetch) / len(fetch)
-    w_kib = sum(write) / len(write)
-    fb, wb = f_kib * 1024 * fscale, w_kib * 1024 * wscale
-    m = re.search(r"<(\d+)>", name)
-    rec = {"workload": args.workload, "kernel": name, "gemv_rows": int(m.group(1)) if m else None,
+    variants = {}
+    for name in sorted(set(fetch) & set(write)):
+        f_kib = sum(fetch[name]) / len(fetch[name])
+        w_kib = sum(write[name]) / len(write[name])
+        fb, wb = f_kib * 1024 * fscale, w_kib * 1024 * wscale
+        m = re.search(r"<(\d+)>", name)
+        key = m.group(1) if m else name
+        variants[key] = {"kernel": name, "launches": len(fetch[name]),
+                         "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
+                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                         "bytes_per_launch": fb + wb}
+        print(f"{name}: {len(fetch[name])} launches; FETCH_SIZE {f_kib:.1f} KiB raw x {fscale:.5f}, "
+              f"WRITE_SIZE {w_kib:.1f} KiB raw x {wscale:.5f} -> {(fb + wb) / 1e9:.4f} GB per launch")
+    rec = {"workload": args.workload, "kernel": base, "variants": variants,
            "source_sha": kernel_source_hash(), "source_files": list(DENSE_KERNEL_SOURCES),
-           "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
-           "launches": len(fetch),
            "copy_calibration": {"bytes": 1 << 30, "fetch_kib_raw": sum(cfetch) / len(cfetch),
                                 "write_kib_raw": sum(cwrite) / len(cwrite), "fetch_scale": fscale,
-                                "write_scale": wscale, "launches": len(cfetch)},
-           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb}
+                                "write_scale": wscale, "launches": len(cfetch)}}
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
-    print(f"{base}: {len(fetch)} launches; FETCH_SIZE {f_kib:.1f} KiB raw x {fscale:.5f}, "
-          f"WRITE_SIZE {w_kib:.1f} KiB raw x {wscale:.5f} -> {(fb + wb) / 1e9:.4f} GB per launch")
     print(json.dumps(rec))
 
 
@@ -268,9 +284,10 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if (tr.get("source_sha") == kernel_source_hash() and tr.get("workload") == args.workload
-                    and tr.get("gemv_rows") == settings.get("tune_gemv_rows")):
-                traffic = tr.get("bytes_per_launch")
+            var = tr.get("variants", {}).get(str(settings.get("tune_gemv_rows")))
+            if tr.get("source_sha") == kernel_source_hash() and tr.get("workload") == args.workload \
+                    and var is not None:
+                traffic = var["bytes_per_launch"]
         except (OSError, ValueError):
             traffic = None
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; forward product avg "
@@ -300,11 +317,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
-        cb, S, f_ref = cpu_baseline(p)
+        cb, K, S, f_ref = cpu_baseline(p)
         out["cpu_baseline"] = cb
         # the same sample on the GPU, for a parity figure at full size
         import dataclasses
-        q = dataclasses.replace(p, outer=1, inner=S)
+        q = dataclasses.replace(p, outer=K, inner=S)
         st, _ = eng.wait(eng.submit(op, problem_struct(q, knobs=settings), g, f))
         assert st == 0
         fg = f.cpu().numpy().astype(np.float64).reshape(f_ref.shape)

@@ -30,23 +30,29 @@ def _csv(folder, rows):
 def test_write_traffic_scales_by_copy(tmp_path):
     k2 = "void plsqr::k_gemv_rows<2>(plsqr::InstDesc* const*, int, int)"
     k4 = "void plsqr::k_gemv_rows<4>(plsqr::InstDesc* const*, int, int)"
-    # two dispatches of the kernel (one of them split over two rows), one of another variant
+    other = "void plsqr::k_gemv_cols(plsqr::InstDesc* const*)"
+    # two dispatches of <2> (one of them split over two rows), one of <4>, one unrelated kernel
     _csv(tmp_path / "f", [(1, k2, "FETCH_SIZE", 1000.0), (2, k2, "FETCH_SIZE", 600.0),
-                          (2, k2, "FETCH_SIZE", 600.0), (3, k4, "FETCH_SIZE", 9e9)])
-    _csv(tmp_path / "w", [(1, k2, "WRITE_SIZE", 10.0), (2, k2, "WRITE_SIZE", 30.0)])
+                          (2, k2, "FETCH_SIZE", 600.0), (3, k4, "FETCH_SIZE", 3000.0),
+                          (4, other, "FETCH_SIZE", 9e9)])
+    _csv(tmp_path / "w", [(1, k2, "WRITE_SIZE", 10.0), (2, k2, "WRITE_SIZE", 30.0),
+                          (3, k4, "WRITE_SIZE", 8.0)])
     cp = "__amd_rocclr_copyBuffer"
     _csv(tmp_path / "cf", [(1, cp, "FETCH_SIZE", 524288.0), (2, cp, "FETCH_SIZE", 524288.0)])
     _csv(tmp_path / "cw", [(1, cp, "WRITE_SIZE", 1048576.0)])
     args = argparse.Namespace(write_traffic=[str(tmp_path / d) for d in ("f", "w", "cf", "cw")],
-                              traffic_kernel="k_gemv_rows<2>", workload="c2")
+                              traffic_kernel="k_gemv_rows", workload="c2")
     out = tmp_path / "traffic.json"
     bench.write_traffic(args, out=str(out))
     rec = json.load(open(out))
-    assert rec["launches"] == 2 and rec["gemv_rows"] == 2
+    assert set(rec["variants"]) == {"2", "4"}
+    v2, v4 = rec["variants"]["2"], rec["variants"]["4"]
+    assert v2["launches"] == 2 and v4["launches"] == 1
     assert rec["copy_calibration"]["fetch_scale"] == pytest.approx(2.0)
     assert rec["copy_calibration"]["write_scale"] == pytest.approx(1.0)
-    assert rec["fetch_bytes_per_launch"] == pytest.approx(1100.0 * 1024 * 2.0)
-    assert rec["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
+    assert v2["fetch_bytes_per_launch"] == pytest.approx(1100.0 * 1024 * 2.0)
+    assert v2["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
+    assert v4["bytes_per_launch"] == pytest.approx(3000.0 * 1024 * 2.0 + 8.0 * 1024)
     assert rec["source_sha"] == bench.kernel_source_hash()
 
 
