@@ -70,6 +70,39 @@ __device__ __forceinline__ void block_partial(const InstDesc &D, int epi, double
   }
 }
 
+// The epilogue operand of output j (u for EPI_FWD, p for EPI_ADJ, g for EPI_RESID), loaded
+// ahead of time so that its latency overlaps the input loads; epilogue_pre then does
+// epilogue()'s arithmetic with it.
+__device__ __forceinline__ const float *pre_operand(const InstDesc &D, int epi) {
+  return epi == EPI_FWD ? sld(D.u) : epi == EPI_ADJ ? sld(D.p) : epi == EPI_RESID ? sld(D.g) : nullptr;
+}
+
+__device__ __forceinline__ void epilogue_pre(const InstDesc &D, int epi, long long j, float y,
+                                             float pre, float *out, double &dot) {
+  const double *sc = sld(D.sc);
+  switch (epi) {
+    case EPI_FWD: {
+      const float c1 = (float)sc[SC_SV], c2 = (float)(sc[SC_ALPHA] * sc[SC_SU]);
+      const float un = c1 * y - c2 * pre;
+      sld(D.u)[j] = un;
+      dot = (double)un * (double)un;
+      break;
+    }
+    case EPI_ADJ: {
+      const float c1 = (float)sc[SC_SU], c2 = (float)(sc[SC_BETA] * sc[SC_SV]);
+      sld(D.p)[j] = c1 * y - c2 * pre;
+      break;
+    }
+    case EPI_ADJ_INIT: sld(D.p)[j] = (float)sc[SC_SU] * y; break;
+    case EPI_RESID: {
+      const double e = (double)pre - (double)y;
+      dot = e * e;
+      break;
+    }
+    default: out[j] = y; break;
+  }
+}
+
 // Tile handled by this block. Workgroups are dealt to the 8 XCDs round-robin; when the grid
 // splits evenly, consecutive tiles are given to blocks on the same XCD, so the halo rows that
 // neighbouring tiles share are found in that XCD's L2.
@@ -278,9 +311,17 @@ __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, i
       }
     }
   }
+  const int x = tx * kStripX + lx;
+  const long long base = obase + x;
+  const float *pre_src = pre_operand(D, epi);
+  float pre[kOut];
+#pragma unroll
+  for (int q = 0; q < kOut; ++q) {
+    const int a = a0 + la * kOut + q;
+    pre[q] = (pre_src && t < tiles && x < nx && a < na) ? pre_src[base + (long long)a * sa] : 0.f;
+  }
   __syncthreads();
   double dot = 0.0;
-  const int x = tx * kStripX + lx;
   if (t < tiles && x < nx) {
     const int q0 = la * kOut;
     const int nwin = kOut + 2 * r;
@@ -299,13 +340,159 @@ __global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, i
       }
     }
     float *dst = vec_of(D, dst_sel);
-    const long long base = obase + x;
 #pragma unroll
     for (int q = 0; q < kOut; ++q) {
       const int a = a0 + q0 + q;
       if (a < na) {
         double dq = 0.0;
-        epilogue(D, epi, base + (long long)a * sa, acc[q], dst, dq);
+        epilogue_pre(D, epi, base + (long long)a * sa, acc[q], pre[q], dst, dq);
+        dot += dq;
+      }
+    }
+  }
+  block_partial(D, epi, dot);
+}
+
+// Fused x and y passes (nx a multiple of 4, ny > 1): a block of 256 threads owns an output
+// tile of kStripX x-columns by kTileY rows of one z-plane. It stages the input rows
+// [y0 - r, y0 + kTileY + r) and columns [x0 - R4, x0 + kStripX + R4) in LDS (zeros outside the
+// grid), runs the x pass over all those rows into a second LDS tile (4 outputs per task from a
+// register window, as k_blur_x4), then the y pass from that tile (as k_blur_strip). The
+// intermediate is rounded to FP32 exactly as the separate passes store it, so the result is
+// the same as the x pass followed by the y pass; the intermediate never goes to HBM.
+constexpr int kTileY = 16;
+constexpr int kTileCols = kStripX + 2 * kR4Max;                 // staged columns
+constexpr int kTileRows = kTileY + 2 * PLSQR_MAX_RADIUS;        // staged rows
+
+template <int kShift>
+__device__ __forceinline__ void xy_xphase(const float (*tile)[kTileCols], float (*mid)[kStripX],
+                                          const float *w, int r, int rows) {
+  const int R4 = r + kShift;
+  const int ng = 1 + R4 / 2;
+  const int ntaps = 2 * r + 1;
+  for (int q = threadIdx.x; q < rows * (kStripX / 4); q += kBlock) {
+    const int row = q / (kStripX / 4), g = q % (kStripX / 4);
+    float win[kWin];
+#pragma unroll
+    for (int k = 0; k < kWinGroups; ++k) {
+      V4 v = {};
+      if (k < ng) {
+        const float4 t = *reinterpret_cast<const float4 *>(&tile[row][4 * g + 4 * k]);
+        v.v[0] = t.x; v.v[1] = t.y; v.v[2] = t.z; v.v[3] = t.w;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) win[4 * k + e] = v.v[e];
+    }
+#pragma unroll
+    for (int e = 4 * kWinGroups; e < kWin; ++e) win[e] = 0.f;
+    V4 y = {};
+#pragma unroll
+    for (int k = 0; k < kMaxTaps; ++k) {
+      if (k < ntaps) {
+        const float wk = w[k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (kShift + e + k < kWin) y.v[e] += wk * win[kShift + e + k];
+      }
+    }
+    *reinterpret_cast<float4 *>(&mid[row][4 * g]) = make_float4(y.v[0], y.v[1], y.v[2], y.v[3]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_blur_xy(InstDesc *const *descs, int src_sel,
+                                                   int dst_sel, int adj, int epi) {
+  constexpr int kOut = kTileY / 4;
+  const InstDesc &D = inst(descs);
+  __shared__ __align__(16) float tile[kTileRows][kTileCols];
+  __shared__ __align__(16) float mid[kTileRows][kStripX];
+  __shared__ float w[kMaxTaps];
+  const int r = sld(D.radius);
+  const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
+  const int tx_n = (nx + kStripX - 1) / kStripX, ty_n = (ny + kTileY - 1) / kTileY;
+  const long long tiles = (long long)tx_n * ty_n * nz;
+  const long long t = xcd_tile();
+  if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
+  int tx = 0, ty = 0, z = 0;
+  if (t < tiles) {
+    tx = (int)(t % tx_n);
+    const long long rest = t / tx_n;
+    ty = (int)(rest % ty_n);
+    z = (int)(rest / ty_n);
+  }
+  const int x0 = tx * kStripX, y0 = ty * kTileY;
+  const int R4 = (r + 3) & ~3;
+  const int rows = kTileY + 2 * r;
+  const int cols4 = (kStripX + 2 * R4) / 4;
+  const float *__restrict__ src = vec_of(D, src_sel);
+  const long long zbase = (long long)z * nx * ny;
+  if (t < tiles) {
+    for (int q0 = threadIdx.x; q0 < rows * cols4; q0 += 4 * kBlock) {
+      V4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * kBlock;
+        const int row = q / cols4, c4 = q % cols4;
+        const int y = y0 - r + row, xg = x0 - R4 + 4 * c4;
+        v[u] = V4{};
+        if (q < rows * cols4 && y >= 0 && y < ny && xg >= 0 && xg < nx)
+          v[u] = ld4(src + zbase + (long long)y * nx + xg);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * kBlock;
+        if (q < rows * cols4) {
+          const int row = q / cols4, c4 = q % cols4;
+          *reinterpret_cast<float4 *>(&tile[row][4 * c4]) =
+              make_float4(v[u].v[0], v[u].v[1], v[u].v[2], v[u].v[3]);
+        }
+      }
+    }
+  }
+  const int lx = threadIdx.x & (kStripX - 1), la = threadIdx.x / kStripX;
+  const int x = x0 + lx;
+  const float *pre_src = pre_operand(D, epi);
+  float pre[kOut];
+#pragma unroll
+  for (int q = 0; q < kOut; ++q) {
+    const int y = y0 + la * kOut + q;
+    pre[q] = (pre_src && t < tiles && x < nx && y < ny) ? pre_src[zbase + (long long)y * nx + x] : 0.f;
+  }
+  __syncthreads();
+  if (t < tiles) {
+    switch (R4 - r) {
+      case 0: xy_xphase<0>(tile, mid, w, r, rows); break;
+      case 1: xy_xphase<1>(tile, mid, w, r, rows); break;
+      case 2: xy_xphase<2>(tile, mid, w, r, rows); break;
+      default: xy_xphase<3>(tile, mid, w, r, rows); break;
+    }
+  }
+  __syncthreads();
+  double dot = 0.0;
+  if (t < tiles && x < nx) {
+    const int q0 = la * kOut;
+    const int nwin = kOut + 2 * r;
+    float acc[kOut];
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) acc[q] = 0.f;
+#pragma unroll
+    for (int m = 0; m < kOut + 2 * PLSQR_MAX_RADIUS; ++m) {
+      if (m < nwin) {
+        // the x pass leaves zeros in rows outside the grid (their inputs were zeros)
+        const float v = mid[q0 + m][lx];
+#pragma unroll
+        for (int q = 0; q < kOut; ++q) {
+          const int k = m - q;
+          if (k >= 0 && k <= 2 * r) acc[q] += w[k] * v;
+        }
+      }
+    }
+    float *dst = vec_of(D, dst_sel);
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+      const int y = y0 + q0 + q;
+      if (y < ny) {
+        double dq = 0.0;
+        epilogue_pre(D, epi, zbase + (long long)y * nx + x, acc[q], pre[q], dst, dq);
         dot += dq;
       }
     }
@@ -329,6 +516,12 @@ int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx
   const unsigned g = (unsigned)((n + kXTile - 1) / kXTile);
   LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);
   return (int)g;
+}
+int launch_blur_xy(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int src,
+                   int dst, int adj, int epi) {
+  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((ny + kTileY - 1) / kTileY) * nz;
+  LAUNCH_B(k_blur_xy, (unsigned)tiles, B, d, src, dst, adj, epi);
+  return (int)tiles;
 }
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
                       int src, int dst, int adj, int epi, int depth) {

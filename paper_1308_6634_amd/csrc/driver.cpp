@@ -174,12 +174,17 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
   for (int a = 0; a < 3; ++a)
     if (ext[a] > 1) axes[na++] = a;
   if (na == 0) axes[na++] = 0;
+  // the x and y passes run as one kernel when rows split into 16-byte groups
+  const bool fuse_xy = (H.nx % 4 == 0) && na >= 2 && axes[0] == 0 && axes[1] == 1;
   int cur = src, np = 0;
   for (int i = 0; i < na; ++i) {
-    const bool last = (i == na - 1);
+    if (fuse_xy && i == 1) continue;
+    const bool last = (i == na - 1) || (fuse_xy && i == 0 && na == 2);
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
     const int e = last ? epi : EPI_STORE;
-    if (axes[i] == 0)
+    if (fuse_xy && i == 0)
+      np = launch_blur_xy(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, cur, dst, adj, e);
+    else if (axes[i] == 0)
       np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e);
     else
       np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,

@@ -12,7 +12,7 @@ namespace plsqr {
 enum LevelBuf : int { LB_X = 0, LB_B, LB_R, LB_T, LB_S };
 
 // One-workgroup V-cycle tail: threads, and the largest level it takes over.
-constexpr int kTailBlock = 512;
+constexpr int kTailBlock = 1024;
 constexpr long long kTailCells = 4096;
 
 void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n);
@@ -70,6 +70,9 @@ int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx
                   int adj, int epi);
 int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
                       int src, int dst, int adj, int epi, int depth);
+// x and y passes in one kernel (nx % 4 == 0, ny > 1)
+int launch_blur_xy(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int src,
+                   int dst, int adj, int epi);
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
                      int rows);
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
