@@ -115,15 +115,15 @@ __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, i
   L.dinv[j] = 1.0f / d;
 }
 
-// Assemble the coarsest operator densely in FP64 and factor it (lower Cholesky, in
-// place). One block per instance.
-__global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
-  const InstDesc &D = inst(descs);
-  const int l = sld(D.levels) - 1;
-  const LevelDesc L = level_of(D, l);
-  const int n = (int)L.n;
-  double *__restrict__ A = sld(D.cfac);
-  for (long long i = threadIdx.x; i < (long long)n * n; i += kBlock) A[i] = 0.0;
+// Assemble the coarsest operator densely in FP64, factor it (lower Cholesky, right-looking,
+// in place) and form its explicit inverse A^{-1} = L^{-T} L^{-1}, so that each V-cycle's
+// coarsest solve is one parallel matrix-vector product. at(i, j) is the working matrix: its
+// lower triangle holds L, and L^{-1} (formed column by column, one thread per column) is kept
+// transposed in the strict upper triangle with its diagonal in dv. A^{-1} goes to Ainv.
+template <class At, class Dv>
+__device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const LevelDesc &L, int l,
+                                                   int n, At at, Dv dv, double *Ainv, int &bad) {
+  for (long long i = threadIdx.x; i < (long long)n * n; i += kBlock) at((int)(i / n), (int)(i % n)) = 0.0;
   __syncthreads();
   for (int J = threadIdx.x; J < n; J += kBlock) {
     const Coord c = coord_of(J, L.nx, L.ny);
@@ -136,36 +136,34 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
       if (pos[a] + 1 < ext[a]) {
         const double w = face_w(D, l, a, J, c);
         diag += w;
-        A[(long long)J * n + J + strides[a]] = -w;
+        at(J, J + strides[a]) = -w;
       }
       if (pos[a] > 0) {
         Coord cm = c;
         if (a == 0) cm.x -= 1; else if (a == 1) cm.y -= 1; else cm.z -= 1;
         const double w = face_w(D, l, a, J - strides[a], cm);
         diag += w;
-        A[(long long)J * n + J - strides[a]] = -w;
+        at(J, J - strides[a]) = -w;
       }
     }
-    A[(long long)J * n + J] = diag;
+    at(J, J) = diag;
   }
-  __syncthreads();
-  __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
     if (threadIdx.x == 0) {
-      double d = A[(long long)k * n + k];
+      double d = at(k, k);
       if (!(d > 0.0)) { bad = 1; d = 1.0; }
-      A[(long long)k * n + k] = sqrt(d);
+      at(k, k) = sqrt(d);
     }
     __syncthreads();
-    const double piv = A[(long long)k * n + k];
-    for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) A[(long long)i * n + k] /= piv;
+    const double piv = at(k, k);
+    for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) at(i, k) /= piv;
     __syncthreads();
     const int rem = n - k - 1;
     for (long long q = threadIdx.x; q < (long long)rem * rem; q += kBlock) {
       const int i = k + 1 + (int)(q / rem), jj = k + 1 + (int)(q % rem);
-      if (jj <= i) A[(long long)i * n + jj] -= A[(long long)i * n + k] * A[(long long)jj * n + k];
+      if (jj <= i) at(i, jj) -= at(i, k) * at(jj, k);
     }
     __syncthreads();
   }
@@ -173,26 +171,48 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
     sld(D.sc)[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
     sld(D.sc)[SC_STOP] = 1.0;
   }
-  // Explicit inverse A^{-1} = L^{-T} L^{-1}, so that each V-cycle's coarsest solve is one
-  // parallel matrix-vector product. L^{-1} overwrites the strictly-upper part's mirror:
-  // it is formed column by column (one thread per column) into the second n x n block.
-  double *__restrict__ Li = A + (long long)n * n;
+  // L^{-1}[k][j] (k >= j) is dv[j] on the diagonal and at(j, k) below it
+  auto li = [&](int k, int j) -> double { return k == j ? dv[j] : at(j, k); };
   for (int j = threadIdx.x; j < n; j += kBlock) {
-    for (int i = 0; i < j; ++i) Li[(long long)i * n + j] = 0.0;
     for (int i = j; i < n; ++i) {
       double sacc = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) sacc -= A[(long long)i * n + k] * Li[(long long)k * n + j];
-      Li[(long long)i * n + j] = sacc / A[(long long)i * n + i];
+      for (int k = j; k < i; ++k) sacc -= at(i, k) * li(k, j);
+      const double v = sacc / at(i, i);
+      if (i == j) dv[j] = v; else at(j, i) = v;
     }
   }
   __syncthreads();
-  // A^{-1}[i][j] = sum_{k >= max(i,j)} Li[k][i] Li[k][j], stored over the factor block
+  // A^{-1}[i][j] = sum_{k >= max(i,j)} L^{-1}[k][i] L^{-1}[k][j]
   for (long long q = threadIdx.x; q < (long long)n * n; q += kBlock) {
     const int i = (int)(q / n), j = (int)(q % n);
     const int k0 = i > j ? i : j;
     double sacc = 0.0;
-    for (int k = k0; k < n; ++k) sacc += Li[(long long)k * n + i] * Li[(long long)k * n + j];
-    A[(long long)n * n * 2 + q] = sacc;
+    for (int k = k0; k < n; ++k) sacc += li(k, i) * li(k, j);
+    Ainv[q] = sacc;
+  }
+}
+
+// One block per instance. Coarsest grids of up to kCoarseLds cells are factored in LDS, larger
+// ones in the instance's FP64 workspace (cfac: working matrix, L^{-1} diagonal, A^{-1}).
+constexpr int kCoarseLds = 64;
+__global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const int l = sld(D.levels) - 1;
+  const LevelDesc L = level_of(D, l);
+  const int n = (int)L.n;
+  double *__restrict__ W = sld(D.cfac);
+  double *Ainv = W + (long long)n * n * 2;
+  __shared__ double S[kCoarseLds * kCoarseLds];
+  __shared__ double sdv[kCoarseLds];
+  __shared__ int bad;
+  if (n <= kCoarseLds) {
+    coarse_factor_body(D, L, l, n, [&](int i, int j) -> double & { return S[i * n + j]; },
+                       sdv, Ainv, bad);
+  } else {
+    double *gdv = W + (long long)n * n;
+    coarse_factor_body(D, L, l, n,
+                       [&](int i, int j) -> double & { return W[(long long)i * n + j]; }, gdv,
+                       Ainv, bad);
   }
 }
 
