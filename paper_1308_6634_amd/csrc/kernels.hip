@@ -444,44 +444,6 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
   }
 }
 
-// Restriction of the residual: b_{l+1}[J] = sum over children j of J of (b - A_l x)_j,
-// or of a stored residual r_l when use_r.
-__global__ void __launch_bounds__(kBlock) k_restrict(InstDesc *const *descs, int l, int x_sel,
-                                                    int use_r) {
-  const InstDesc &D = inst(descs);
-  const LevelDesc F = level_of(D, l);
-  const LevelDesc Cl = level_of(D, l + 1);
-  const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (J >= Cl.n) return;
-  const Coord cc = coord_of(J, Cl.nx, Cl.ny);
-  const int cz = (F.nz > 1) ? 2 : 1;
-  const float *__restrict__ x = lvbuf(F, x_sel);
-  float s = 0.f;
-  for (int dz = 0; dz < cz; ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        Coord fc;
-        fc.x = 2 * cc.x + dx;
-        fc.y = 2 * cc.y + dy;
-        fc.z = cz * cc.z + dz;
-        const long long j = fc.x + (long long)F.nx * (fc.y + (long long)F.ny * fc.z);
-        s += use_r ? F.r[j] : F.b[j] - stencil(D, l, x, j, fc);
-      }
-  Cl.b[J] = s;
-}
-
-// Prolongation: x_l[j] += x_{l+1}[parent(j)].
-__global__ void __launch_bounds__(kBlock) k_prolong(InstDesc *const *descs, int l, int x_sel) {
-  const InstDesc &D = inst(descs);
-  const LevelDesc F = level_of(D, l);
-  const LevelDesc Cl = level_of(D, l + 1);
-  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= F.n) return;
-  const Coord c = coord_of(j, F.nx, F.ny);
-  const int cz = (F.nz > 1) ? 2 : 1;
-  const long long J = (c.x >> 1) + (long long)Cl.nx * ((c.y >> 1) + (long long)Cl.ny * (c.z / cz));
-  lvbuf(F, x_sel)[j] += Cl.x[J];
-}
 
 // ------------------------------------------------------------------------------------
 // Krylov recurrences: copies, reductions, rotations, updates (section 3.2, Algorithm 2)
@@ -743,13 +705,6 @@ void launch_cheb_start_prolong(hipStream_t st, InstDesc *const *d, int B, int l,
 void launch_restrict_fine(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
                           int nchild, int x_sel, int use_r) {
   LAUNCH(k_restrict_fine, blocks_for(n_coarse * nchild), B, d, l, x_sel, use_r);
-}
-void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
-                     int x_sel, int use_r) {
-  LAUNCH(k_restrict, blocks_for(n_coarse), B, d, l, x_sel, use_r);
-}
-void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel) {
-  LAUNCH(k_prolong, blocks_for(n_l), B, d, l, x_sel);
 }
 int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m) {
   const unsigned g = blocks_for(m);

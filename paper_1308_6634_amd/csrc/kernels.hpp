@@ -30,9 +30,6 @@ void launch_cheb_start(hipStream_t st, InstDesc *const *d, int B, int l, long lo
 int launch_cheb_step(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int set_x,
                      int update_r, int last, int d_sel, int dn_sel, int step, int want_dot,
                      int add_prolong = 0);
-void launch_restrict(hipStream_t st, InstDesc *const *d, int B, int l, long long n_coarse,
-                     int x_sel, int use_r);
-void launch_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int x_sel);
 int launch_jacobi_first2(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int dst,
                          int want_dot);
 int launch_jacobi_prolong(hipStream_t st, InstDesc *const *d, int B, int l, long long n_l, int src,
