@@ -70,14 +70,19 @@ def dominant_bytes(p):
     if p.op_kind == "dense":
         m = p.A.shape[0]
         return 4 * m * n + 4 * n + 8 * m, "k_gemv_rows (dense forward product A v, u update)"
-    # blur: the forward product is one 1D pass per axis of extent > 1; each pass reads and
-    # writes one vector (halo re-reads come from cache) and the last one also reads u
-    # (u <- sv A v - alpha su u), so 2 na + 1 vectors move per product
+    # blur: the forward product is one 1D pass per axis of extent > 1, the x and y passes fused
+    # into one kernel when nx % 4 == 0; each kernel reads and writes one vector (halo re-reads
+    # come from cache) and the last one also reads u (u <- sv A v - alpha su u), so
+    # 2 k + 1 vectors move per product for k kernels
     na = max(1, sum(1 for e in (nx, ny, nz) if e > 1))
-    return 4 * n * (2 * na + 1), f"k_blur_x + k_blur_strip ({na}-pass forward blur product)"
+    fused = nx % 4 == 0 and nx > 1 and ny > 1
+    k = na - 1 if fused else na
+    names = ("k_blur_xy" + (" + k_blur_strip" if nz > 1 else "")) if fused else \
+        ("k_blur_x4" if nx % 4 == 0 else "k_blur_x") + (" + k_blur_strip" if na > 1 else "")
+    return 4 * n * (2 * k + 1), f"{names} (forward blur product, {k} kernel{'s' if k > 1 else ''})"
 
 
-def cpu_baseline(p, target_s=15.0):
+def cpu_baseline(p, target_s=20.0):
     """The FP64 oracle on a bounded sample of about target_s seconds: the first K outer
     iterations with all their inner iterations when one outer iteration fits the budget,
     otherwise the first outer iteration with S inner iterations. Returns (record, K, S, f)."""

@@ -62,9 +62,13 @@ def test_dominant_bytes():
 
     p = P()
     p.dims, p.op_kind = (8, 8, 8), "blur"
-    assert bench.dominant_bytes(p)[0] == 4 * 512 * 7        # 3 passes: 3 reads + u, 3 writes
+    assert bench.dominant_bytes(p)[0] == 4 * 512 * 5        # fused xy + z: 2 reads + u, 2 writes
+    p.dims = (6, 8, 8)
+    assert bench.dominant_bytes(p)[0] == 4 * 384 * 7        # 3 separate passes
     p.dims = (16, 8, 1)
-    assert bench.dominant_bytes(p)[0] == 4 * 128 * 5
+    assert bench.dominant_bytes(p)[0] == 4 * 128 * 3        # one fused kernel
+    p.dims = (10, 8, 1)
+    assert bench.dominant_bytes(p)[0] == 4 * 80 * 5
     import numpy as np
     p.dims, p.op_kind, p.A = (4, 4, 2), "dense", np.zeros((10, 32), np.float32)
     assert bench.dominant_bytes(p)[0] == 4 * 10 * 32 + 4 * 32 + 8 * 10
