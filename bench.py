@@ -207,6 +207,9 @@ def main():
                     help="c4 only: BF16 product mode of the batched path")
     ap.add_argument("--plain-sample", type=int, default=2,
                     help="c4 only: instances run one at a time on the FP32 path for comparison")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="c3 only: run this many 128^3 instances (seeds 2, 3, ...) as one lockstep "
+                         "FP32 batch, so that every stencil and multigrid launch moves B vectors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) autotuning of tiling knobs before the warm-up")
@@ -245,6 +248,10 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.batch > 1:
+        if args.workload != "c3":
+            raise SystemExit("--batch applies to the c3 workload only")
+        return bench_c3_batch(args)
     p, desc = workload(args.workload)
     nx, ny, nz = p.dims
     n = nx * ny * nz
@@ -417,6 +424,73 @@ def bench_c4(args):
                                      "sample": f"{len(pl)} of the {B} instances, FP32 products",
                                      "s_per_instance": plain_s},
         "batched_over_plain": value / plain_value,
+    }
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3_batch(args):
+    """B reconstructions of the c3 workload (own phantom and noise per seed) advanced in
+    lockstep: one launch of every stencil, blur and multigrid kernel serves all B instances,
+    so each launch moves B times the single-instance bytes (for B >= 4 the vectors no longer
+    fit the 256 MB last-level cache)."""
+    import numpy as np
+    import torch
+    import gen
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct
+
+    B = args.batch
+    print(f"[bench] c3 batch: generating {B} instances", file=sys.stderr, flush=True)
+    probs = [gen.config_c3(seed=2 + i) for i in range(B)]
+    p0 = probs[0]
+    n = p0.n_x
+    _, desc = workload("c3")
+    eng = Engine(0)
+    settings = {}
+    if not args.no_tune:
+        from paper_1308_6634_amd import autotune
+        settings, _ = autotune.tune(p0, eng)
+        probs = [autotune.apply(p, settings) for p in probs]
+        print(f"[bench] autotuned on instance 0: {settings}", file=sys.stderr, flush=True)
+    op = eng.blur_operator(p0.dims, p0.taps)
+    gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda() for p in probs]
+    fs = [torch.zeros(n, device="cuda") for _ in probs]
+    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, knobs=settings) for p in probs]
+
+    def run_batch():
+        ts = eng.submit_batch(op, pbs, gs, fs)
+        res = [eng.wait(t) for t in ts]
+        for st, _ in res:
+            assert st == 0, P.plsqr_last_error(eng.handle)
+        return res
+
+    for _ in range(args.warmup):
+        run_batch()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [run_batch() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = B * n * p0.outer * p0.inner * args.steps / elapsed
+    r0 = [res[0][1] for res in results]
+    fwd_s = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1) / 1e3
+    nbytes, kname = dominant_bytes(p0)
+    nbytes *= B
+    achieved = nbytes / fwd_s / 1e9
+    out = {
+        "metric": "voxel-LSQR-iters/s", "value": value, "unit": "voxel-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c3 x {B} lockstep: {desc}; seeds 2..{1 + B}", "instances": B,
+                   "n_x": n, "n_y": n, "outer": p0.outer, "inner": p0.inner,
+                   "precision": "fp32 vectors, fp64 scalars", "autotuned": settings},
+        "roofline": {"bound": "hbm", "kernel": kname + f" over {B} instances", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": fwd_s * 1e3,
+                     "launches": int(sum(r.forward_launches for r in r0))},
     }
     eng.close()
     print(json.dumps(out), flush=True)

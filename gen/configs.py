@@ -55,6 +55,13 @@ class Problem:
     cheb_lo: float = 1.0 / 3.0
     cheb_hi: float = 2.0
     noise_sd: float = 0.0
+    delta: float = 0.0                # Euclidean norm of the noise actually drawn (noise level)
+    # adaptive stopping (off by default: fixed outer x inner counts)
+    stop_s4: bool = False             # stop MLSQR once ||g - A f_i|| <= eta * delta
+    eta: float = 1.1
+    stop_outer: bool = False          # stop the outer loop once R(f^k) no longer falls by
+    outer_rtol: float = 0.0           #   more than outer_rtol * R(f^{k-1}) (checked for k >=
+    outer_min: int = 3                #   outer_min)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -84,17 +91,17 @@ def auto_levels(dims, max_levels=16):
 
 def make_blur_problem(name, f_true, rng, sigma, radius, noise_frac, **kw):
     taps = ops.gaussian_taps(sigma, radius)
-    g, sd = ops.blur_data(rng, f_true, taps, noise_frac)
+    g, sd, delta = ops.blur_data(rng, f_true, taps, noise_frac)
     nz, ny, nx = f_true.shape
     return Problem(name=name, dims=(nx, ny, nz), f_true=f_true, g=g, op_kind="blur", taps=taps,
-                   noise_sd=sd, extra={"sigma": sigma}, **kw)
+                   noise_sd=sd, delta=delta, extra={"sigma": sigma}, **kw)
 
 
 def make_dense_problem(name, f_true, rng, A, noise_frac, **kw):
-    g, sd = ops.dense_data(rng, A, f_true, noise_frac)
+    g, sd, delta = ops.dense_data(rng, A, f_true, noise_frac)
     nz, ny, nx = f_true.shape
     return Problem(name=name, dims=(nx, ny, nz), f_true=f_true, g=g, op_kind="dense", A=A,
-                   noise_sd=sd, **kw)
+                   noise_sd=sd, delta=delta, **kw)
 
 
 def config_c1(seed=0, n=64, outer=10, inner=50):

@@ -101,12 +101,15 @@ def dense_sensitivity(n, mu=0.5, n_src_rings=4, n_det_rings=4, per_ring=16, thre
 
 
 def _add_noise(rng, clean, noise_frac):
+    """Returns (float32 data, noise standard deviation, Euclidean norm of the drawn noise)."""
     sd = noise_frac * float(np.max(np.abs(clean)))
-    return (clean + rng.normal(0.0, sd, size=clean.shape)).astype(np.float32), sd
+    e = rng.normal(0.0, sd, size=clean.shape)
+    return (clean + e).astype(np.float32), sd, float(np.linalg.norm(e))
 
 
 def blur_data(rng, f_true, taps, noise_frac):
-    """g = blur(f_true) + N(0, (noise_frac * max|blur f|)^2), float32, same shape as f_true."""
+    """g = blur(f_true) + N(0, (noise_frac * max|blur f|)^2), float32, same shape as f_true;
+    returns (g, noise sd, noise norm)."""
     w = np.asarray(taps, dtype=np.float64)
     clean = np.asarray(f_true, dtype=np.float64)
     for ax in range(3):

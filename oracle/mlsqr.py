@@ -19,6 +19,12 @@ Readings of points the paper leaves open:
 
 ``apply_Minv`` is any fixed SPD operator standing for M^{-1} (a V-cycle, an
 exact solve, or the identity, which gives plain damped LSQR).
+
+Stopping (Section 3.4): besides the iteration cap, the Morozov discrepancy
+principle S4 ends the iteration at the first i with ||g - A f_i|| <= eta * delta.
+The residual is formed here from its definition, one extra product with A per
+iteration, checked after the update of f (the test closes each loop pass of
+Algorithm 2).
 """
 
 import math
@@ -32,8 +38,11 @@ class NotSPD(ArithmeticError):
     pass
 
 
-def mlsqr(apply_A, apply_AT, apply_Minv, g, tau, iters, history=None):
-    """Run ``iters`` MLSQR iterations from f = 0; returns (f, iterations completed)."""
+def mlsqr(apply_A, apply_AT, apply_Minv, g, tau, iters, history=None, resid_stop=None):
+    """Run at most ``iters`` MLSQR iterations from f = 0; returns (f, iterations completed).
+
+    ``resid_stop`` (eta * delta of S4, or None): stop after the first iteration whose
+    iterate has ||g - A f_i|| <= resid_stop."""
     lam = math.sqrt(tau)
     g = np.asarray(g, dtype=np.float64)
     beta = float(np.linalg.norm(g))
@@ -87,7 +96,12 @@ def mlsqr(apply_A, apply_AT, apply_Minv, g, tau, iters, history=None):
         f = f + (phi / rho) * w
         w = v - (theta / rho) * w
         done = i
+        resid = None
+        if resid_stop is not None:
+            resid = float(np.linalg.norm(np.ravel(g) - np.ravel(apply_A(f))))
         if history is not None:
             history.append(dict(i=i, alpha=alpha, beta=beta, phibar=phibar, rho=rho, phi=phi,
-                                theta=theta, s1=s1))
+                                theta=theta, s1=s1, resid=resid))
+        if resid is not None and resid <= resid_stop:
+            break
     return f, done
