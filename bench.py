@@ -64,22 +64,21 @@ def workload(name):
 
 
 def dominant_bytes(p):
-    """Algorithmic HBM bytes of one dominant-kernel launch."""
+    """Algorithmic HBM bytes of one dominant-kernel launch (the forward product u <- A v - alpha u:
+    read A (dense), read v, read and write u), its name, and the bytes its kernels move."""
     nx, ny, nz = p.dims
     n = nx * ny * nz
     if p.op_kind == "dense":
         m = p.A.shape[0]
-        return 4 * m * n + 4 * n + 8 * m, "k_gemv_rows (dense forward product A v, u update)"
-    # blur: the forward product is one 1D pass per axis of extent > 1, the x and y passes fused
-    # into one kernel when nx % 4 == 0; each kernel reads and writes one vector (halo re-reads
-    # come from cache) and the last one also reads u (u <- sv A v - alpha su u), so
-    # 2 k + 1 vectors move per product for k kernels
-    na = max(1, sum(1 for e in (nx, ny, nz) if e > 1))
-    fused = nx % 4 == 0 and nx > 1 and ny > 1
-    k = na - 1 if fused else na
-    names = ("k_blur_xy" + (" + k_blur_strip" if nz > 1 else "")) if fused else \
-        ("k_blur_x4" if nx % 4 == 0 else "k_blur_x") + (" + k_blur_strip" if na > 1 else "")
-    return 4 * n * (2 * k + 1), f"{names} (forward blur product, {k} kernel{'s' if k > 1 else ''})"
+        b = 4 * m * n + 4 * n + 8 * m
+        return b, "k_gemv_rows (dense forward product A v, u update)", b
+    # blur: one 1D pass per axis of extent > 1; each pass reads and writes one vector (halo
+    # re-reads come from cache) and the last one also reads u, so 2 k + 1 vectors move for k
+    # passes, against 3 vectors (v in, u in and out) for the product itself
+    k = max(1, sum(1 for e in (nx, ny, nz) if e > 1))
+    names = ("k_blur_xg" if nx % 4 == 0 else "k_blur_x") + (" + k_blur_win" if k > 1 else "")
+    return 12 * n, f"{names} (forward blur product, {k} pass{'es' if k > 1 else ''})", \
+        4 * n * (2 * k + 1)
 
 
 def cpu_baseline(p, target_s=20.0):
@@ -210,6 +209,14 @@ def main():
     ap.add_argument("--batch", type=int, default=1,
                     help="c3 only: run this many 128^3 instances (seeds 2, 3, ...) as one lockstep "
                          "FP32 batch, so that every stencil and multigrid launch moves B vectors")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel eagerly (for hardware-counter profiling, which "
+                         "does not see kernels replayed from HIP graphs)")
+    ap.add_argument("--stop", action="store_true",
+                    help="c1-c3: also time the same reconstruction with the paper's adaptive stops "
+                         "(S4 with eta = 1.1 and the drawn noise norm as delta, the configured "
+                         "inner count as the cap; outer stop once R(f^k) stops decreasing, checked "
+                         "from k = 3) and compare its result with the fixed-count one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) autotuning of tiling knobs before the warm-up")
@@ -269,7 +276,8 @@ def main():
         op = eng.blur_operator(p.dims, p.taps)
     g = torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda()
     f = torch.zeros(n, dtype=torch.float32, device="cuda")
-    pb = problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, knobs=settings)
+    pb = problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS |
+                        (P.PLSQR_FLAG_NO_GRAPHS if args.no_graphs else 0), knobs=settings)
 
     for _ in range(args.warmup):
         st, _ = eng.wait(eng.submit(op, pb, g, f))
@@ -291,7 +299,7 @@ def main():
     adj_ms = sum(r.adjoint_ms for _, r in results)
     adj_n = sum(r.adjoint_launches for _, r in results)
     avg_fwd_s = fwd_ms / max(fwd_n, 1) / 1e3
-    nbytes, kname = dominant_bytes(p)
+    nbytes, kname, pass_bytes = dominant_bytes(p)
     achieved = nbytes / avg_fwd_s / 1e9 if avg_fwd_s > 0 else None
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -326,8 +334,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic, "bytes_per_launch": nbytes,
+                     "kernel_bytes_per_launch": pass_bytes,
                      "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)},
     }
+    if args.stop:
+        out["adaptive"] = adaptive_run(args, eng, op, p, settings, g, f)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
         cb, K, S, f_ref = cpu_baseline(p)
@@ -341,6 +352,40 @@ def main():
         out["parity_sample_rel_l2"] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
     eng.close()
     print(json.dumps(out), flush=True)
+
+
+def adaptive_run(args, eng, op, p, settings, g, f):
+    """The workload with the adaptive stops against its fixed-count result (already in f)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_1308_6634_amd.engine import problem_struct
+    q = dataclasses.replace(p, stop_s4=True, eta=1.1, stop_outer=True, outer_rtol=0.0, outer_min=3)
+    f_fixed = f.clone()
+    fa = torch.zeros_like(f)
+    pb = problem_struct(q, knobs=settings)
+    st, res = eng.wait(eng.submit(op, pb, g, fa))            # warm-up
+    assert st == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [eng.wait(eng.submit(op, pb, g, fa)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    res = results[-1][1]
+    inner = [int(res.inner_done[k]) for k in range(res.outer_done)]
+    n = p.n_x
+    nx, ny, nz = p.dims
+    truth = np.asarray(p.f_true, dtype=np.float64).ravel()
+    a = fa.cpu().numpy().astype(np.float64)
+    b = f_fixed.cpu().numpy().astype(np.float64)
+    return {"ms_per_reconstruction": el * 1e3, "outer_done": int(res.outer_done),
+            "inner_done": inner, "voxel_iters": n * sum(inner),
+            "voxel_iters_per_s": n * sum(inner) / el,
+            "fixed_count_voxel_iters": n * p.outer * p.inner,
+            "rel_l2_vs_fixed_count": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "rel_error_vs_truth": float(np.linalg.norm(a - truth) / np.linalg.norm(truth)),
+            "fixed_count_rel_error_vs_truth": float(np.linalg.norm(b - truth) / np.linalg.norm(truth)),
+            "rule": "S4 eta=1.1, delta=noise norm, inner cap as configured; outer stop rtol=0 from k=3"}
 
 
 def bench_c4(args):
@@ -456,7 +501,8 @@ def bench_c3_batch(args):
     op = eng.blur_operator(p0.dims, p0.taps)
     gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda() for p in probs]
     fs = [torch.zeros(n, device="cuda") for _ in probs]
-    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, knobs=settings) for p in probs]
+    flags = P.PLSQR_FLAG_TIME_PRODUCTS | (P.PLSQR_FLAG_NO_GRAPHS if args.no_graphs else 0)
+    pbs = [problem_struct(p, flags=flags, knobs=settings) for p in probs]
 
     def run_batch():
         ts = eng.submit_batch(op, pbs, gs, fs)
@@ -476,8 +522,9 @@ def bench_c3_batch(args):
     value = B * n * p0.outer * p0.inner * args.steps / elapsed
     r0 = [res[0][1] for res in results]
     fwd_s = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1) / 1e3
-    nbytes, kname = dominant_bytes(p0)
+    nbytes, kname, pass_bytes = dominant_bytes(p0)
     nbytes *= B
+    pass_bytes *= B
     achieved = nbytes / fwd_s / 1e9
     out = {
         "metric": "voxel-LSQR-iters/s", "value": value, "unit": "voxel-iter/s", "n_gpus": 1,
@@ -489,7 +536,8 @@ def bench_c3_batch(args):
                    "precision": "fp32 vectors, fp64 scalars", "autotuned": settings},
         "roofline": {"bound": "hbm", "kernel": kname + f" over {B} instances", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": fwd_s * 1e3,
+                     "traffic": None, "bytes_per_launch": nbytes,
+                     "kernel_bytes_per_launch": pass_bytes, "avg_launch_ms": fwd_s * 1e3,
                      "launches": int(sum(r.forward_launches for r in r0))},
     }
     eng.close()

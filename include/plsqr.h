@@ -11,7 +11,9 @@
  *     M = G^T diag(kappa) G + eps I   (G: forward differences, zero at the upper
  *                                      boundary, i.e. the Neumann condition of (1.12))
  * is replaced by one geometric-multigrid V-cycle, a fixed SPD operator (Section 4.2).
- * Iteration counts are fixed: `outer` lagged-diffusivity steps x `inner` MLSQR steps.
+ * Iteration counts are fixed (`outer` lagged-diffusivity steps x `inner` MLSQR steps)
+ * unless the adaptive stops of the paper are requested (PLSQR_FLAG_STOP_S4,
+ * PLSQR_FLAG_STOP_OUTER), which make the counts caps.
  *
  * Conventions
  *  - Grids are (nx, ny, nz), x fastest, float32, contiguous; nz == 1 is a 2D image.
@@ -73,8 +75,19 @@ enum {
 enum {
   PLSQR_FLAG_TIME_PRODUCTS = 1u << 0, /* time every launch of the forward/adjoint product
                                          kernels with HIP events; totals in plsqr_result */
-  PLSQR_FLAG_NO_GRAPHS = 1u << 1      /* launch every kernel eagerly instead of replaying the
+  PLSQR_FLAG_NO_GRAPHS = 1u << 1,     /* launch every kernel eagerly instead of replaying the
                                          inner iteration as a captured HIP graph */
+  PLSQR_FLAG_STOP_S4 = 1u << 2,       /* inner stop by the discrepancy principle S4 of
+                                         Section 3.4: MLSQR ends after the first step i with
+                                         ||g - A f_i|| <= eta * delta; `inner` stays the cap
+                                         on steps per outer iteration (Section 4.1) */
+  PLSQR_FLAG_STOP_OUTER = 1u << 3     /* outer stop of Algorithm 3 (step 5): after outer step
+                                         k >= outer_min, stop when
+                                         R(f^k) - R(f^{k-1}) >= -outer_rtol * R(f^{k-1}),
+                                         i.e. R no longer falls by more than the fraction
+                                         outer_rtol (Section 4.3 uses 0.15; Section 5.3 stops
+                                         once R stops decreasing, outer_rtol = 0); the result
+                                         is f^k, `outer` stays the cap */
 };
 
 #define PLSQR_MAX_LEVELS 12
@@ -111,7 +124,8 @@ typedef struct {
  *  reg, T        : regulariser r(t) and its parameter T > 0 (ignored for Tikhonov)
  *  tau >= 0      : prior weight; MLSQR damping is sqrt(tau) (Section 3.3)
  *  eps > 0       : shift making M = G^T diag(kappa) G + eps I positive definite
- *  outer, inner  : fixed iteration counts, 1 <= outer <= PLSQR_MAX_OUTER, inner >= 1
+ *  outer, inner  : iteration counts (caps under the stop flags), 1 <= outer <= PLSQR_MAX_OUTER,
+ *                  inner >= 1
  *  mg_levels     : number of grids (0: halve while every coarsened axis is even and
  *                  > 4); each coarsening halves nx, ny and (3D) nz, which must be even;
  *                  the coarsest grid must have <= PLSQR_MAX_COARSE cells
@@ -121,6 +135,14 @@ typedef struct {
  *                  post smoothing keeps the V-cycle symmetric (Section 4.2)
  *  precision     : PLSQR_PREC_*
  *  flags         : PLSQR_FLAG_*
+ *  eta, delta    : with PLSQR_FLAG_STOP_S4, the discrepancy level eta * delta of S4 (delta:
+ *                  the noise norm ||g - A f_true||, eta > 0, typically slightly above 1);
+ *                  the residual ||g - A f_i|| is tracked through the recurrences
+ *                  A w_{i+1} = A v_{i+1} - (theta/rho) A w_i, A f_i = A f_{i-1} + (phi/rho) A w_i
+ *                  on two extra n_y vectors, so no extra product with A is spent
+ *  outer_rtol,
+ *  outer_min     : with PLSQR_FLAG_STOP_OUTER, the tolerance and first outer step
+ *                  (2 <= outer_min) of the outer stop; ignored otherwise
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -138,20 +160,26 @@ typedef struct {
   /* performance knobs (0 = library default); they never change the method, only tiling:
    *  tune_gemv_rows   rows of A per block of the dense forward product (1, 2, 4 or 8)
    *  tune_col_chunks  row chunks of the dense adjoint product (1..64)
-   *  tune_strip_depth outputs per block along y/z in the blur passes (16, 32 or 64) */
+   *  tune_blur_window outputs per thread of the y/z blur passes (4, 8, 16 or 32; default 8)
+   *  tune_blur_xgroups 4-output groups per thread of the x blur pass (1, 2 or 4; default 2) */
   int32_t tune_gemv_rows;
   int32_t tune_col_chunks;
-  int32_t tune_strip_depth;
+  /* adaptive stopping (PLSQR_FLAG_STOP_S4, PLSQR_FLAG_STOP_OUTER) */
+  double eta, delta;
+  double outer_rtol;
+  int32_t outer_min;
+  int32_t tune_blur_window;
+  int32_t tune_blur_xgroups;
 } plsqr_problem;
 
 /* Completion record of one request (filled by plsqr_poll). */
 typedef struct {
   int32_t status;                     /* PLSQR_OK or the request's error code */
-  int32_t outer_done;                 /* outer iterations run */
+  int32_t outer_done;                 /* outer iterations run (< outer after an outer stop) */
   int32_t levels;                     /* multigrid levels used */
   int32_t reserved0;
   int32_t inner_done[PLSQR_MAX_OUTER];/* MLSQR steps completed per outer iteration
-                                         (< inner after an exact-termination stop) */
+                                         (< inner after an S4 or exact-termination stop) */
   double resid[PLSQR_MAX_OUTER];      /* ||g - A f^k|| per outer iteration k */
   double penalty[PLSQR_MAX_OUTER];    /* R(f^k) per outer iteration k */
   double submit_to_done_ms;           /* host wall time from plsqr_solve to completion

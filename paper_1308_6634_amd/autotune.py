@@ -1,6 +1,6 @@
 """Autotuner for the library's tiling knobs and the Chebyshev smoother interval.
 
-Tiling knobs (``tune_gemv_rows``, ``tune_col_chunks``, ``tune_strip_depth``) only change how
+Tiling knobs (``tune_gemv_rows``, ``tune_col_chunks``, ``tune_blur_window``) only change how
 the kernels split their work; the autotuner times each candidate with short solves (first
 outer iteration, a few inner iterations) through the C ABI and keeps the fastest, one knob
 at a time (coordinate descent), using the HIP-event product timings the library reports.
@@ -18,7 +18,7 @@ import json
 from . import plsqr as P
 
 DENSE_KNOBS = {"tune_gemv_rows": (1, 2, 4, 8), "tune_col_chunks": (4, 8, 16, 32, 64)}
-BLUR_KNOBS = {"tune_strip_depth": (16, 32, 64)}
+BLUR_KNOBS = {"tune_blur_window": (8, 16), "tune_blur_xgroups": (1, 2, 4)}
 CHEB_LO = (1.0 / 8.0, 1.0 / 4.0, 1.0 / 3.0, 1.0 / 2.0)
 
 
@@ -87,8 +87,10 @@ def tune(problem, engine, inner=4, repeats=3, tune_cheb=True):
             best = min(best, res.forward_ms + res.adjoint_ms)
         return best
 
-    start = {k: v[min(len(v) - 1, len(v) // 2)] for k, v in knobs.items()}
-    settings, log = coordinate_descent(knobs, measure, start)
+    settings, log = {}, []
+    if knobs:
+        start = {k: v[min(len(v) - 1, len(v) // 2)] for k, v in knobs.items()}
+        settings, log = coordinate_descent(knobs, measure, start)
     report = {"knob_trials": [{"settings": s, "product_ms": c} for s, c in log]}
 
     if tune_cheb and problem.smoother == "chebyshev":

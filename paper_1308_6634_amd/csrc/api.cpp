@@ -75,7 +75,10 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
     D.cheb_sigma = D.cheb_theta / D.cheb_delta;
   }
   if (op.op.kind == PLSQR_OP_BLUR)
-    for (size_t i = 0; i < op.taps.size() && i < (size_t)kMaxTaps; ++i) D.taps[i] = op.taps[i];
+    for (size_t i = 0; i < op.taps.size() && i < (size_t)kMaxTaps; ++i) {
+      D.taps[i] = op.taps[i];
+      D.taps_rev[i] = op.taps[op.taps.size() - 1 - i];
+    }
   D.g = r.g;
   D.A = op.op.kind == PLSQR_OP_DENSE ? op.op.A_dev : nullptr;
   auto F = [&](size_t off) { return reinterpret_cast<float *>(ws + off); };
@@ -90,13 +93,20 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.colpart = Ly.colpart ? F(Ly.colpart) : nullptr;
   D.colchunks = Ly.colchunks;
   D.gemv_rows = pb.tune_gemv_rows ? pb.tune_gemv_rows : 4;
-  D.strip_depth = pb.tune_strip_depth ? pb.tune_strip_depth : 32;
+  D.blur_window = pb.tune_blur_window;
+  D.blur_xgroups = pb.tune_blur_xgroups;
   D.out_f = r.f_out;
   D.sc = reinterpret_cast<double *>(ws + Ly.sc);
   D.part = reinterpret_cast<double *>(ws + Ly.part);
   D.cfac = reinterpret_cast<double *>(ws + Ly.cfac);
   D.diag = reinterpret_cast<double *>(ws + Ly.diag);
   D.nc = Ly.nc;
+  D.stop_flags = (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER));
+  D.s4_level = (pb.flags & PLSQR_FLAG_STOP_S4) ? pb.eta * pb.delta : 0.0;
+  D.outer_rtol = pb.outer_rtol;
+  D.outer_min = pb.outer_min;
+  D.aw = Ly.aw ? F(Ly.aw) : nullptr;
+  D.af = Ly.af ? F(Ly.af) : nullptr;
   const int d = pb.nz > 1 ? 3 : 2;
   for (int l = 0; l < Ly.levels; ++l) {
     LevelDesc &L = D.lv[l];
@@ -331,6 +341,20 @@ double total_ms(const EventList &lst) {
   return s;
 }
 
+// Status, counts and per-outer records of a finished request from its scalar block and
+// diagnostics (copied back to pinned memory at the end of the request).
+void fill_records(const Request &r, const double *sc, const double *dg, plsqr_result &res) {
+  res.status = (int)sc[SC_STATUS];
+  // SC_OUTER counts the outer steps run (it stops advancing once the outer stop fired)
+  res.outer_done = std::max(0, std::min(r.pb.outer, (int)sc[SC_OUTER]));
+  res.levels = r.lay.levels;
+  for (int k = 1; k <= res.outer_done; ++k) {
+    res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
+    res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
+    res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
+  }
+}
+
 // Collect a finished group: read every member's diagnostics, release memory.
 void reap(plsqr_engine *eng, Group &G) {
   float ms = 0.f;
@@ -343,14 +367,7 @@ void reap(plsqr_engine *eng, Group &G) {
     std::memset(&res, 0, sizeof(res));
     const double *sc = reinterpret_cast<const double *>(r.pinned + pin_sc_off());
     const double *dg = reinterpret_cast<const double *>(r.pinned + pin_dg_off());
-    res.status = (int)sc[SC_STATUS];
-    res.outer_done = r.pb.outer;
-    res.levels = r.lay.levels;
-    for (int k = 1; k <= r.pb.outer; ++k) {
-      res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
-      res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
-      res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
-    }
+    fill_records(r, sc, dg, res);
     res.device_ms = ms;
     res.forward_ms = fwd;
     res.forward_launches = (int64_t)G.fwd_events.size();
@@ -404,7 +421,7 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
         c.smoother != a.smoother || c.nu_pre != a.nu_pre || c.cheb_degree != a.cheb_degree ||
         c.precision != a.precision || c.flags != a.flags ||
         c.tune_gemv_rows != a.tune_gemv_rows || c.tune_col_chunks != a.tune_col_chunks ||
-        c.tune_strip_depth != a.tune_strip_depth)
+        c.tune_blur_window != a.tune_blur_window || c.tune_blur_xgroups != a.tune_blur_xgroups)
       return set_error(PLSQR_E_INVALID,
                        "a batch must share counts, levels, smoother schedule, precision and flags");
   }
@@ -457,10 +474,10 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
 // arrive while others run join the next tick. Only this thread issues HIP calls.
 // ------------------------------------------------------------------------------------
 struct ClassKey {
-  int nx, ny, nz, levels, smoother, nu, deg, kind, type;
+  int nx, ny, nz, levels, smoother, nu, deg, kind, type, s4;
   bool operator<(const ClassKey &o) const {
-    return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type) <
-           std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type);
+    return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type, s4) <
+           std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type, o.s4);
   }
 };
 
@@ -475,14 +492,7 @@ void serve_collect(plsqr_engine *eng) {
     std::memset(&res, 0, sizeof(res));
     const double *sc = reinterpret_cast<const double *>(r.pinned + pin_sc_off());
     const double *dg = reinterpret_cast<const double *>(r.pinned + pin_dg_off());
-    res.status = (int)sc[SC_STATUS];
-    res.outer_done = r.pb.outer;
-    res.levels = r.lay.levels;
-    for (int k = 1; k <= r.pb.outer; ++k) {
-      res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
-      res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
-      res.inner_done[k - 1] = (int)dg[(size_t)k * DG_COUNT + DG_INNER];
-    }
+    fill_records(r, sc, dg, res);
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.ev_start, r.ev_done) == hipSuccess) res.device_ms = ms;
     res.workspace_bytes = (int64_t)r.lay.total;
@@ -546,8 +556,9 @@ void serve_tick(plsqr_engine *eng) {
   for (uint64_t t : eng->resident) {
     Request &r = *eng->reqs[t];
     const plsqr_problem &pb = r.pb;
+    // the S4 kernels run only for subgroups whose members all carry the S4 vectors
     ClassKey key{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
-                 r.host.op_kind, step_type(pb, r.step)};
+                 r.host.op_kind, step_type(pb, r.step), (int)(pb.flags & PLSQR_FLAG_STOP_S4)};
     groups[key].push_back(&r);
   }
   plsqr_engine::TickSlot &slot = eng->ring[eng->ring_next];

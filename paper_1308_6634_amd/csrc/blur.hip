@@ -2,9 +2,12 @@
 // adjoint, the same passes with reversed taps): one 1D correlation pass per axis with zero
 // values outside the grid, y[x] = sum_k w[k] src[x + k - r]. The last pass applies the Krylov
 // epilogue of the bidiagonalization (section 3.2, Algorithm 2). Every pass reads and writes
-// one vector, so the passes are HBM-bound; the kernels below keep each HBM byte read once
-// (halo re-reads come from L1/LDS) and move data in 16-byte vectors where the rows allow.
+// one vector, so the passes are HBM-bound; each thread loads its whole input window into
+// registers at once (16-byte groups along x, one coalesced row segment per wave along y and
+// z), halo re-reads coming from L1/L2.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -103,18 +106,6 @@ __device__ __forceinline__ void epilogue_pre(const InstDesc &D, int epi, long lo
   }
 }
 
-// Tile handled by this block. Workgroups are dealt to the 8 XCDs round-robin; when the grid
-// splits evenly, consecutive tiles are given to blocks on the same XCD, so the halo rows that
-// neighbouring tiles share are found in that XCD's L2.
-__device__ __forceinline__ long long xcd_tile() {
-  const unsigned b = blockIdx.x, nb = gridDim.x;
-  if (nb % 8u != 0u) return b;
-  return (long long)(b % 8u) * (nb / 8u) + b / 8u;
-}
-
-constexpr int kR4Max = (PLSQR_MAX_RADIUS + 3) / 4 * 4;   // radius rounded up to a multiple of 4
-constexpr int kWinGroups = 1 + kR4Max / 2;               // float4 groups in a 4-output window
-constexpr int kWin = 4 * kWinGroups + 4;                 // + 4 zeros: every unrolled index valid
 
 }  // namespace
 
@@ -125,6 +116,7 @@ constexpr int kXTile = 4 * kBlock;
 __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int src_sel, int dst_sel,
                                                   int adj, int epi) {
   const InstDesc &D = inst(descs);
+  if (product_masked(D, epi)) return;
   __shared__ float tile[kXTile + 2 * PLSQR_MAX_RADIUS];
   __shared__ float w[kMaxTaps];
   const int r = sld(D.radius);
@@ -173,329 +165,183 @@ __global__ void __launch_bounds__(kBlock) k_blur_x(InstDesc *const *descs, int s
 }
 
 
-// x pass, nx a multiple of 4: every thread computes the 4 outputs x0..x0+3 (x0 % 4 == 0) of one
-// row from a register window [x0 - R4, x0 + 4 + R4), R4 = r rounded up to a multiple of 4,
-// loaded as float4 groups straight from memory (neighbouring threads' windows overlap in L1).
-// A group lies wholly inside or wholly outside the row; outside groups are zeros, which is the
-// operator's zero boundary. kShift = R4 - r places tap k of output e at window index
-// kShift + e + k.
-template <int kShift>
-__device__ __forceinline__ V4 blur_x_window(const float *__restrict__ src, const float *w,
-                                            long long j, int x0, int nx, int r) {
-  const int R4 = r + kShift;
-  const int ng = 1 + R4 / 2;
-  const int ntaps = 2 * r + 1;
-  float win[kWin];
+// The radius is a template parameter of the pass bodies below: with it every window, tap loop
+// and boundary test is static, so a thread's loads are straight-line code issued back to back
+// (no branch per load, no wait between them) and the taps sit in scalar registers. Instances of
+// one batch may differ in radius, so each block picks its body with a switch on r.
+#define PLSQR_RADIUS_SWITCH(r, CALL) \
+  switch (r) {                        \
+    case 0: CALL(0); break;           \
+    case 1: CALL(1); break;           \
+    case 2: CALL(2); break;           \
+    case 3: CALL(3); break;           \
+    case 4: CALL(4); break;           \
+    case 5: CALL(5); break;           \
+    case 6: CALL(6); break;           \
+    case 7: CALL(7); break;           \
+    case 8: CALL(8); break;           \
+    case 9: CALL(9); break;           \
+    case 10: CALL(10); break;         \
+    case 11: CALL(11); break;         \
+    case 12: CALL(12); break;         \
+    case 13: CALL(13); break;         \
+    case 14: CALL(14); break;         \
+    case 15: CALL(15); break;         \
+    default: CALL(16); break;         \
+  }
+static_assert(PLSQR_MAX_RADIUS == 16, "the radius switch covers 0..16");
+
+// zero_pad_note: inputs outside the grid are read from the nearest inside address and scaled
+// by 0 rather than selected away, so that no load depends on a condition and a thread issues
+// all its loads back to back. For finite data v * 0 = +-0 and v * 1 = v exactly, so the
+// outputs equal those of explicit zero padding bit for bit; a non-finite boundary value that
+// is copied this way only reaches outputs whose windows already contain it (the copies sit
+// next to it), so NaN/Inf propagate as they would anyway.
+
+// x pass, nx a multiple of 4: every thread computes kXG (1, 2 or 4) groups of 4 consecutive
+// outputs of one
+// row (fewer at the row's end) from a register window of float4 groups loaded straight from
+// memory, [x0 - R4, x0 + 4 kXG + R4) with R4 = R rounded up to a multiple of 4 (groups outside
+// the row are zeros: the operator's zero boundary). Out-of-row groups are loaded from a clamped
+// address and replaced by zeros, so the loads carry no branches. Per output the taps are
+// applied in order k = 0..2R.
+template <int kXG, int R>
+__device__ __forceinline__ void xg_outputs(const float *__restrict__ src, const float *T,
+                                           long long rowbase, int x0, int nx, V4 (&y)[kXG]) {
+  constexpr int R4 = (R + 3) & ~3;
+  constexpr int kShift = R4 - R;
+  constexpr int NG = kXG + R4 / 2;
+  float win[4 * NG];
 #pragma unroll
-  for (int g = 0; g < kWinGroups; ++g) {
+  for (int g = 0; g < NG; ++g) {
     const int xs = x0 - R4 + 4 * g;
-    V4 v = {};
-    if (g < ng && xs >= 0 && xs < nx) v = ld4(src + j - R4 + 4 * g);
+    const float okf = (xs >= 0 && xs < nx) ? 1.f : 0.f;
+    const int xc = min(max(xs, 0), nx - 4);
+    const V4 v = ld4(src + rowbase + xc);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) win[4 * g + e] = v.v[e];
+    for (int e = 0; e < 4; ++e) win[4 * g + e] = v.v[e] * okf;   // see zero_pad_note
   }
+  float w[2 * R + 1];
 #pragma unroll
-  for (int e = 4 * kWinGroups; e < kWin; ++e) win[e] = 0.f;
-  V4 y = {};
+  for (int k = 0; k <= 2 * R; ++k) w[k] = sld(T[k]);
 #pragma unroll
-  for (int k = 0; k < kMaxTaps; ++k) {
-    if (k < ntaps) {
-      const float wk = w[k];
+  for (int g = 0; g < kXG; ++g) y[g] = V4{};
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (kShift + e + k < kWin) y.v[e] += wk * win[kShift + e + k];
-    }
-  }
-  return y;
+  for (int k = 0; k <= 2 * R; ++k)
+#pragma unroll
+    for (int e = 0; e < 4 * kXG; ++e) y[e / 4].v[e % 4] += w[k] * win[kShift + e + k];
 }
 
-// The radius is per instance (instances of one batch may differ), so the window offset is
-// selected per block.
-__global__ void __launch_bounds__(kBlock) k_blur_x4(InstDesc *const *descs, int src_sel,
+template <int kXG>
+__global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int src_sel,
                                                    int dst_sel, int adj, int epi) {
   const InstDesc &D = inst(descs);
-  __shared__ float w[kMaxTaps];
+  if (product_masked(D, epi)) return;
   const int r = sld(D.radius);
-  if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-  __syncthreads();
-  const long long j = 4 * ((long long)blockIdx.x * kBlock + threadIdx.x);
+  const int nx = sld(D.nx);
+  const long long n = sld(D.n);
+  const int tpr = (nx + 4 * kXG - 1) / (4 * kXG);          // threads per row
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long rows = n / nx;
   double dot = 0.0;
-  if (j < sld(D.n)) {
-    const int nx = sld(D.nx);
-    const int x0 = (int)((unsigned)j % (unsigned)nx);
+  if (t < rows * tpr) {
+    const long long row = t / tpr;
+    const int x0 = (int)(t % tpr) * 4 * kXG;
+    const long long rowbase = row * nx;
     const float *__restrict__ src = vec_of(D, src_sel);
-    V4 y;
-    switch ((4 - r % 4) % 4) {
-      case 0: y = blur_x_window<0>(src, w, j, x0, nx, r); break;
-      case 1: y = blur_x_window<1>(src, w, j, x0, nx, r); break;
-      case 2: y = blur_x_window<2>(src, w, j, x0, nx, r); break;
-      default: y = blur_x_window<3>(src, w, j, x0, nx, r); break;
-    }
-    epilogue4(D, epi, j, y, vec_of(D, dst_sel), dot);
+    const float *T = adj ? D.taps_rev : D.taps;
+    V4 y[kXG];
+#define PLSQR_XG(RR) xg_outputs<kXG, RR>(src, T, rowbase, x0, nx, y)
+    PLSQR_RADIUS_SWITCH(r, PLSQR_XG)
+#undef PLSQR_XG
+    float *dst = vec_of(D, dst_sel);
+#pragma unroll
+    for (int g = 0; g < kXG; ++g)
+      if (x0 + 4 * g < nx) epilogue4(D, epi, rowbase + x0 + 4 * g, y[g], dst, dot);
   }
   block_partial(D, epi, dot);
 }
 
-// y or z pass: a block of 64 x 4 threads owns a strip of 64 x-columns and kStripA outputs along
-// the axis (the other coordinate fixed). It stages the kStripA + 2r input planes of the strip in
-// LDS (16-byte loads when nx is a multiple of 4), then each thread computes kStripA / 4
-// consecutive outputs of one column from a window of LDS values read once each; the tap
-// products are accumulated per output in tap order, out-of-grid planes being zeros.
-constexpr int kStripX = 64;
-template <int kStripA>
-__global__ void __launch_bounds__(kBlock) k_blur_strip(InstDesc *const *descs, int axis,
-                                                      int src_sel, int dst_sel, int adj, int epi) {
-  constexpr int kOut = kStripA / 4;
+// y or z pass with a register window (any nx): every thread owns one column element (x and the
+// remaining coordinate fixed) and kWinS consecutive outputs along the axis. It issues the loads
+// of all its kWinS + 2R inputs and of the epilogue operands back to back -- 64 lanes read 64
+// consecutive x, so each load of a wave is one coalesced row segment -- and then forms the
+// outputs from registers, taps in order k = 0..2R. No LDS and no barrier; neighbouring segments
+// re-read their 2R halo lines through L2.
+template <int kWinS, int R>
+__device__ __forceinline__ double win_outputs(const InstDesc &D, int epi,
+                                              const float *__restrict__ src, float *dst,
+                                              const float *pre_src, const float *T, long long base,
+                                              long long sa, int a0, int na) {
+  constexpr int W = kWinS + 2 * R;
+  float win[W];
+#pragma unroll
+  for (int m = 0; m < W; ++m) {
+    const int a = a0 - R + m;
+    const float okf = (a >= 0 && a < na) ? 1.f : 0.f;
+    const int ac = min(max(a, 0), na - 1);
+    win[m] = src[base + (long long)ac * sa] * okf;   // see zero_pad_note
+  }
+  float pre[kWinS];
+  if (pre_src) {
+#pragma unroll
+    for (int q = 0; q < kWinS; ++q) pre[q] = pre_src[base + (long long)min(a0 + q, na - 1) * sa];
+  } else {
+#pragma unroll
+    for (int q = 0; q < kWinS; ++q) pre[q] = 0.f;
+  }
+  float w[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) w[k] = sld(T[k]);
+  float acc[kWinS];
+#pragma unroll
+  for (int q = 0; q < kWinS; ++q) acc[q] = 0.f;
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k)
+#pragma unroll
+    for (int q = 0; q < kWinS; ++q) acc[q] += w[k] * win[q + k];
+  double dot = 0.0;
+#pragma unroll
+  for (int q = 0; q < kWinS; ++q) {
+    if (a0 + q < na) {
+      double dq = 0.0;
+      epilogue_pre(D, epi, base + (long long)(a0 + q) * sa, acc[q], pre[q], dst, dq);
+      dot += dq;
+    }
+  }
+  return dot;
+}
+
+template <int kWinS>
+__global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int axis,
+                                                    int src_sel, int dst_sel, int adj, int epi) {
   const InstDesc &D = inst(descs);
-  __shared__ float tile[kStripA + 2 * PLSQR_MAX_RADIUS][kStripX];
-  __shared__ float w[kMaxTaps];
+  if (product_masked(D, epi)) return;
   const int r = sld(D.radius);
   const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
   const int na = (axis == 1) ? ny : nz;        // extent along the pass
   const int no = (axis == 1) ? nz : ny;        // the remaining coordinate
   const long long sa = (axis == 1) ? (long long)nx : (long long)nx * ny;
   const long long so = (axis == 1) ? (long long)nx * ny : (long long)nx;
-  const int tx_n = (nx + kStripX - 1) / kStripX, ta_n = (na + kStripA - 1) / kStripA;
-  const long long tiles = (long long)tx_n * ta_n * no;
-  const long long t = xcd_tile();
-  const int lx = threadIdx.x & (kStripX - 1), la = threadIdx.x / kStripX;   // 64 x 4
-  if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-  int tx = 0, ta = 0, o = 0;
-  if (t < tiles) {
-    tx = (int)(t % tx_n);
-    const long long rest = t / tx_n;
-    ta = (int)(rest % ta_n);
-    o = (int)(rest / ta_n);
-  }
-  const int a0 = ta * kStripA;
-  const int rows = kStripA + 2 * r;
-  const float *__restrict__ src = vec_of(D, src_sel);
-  const long long obase = (long long)o * so;
-  if (t < tiles) {
-    if ((nx & 3) == 0) {
-      // 16 float4 columns x 16 planes per pass of the block, 4 loads in flight per thread
-      const int c4 = threadIdx.x & 15, sub = threadIdx.x >> 4;
-      const int xg = tx * kStripX + 4 * c4;
-      for (int i0 = sub; i0 < rows; i0 += 64) {
-        V4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 16 * u;
-          const int a = a0 - r + i;
-          v[u] = V4{};
-          if (i < rows && xg < nx && a >= 0 && a < na) v[u] = ld4(src + obase + xg + (long long)a * sa);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 16 * u;
-          if (i < rows)
-            *reinterpret_cast<float4 *>(&tile[i][4 * c4]) =
-                make_float4(v[u].v[0], v[u].v[1], v[u].v[2], v[u].v[3]);
-        }
-      }
-    } else {
-      const int x = tx * kStripX + lx;
-      for (int i0 = la; i0 < rows; i0 += 16) {
-        float v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 4 * u;
-          const int a = a0 - r + i;
-          v[u] = (i < rows && x < nx && a >= 0 && a < na) ? src[obase + x + (long long)a * sa] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 4 * u;
-          if (i < rows) tile[i][lx] = v[u];
-        }
-      }
-    }
-  }
-  const int x = tx * kStripX + lx;
-  const long long base = obase + x;
-  const float *pre_src = pre_operand(D, epi);
-  float pre[kOut];
-#pragma unroll
-  for (int q = 0; q < kOut; ++q) {
-    const int a = a0 + la * kOut + q;
-    pre[q] = (pre_src && t < tiles && x < nx && a < na) ? pre_src[base + (long long)a * sa] : 0.f;
-  }
-  __syncthreads();
+  const int segs = (na + kWinS - 1) / kWinS;
+  const long long total = (long long)nx * segs * no;
+  // consecutive segments of a line share 2R halo lines: xcd_tile keeps consecutive blocks on
+  // one XCD, so the halo is re-read from that XCD's L2
+  const long long t = xcd_tile() * kBlock + threadIdx.x;
   double dot = 0.0;
-  if (t < tiles && x < nx) {
-    const int q0 = la * kOut;
-    const int nwin = kOut + 2 * r;
-    float acc[kOut];
-#pragma unroll
-    for (int q = 0; q < kOut; ++q) acc[q] = 0.f;
-#pragma unroll
-    for (int m = 0; m < kOut + 2 * PLSQR_MAX_RADIUS; ++m) {
-      if (m < nwin) {
-        const float v = tile[q0 + m][lx];
-#pragma unroll
-        for (int q = 0; q < kOut; ++q) {
-          const int k = m - q;
-          if (k >= 0 && k <= 2 * r) acc[q] += w[k] * v;
-        }
-      }
-    }
+  if (t < total) {
+    const int x = (int)(t % nx);
+    const long long rest = t / nx;
+    const int seg = (int)(rest % segs);
+    const int o = (int)(rest / segs);
+    const long long base = (long long)o * so + x;
+    const float *T = adj ? D.taps_rev : D.taps;
+    const float *__restrict__ src = vec_of(D, src_sel);
     float *dst = vec_of(D, dst_sel);
-#pragma unroll
-    for (int q = 0; q < kOut; ++q) {
-      const int a = a0 + q0 + q;
-      if (a < na) {
-        double dq = 0.0;
-        epilogue_pre(D, epi, base + (long long)a * sa, acc[q], pre[q], dst, dq);
-        dot += dq;
-      }
-    }
-  }
-  block_partial(D, epi, dot);
-}
-
-// Fused x and y passes (nx a multiple of 4, ny > 1): a block of 256 threads owns an output
-// tile of kStripX x-columns by kTileY rows of one z-plane. It stages the input rows
-// [y0 - r, y0 + kTileY + r) and columns [x0 - R4, x0 + kStripX + R4) in LDS (zeros outside the
-// grid), runs the x pass over all those rows into a second LDS tile (4 outputs per task from a
-// register window, as k_blur_x4), then the y pass from that tile (as k_blur_strip). The
-// intermediate is rounded to FP32 exactly as the separate passes store it, so the result is
-// the same as the x pass followed by the y pass; the intermediate never goes to HBM.
-constexpr int kTileY = 16;
-constexpr int kTileCols = kStripX + 2 * kR4Max;                 // staged columns
-constexpr int kTileRows = kTileY + 2 * PLSQR_MAX_RADIUS;        // staged rows
-
-template <int kShift>
-__device__ __forceinline__ void xy_xphase(const float (*tile)[kTileCols], float (*mid)[kStripX],
-                                          const float *w, int r, int rows) {
-  const int R4 = r + kShift;
-  const int ng = 1 + R4 / 2;
-  const int ntaps = 2 * r + 1;
-  for (int q = threadIdx.x; q < rows * (kStripX / 4); q += kBlock) {
-    const int row = q / (kStripX / 4), g = q % (kStripX / 4);
-    float win[kWin];
-#pragma unroll
-    for (int k = 0; k < kWinGroups; ++k) {
-      V4 v = {};
-      if (k < ng) {
-        const float4 t = *reinterpret_cast<const float4 *>(&tile[row][4 * g + 4 * k]);
-        v.v[0] = t.x; v.v[1] = t.y; v.v[2] = t.z; v.v[3] = t.w;
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) win[4 * k + e] = v.v[e];
-    }
-#pragma unroll
-    for (int e = 4 * kWinGroups; e < kWin; ++e) win[e] = 0.f;
-    V4 y = {};
-#pragma unroll
-    for (int k = 0; k < kMaxTaps; ++k) {
-      if (k < ntaps) {
-        const float wk = w[k];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (kShift + e + k < kWin) y.v[e] += wk * win[kShift + e + k];
-      }
-    }
-    *reinterpret_cast<float4 *>(&mid[row][4 * g]) = make_float4(y.v[0], y.v[1], y.v[2], y.v[3]);
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_blur_xy(InstDesc *const *descs, int src_sel,
-                                                   int dst_sel, int adj, int epi) {
-  constexpr int kOut = kTileY / 4;
-  const InstDesc &D = inst(descs);
-  __shared__ __align__(16) float tile[kTileRows][kTileCols];
-  __shared__ __align__(16) float mid[kTileRows][kStripX];
-  __shared__ float w[kMaxTaps];
-  const int r = sld(D.radius);
-  const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
-  const int tx_n = (nx + kStripX - 1) / kStripX, ty_n = (ny + kTileY - 1) / kTileY;
-  const long long tiles = (long long)tx_n * ty_n * nz;
-  const long long t = xcd_tile();
-  if (threadIdx.x < 2 * r + 1) w[threadIdx.x] = D.taps[adj ? 2 * r - threadIdx.x : threadIdx.x];
-  int tx = 0, ty = 0, z = 0;
-  if (t < tiles) {
-    tx = (int)(t % tx_n);
-    const long long rest = t / tx_n;
-    ty = (int)(rest % ty_n);
-    z = (int)(rest / ty_n);
-  }
-  const int x0 = tx * kStripX, y0 = ty * kTileY;
-  const int R4 = (r + 3) & ~3;
-  const int rows = kTileY + 2 * r;
-  const int cols4 = (kStripX + 2 * R4) / 4;
-  const float *__restrict__ src = vec_of(D, src_sel);
-  const long long zbase = (long long)z * nx * ny;
-  if (t < tiles) {
-    for (int q0 = threadIdx.x; q0 < rows * cols4; q0 += 4 * kBlock) {
-      V4 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = q0 + u * kBlock;
-        const int row = q / cols4, c4 = q % cols4;
-        const int y = y0 - r + row, xg = x0 - R4 + 4 * c4;
-        v[u] = V4{};
-        if (q < rows * cols4 && y >= 0 && y < ny && xg >= 0 && xg < nx)
-          v[u] = ld4(src + zbase + (long long)y * nx + xg);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = q0 + u * kBlock;
-        if (q < rows * cols4) {
-          const int row = q / cols4, c4 = q % cols4;
-          *reinterpret_cast<float4 *>(&tile[row][4 * c4]) =
-              make_float4(v[u].v[0], v[u].v[1], v[u].v[2], v[u].v[3]);
-        }
-      }
-    }
-  }
-  const int lx = threadIdx.x & (kStripX - 1), la = threadIdx.x / kStripX;
-  const int x = x0 + lx;
-  const float *pre_src = pre_operand(D, epi);
-  float pre[kOut];
-#pragma unroll
-  for (int q = 0; q < kOut; ++q) {
-    const int y = y0 + la * kOut + q;
-    pre[q] = (pre_src && t < tiles && x < nx && y < ny) ? pre_src[zbase + (long long)y * nx + x] : 0.f;
-  }
-  __syncthreads();
-  if (t < tiles) {
-    switch (R4 - r) {
-      case 0: xy_xphase<0>(tile, mid, w, r, rows); break;
-      case 1: xy_xphase<1>(tile, mid, w, r, rows); break;
-      case 2: xy_xphase<2>(tile, mid, w, r, rows); break;
-      default: xy_xphase<3>(tile, mid, w, r, rows); break;
-    }
-  }
-  __syncthreads();
-  double dot = 0.0;
-  if (t < tiles && x < nx) {
-    const int q0 = la * kOut;
-    const int nwin = kOut + 2 * r;
-    float acc[kOut];
-#pragma unroll
-    for (int q = 0; q < kOut; ++q) acc[q] = 0.f;
-#pragma unroll
-    for (int m = 0; m < kOut + 2 * PLSQR_MAX_RADIUS; ++m) {
-      if (m < nwin) {
-        // the x pass leaves zeros in rows outside the grid (their inputs were zeros)
-        const float v = mid[q0 + m][lx];
-#pragma unroll
-        for (int q = 0; q < kOut; ++q) {
-          const int k = m - q;
-          if (k >= 0 && k <= 2 * r) acc[q] += w[k] * v;
-        }
-      }
-    }
-    float *dst = vec_of(D, dst_sel);
-#pragma unroll
-    for (int q = 0; q < kOut; ++q) {
-      const int y = y0 + q0 + q;
-      if (y < ny) {
-        double dq = 0.0;
-        epilogue_pre(D, epi, zbase + (long long)y * nx + x, acc[q], pre[q], dst, dq);
-        dot += dq;
-      }
-    }
+    const float *pre_src = pre_operand(D, epi);
+#define PLSQR_WIN(RR) dot = win_outputs<kWinS, RR>(D, epi, src, dst, pre_src, T, base, sa, seg * kWinS, na)
+    PLSQR_RADIUS_SWITCH(r, PLSQR_WIN)
+#undef PLSQR_WIN
   }
   block_partial(D, epi, dot);
 }
@@ -506,34 +352,45 @@ __global__ void __launch_bounds__(kBlock) k_blur_xy(InstDesc *const *descs, int 
 #define LAUNCH_B(kern, gx, gy, ...) \
   hipLaunchKernelGGL(kern, dim3(gx, gy), dim3(kBlock), 0, st, __VA_ARGS__)
 
+// Work per thread of the blur passes when not set by the caller: measured on 128^3 grids, alone
+// and in lockstep batches of 8, 2 groups per thread in x and 8 outputs per thread along y and z
+// are within a few percent of the best of {1, 2, 4} x {4, 8, 16, 32}.
+constexpr int kDefaultXGroups = 2;
+constexpr int kDefaultWindow = 8;
+
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi) {
+                  int adj, int epi, int groups) {
   if (nx % 4 == 0) {
-    const unsigned g = (unsigned)((n / 4 + kBlock - 1) / kBlock);
-    LAUNCH_B(k_blur_x4, g, B, d, src, dst, adj, epi);
+    const int G = groups ? groups : kDefaultXGroups;
+    const long long threads = n / nx * ((nx + 4 * G - 1) / (4 * G));
+    const unsigned g = (unsigned)((threads + kBlock - 1) / kBlock);
+    if (G == 1)
+      LAUNCH_B(k_blur_xg<1>, g, B, d, src, dst, adj, epi);
+    else if (G == 2)
+      LAUNCH_B(k_blur_xg<2>, g, B, d, src, dst, adj, epi);
+    else
+      LAUNCH_B(k_blur_xg<4>, g, B, d, src, dst, adj, epi);
     return (int)g;
   }
   const unsigned g = (unsigned)((n + kXTile - 1) / kXTile);
   LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);
   return (int)g;
 }
-int launch_blur_xy(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int src,
-                   int dst, int adj, int epi) {
-  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((ny + kTileY - 1) / kTileY) * nz;
-  LAUNCH_B(k_blur_xy, (unsigned)tiles, B, d, src, dst, adj, epi);
-  return (int)tiles;
-}
-int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                      int src, int dst, int adj, int epi, int depth) {
+int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
+                     int src, int dst, int adj, int epi, int window) {
+  const int S = window ? window : kDefaultWindow;
   const int na = (axis == 1) ? ny : nz, no = (axis == 1) ? nz : ny;
-  const long long tiles = (long long)((nx + kStripX - 1) / kStripX) * ((na + depth - 1) / depth) * no;
-  if (depth == 16)
-    LAUNCH_B(k_blur_strip<16>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
-  else if (depth == 64)
-    LAUNCH_B(k_blur_strip<64>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
+  const long long threads = (long long)nx * ((na + S - 1) / S) * no;
+  const unsigned g = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (S == 4)
+    LAUNCH_B(k_blur_win<4>, g, B, d, axis, src, dst, adj, epi);
+  else if (S == 8)
+    LAUNCH_B(k_blur_win<8>, g, B, d, axis, src, dst, adj, epi);
+  else if (S == 32)
+    LAUNCH_B(k_blur_win<32>, g, B, d, axis, src, dst, adj, epi);
   else
-    LAUNCH_B(k_blur_strip<32>, (unsigned)tiles, B, d, axis, src, dst, adj, epi);
-  return (int)tiles;
+    LAUNCH_B(k_blur_win<16>, g, B, d, axis, src, dst, adj, epi);
+  return (int)g;
 }
 
 }  // namespace plsqr

@@ -17,6 +17,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int kRows>
 __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, int src_sel, int epi) {
   const InstDesc &D = inst(descs);
+  if (product_masked(D, epi)) return;
   const long long row0 = (long long)blockIdx.x * kRows;
   const long long n = sld(D.n);
   const float *__restrict__ x = vec_of(D, src_sel);
@@ -91,6 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_rows(InstDesc *const *descs, in
 // grid (ceil(n/(4*kBlock)), B, chunks); colpart[chunk][col] = sum_{rows in chunk} A[row][col] u[row]
 __global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const long long n = sld(D.n), m = sld(D.m);
   const int chunks = sld(D.colchunks);
   const int ch = blockIdx.z;
@@ -150,6 +152,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_cols(InstDesc *const *descs) {
 // Dense adjoint, stage 2: sum the chunk partials and apply the epilogue.
 __global__ void __launch_bounds__(kBlock) k_colsum(InstDesc *const *descs, int epi) {
   const InstDesc &D = inst(descs);
+  if (product_masked(D, epi)) return;
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= sld(D.n)) return;
   float y = 0.f;

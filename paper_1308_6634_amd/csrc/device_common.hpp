@@ -17,6 +17,15 @@ __device__ __forceinline__ const InstDesc &inst(InstDesc *const *descs) {
   return *descs[blockIdx.y];
 }
 
+// Tile handled by this block. Workgroups are dealt to the 8 XCDs round-robin; when the grid
+// splits evenly, consecutive tiles are given to blocks on the same XCD, so data that
+// neighbouring tiles share (stencil and blur halos) is found in that XCD's L2.
+__device__ __forceinline__ long long xcd_tile() {
+  const unsigned b = blockIdx.x, nb = gridDim.x;
+  if (nb % 8u != 0u) return b;
+  return (long long)(b % 8u) * (nb / 8u) + b / 8u;
+}
+
 // Uniform read of a descriptor field through the scalar cache. Descriptors are written by the
 // host before the kernels that read them and never by a kernel, so they can be read as
 // constant memory: one scalar load into SGPRs instead of a vector load per lane (which would
@@ -47,6 +56,25 @@ __device__ __forceinline__ LevelDesc level_of(const InstDesc &D, int l) {
   L.dinv = sld(g.dinv);
   L.eps = sld(g.eps);
   return L;
+}
+
+// Adaptive stops (only for problems that request them): work that can no longer change the
+// result is skipped. stopped_inner: MLSQR has ended in this outer step (S4, breakdown) or the
+// outer loop has ended; stopped_outer: the outer loop has ended. The flags live in the scalar
+// block, which kernels write, so they are read with ordinary loads.
+__device__ __forceinline__ bool stopped_inner(const InstDesc &D) {
+  return sld(D.stop_flags) != 0 && sld(D.sc)[SC_STOP] != 0.0;
+}
+__device__ __forceinline__ bool stopped_outer(const InstDesc &D) {
+  return sld(D.stop_flags) != 0 && sld(D.sc)[SC_HALT] != 0.0;
+}
+// Strips the mask bits from a product's epilogue code; true if this instance skips the launch.
+__device__ __forceinline__ bool product_masked(const InstDesc &D, int &epi) {
+  const int m = epi & (EPI_MASK_INNER | EPI_MASK_OUTER);
+  epi &= ~(EPI_MASK_INNER | EPI_MASK_OUTER);
+  if (m == EPI_MASK_INNER) return stopped_inner(D);
+  if (m == EPI_MASK_OUTER) return stopped_outer(D);
+  return false;
 }
 
 __device__ __forceinline__ float *vec_of(const InstDesc &D, int sel) {

@@ -52,9 +52,12 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
       pb.tune_gemv_rows != 4 && pb.tune_gemv_rows != 8)
     return bad("tune_gemv_rows must be 0, 1, 2, 4 or 8");
   if (pb.tune_col_chunks < 0 || pb.tune_col_chunks > 64) return bad("tune_col_chunks must be in [0, 64]");
-  if (pb.tune_strip_depth && pb.tune_strip_depth != 16 && pb.tune_strip_depth != 32 &&
-      pb.tune_strip_depth != 64)
-    return bad("tune_strip_depth must be 0, 16, 32 or 64");
+  if (pb.tune_blur_window && pb.tune_blur_window != 4 && pb.tune_blur_window != 8 &&
+      pb.tune_blur_window != 16 && pb.tune_blur_window != 32)
+    return bad("tune_blur_window must be 0, 4, 8, 16 or 32");
+  if (pb.tune_blur_xgroups && pb.tune_blur_xgroups != 1 && pb.tune_blur_xgroups != 2 &&
+      pb.tune_blur_xgroups != 4)
+    return bad("tune_blur_xgroups must be 0, 1, 2 or 4");
   int levels = pb.mg_levels;
   if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
   if (levels < 1 || levels > kMaxLevels) return bad("mg_levels out of range");
@@ -68,6 +71,15 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   }
   if (nx * ny * nz > PLSQR_MAX_COARSE) return bad("coarsest grid has more than 512 cells");
   if (op->op.kind == PLSQR_OP_BLUR && 2 * op->op.radius + 1 > kMaxTaps) return bad("radius too large");
+  if (pb.flags & PLSQR_FLAG_STOP_S4) {
+    if (!(pb.eta > 0.0 && std::isfinite(pb.eta))) return bad("S4 needs eta > 0");
+    if (!(pb.delta >= 0.0 && std::isfinite(pb.delta))) return bad("S4 needs a finite delta >= 0");
+  }
+  if (pb.flags & PLSQR_FLAG_STOP_OUTER) {
+    if (!std::isfinite(pb.outer_rtol) || pb.outer_rtol < -1.0 || pb.outer_rtol >= 1.0)
+      return bad("outer_rtol must be in [-1, 1)");
+    if (pb.outer_min < 2) return bad("the outer stop compares R(f^k) with R(f^{k-1}): outer_min >= 2");
+  }
   *levels_out = levels;
   return PLSQR_OK;
 }
@@ -119,6 +131,10 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   L.w = take(vb);
   L.kappa = take(vb);
   L.u = take((size_t)L.m * sizeof(float));
+  if (pb.flags & PLSQR_FLAG_STOP_S4) {
+    L.aw = take((size_t)L.m * sizeof(float));
+    L.af = take((size_t)L.m * sizeof(float));
+  }
   L.colchunks = 0;
   if (!dense) {
     L.tmp1 = take(vb);
@@ -174,24 +190,26 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
   for (int a = 0; a < 3; ++a)
     if (ext[a] > 1) axes[na++] = a;
   if (na == 0) axes[na++] = 0;
-  // the x and y passes run as one kernel when rows split into 16-byte groups
-  const bool fuse_xy = (H.nx % 4 == 0) && na >= 2 && axes[0] == 0 && axes[1] == 1;
   int cur = src, np = 0;
   for (int i = 0; i < na; ++i) {
-    if (fuse_xy && i == 1) continue;
-    const bool last = (i == na - 1) || (fuse_xy && i == 0 && na == 2);
+    const bool last = (i == na - 1);
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
-    const int e = last ? epi : EPI_STORE;
-    if (fuse_xy && i == 0)
-      np = launch_blur_xy(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, cur, dst, adj, e);
-    else if (axes[i] == 0)
-      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e);
+    const int e = last ? epi : (EPI_STORE | (epi & (EPI_MASK_INNER | EPI_MASK_OUTER)));
+    if (axes[i] == 0)
+      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e, H.blur_xgroups);
     else
-      np = launch_blur_strip(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
-                             H.strip_depth);
+      np = launch_blur_axis(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
+                            H.blur_window);
     cur = dst;
   }
   return np;
+}
+
+// With adaptive stops, the mask bit that lets an instance skip a product: inner products once
+// its MLSQR has ended, the per-outer residual product once its outer loop has ended.
+static int with_mask(const InstDesc &H, int epi) {
+  if (!H.stop_flags) return epi;
+  return epi | (epi == EPI_RESID ? EPI_MASK_OUTER : EPI_MASK_INNER);
 }
 
 // y = A x from vector `src`, epilogue `epi`; returns the partial count.
@@ -201,12 +219,13 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   EventList *ev = (epi == EPI_FWD) ? bv.prod_events : nullptr;
   time_begin(st, ev, &a);
   int np;
+  const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR)
-    np = blur_chain(st, bv, src, 0, epi);
+    np = blur_chain(st, bv, src, 0, em);
   else if (bv.gemm)
-    np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, epi);
+    np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, em);
   else
-    np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, epi, H.gemv_rows);
+    np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, em, H.gemv_rows);
   time_end(st, ev, a);
   return np;
 }
@@ -217,13 +236,14 @@ static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
   hipEvent_t a = nullptr;
   EventList *ev = (epi == EPI_ADJ) ? bv.adj_events : nullptr;
   time_begin(st, ev, &a);
+  const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR) {
-    blur_chain(st, bv, V_U, 1, epi);
+    blur_chain(st, bv, V_U, 1, em);
   } else if (bv.gemm) {
-    launch_gemm_adjoint(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, epi);
+    launch_gemm_adjoint(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, em);
   } else {
     launch_gemv_cols(st, bv.d_descs, bv.B, H.n, H.colchunks);
-    launch_colsum(st, bv.d_descs, bv.B, H.n, epi);
+    launch_colsum(st, bv.d_descs, bv.B, H.n, em);
   }
   time_end(st, ev, a);
 }
@@ -422,6 +442,15 @@ void enqueue_mlsqr_init(hipStream_t st, const BatchView &bv) {
   np = enqueue_vcycle(st, bv);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA_INIT);
   launch_init_wf(st, bv.d_descs, bv.B, H.n);
+  if (H.stop_flags & PLSQR_FLAG_STOP_S4) launch_s4_begin(st, bv.d_descs, bv.B, H.m);
+}
+
+// After the f/w update: the S4 residual of the new iterate, and the stop test.
+static void enqueue_s4(hipStream_t st, const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  if (!(H.stop_flags & PLSQR_FLAG_STOP_S4)) return;
+  const int np = launch_s4_step(st, bv.d_descs, bv.B, H.m);
+  launch_finalize(st, bv.d_descs, bv.B, np, FIN_S4);
 }
 
 void enqueue_inner(hipStream_t st, const BatchView &bv) {
@@ -432,6 +461,7 @@ void enqueue_inner(hipStream_t st, const BatchView &bv) {
   np = enqueue_vcycle(st, bv);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
   launch_update_fw(st, bv.d_descs, bv.B, H.n);
+  enqueue_s4(st, bv);
 }
 
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
@@ -482,6 +512,7 @@ static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
       const int np = enqueue_vcycle(s, quiet);
       launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
       launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
+      enqueue_s4(s, quiet);
     });
   } else {
     ex = capture_graph(gc.cap, [&](hipStream_t s) { enqueue_inner(s, quiet); });

@@ -30,6 +30,7 @@ struct Layout {
   size_t total = 0;
   size_t desc = 0, descptr = 0, sc = 0, diag = 0, part = 0, cfac = 0;
   size_t f = 0, p = 0, v = 0, w = 0, kappa = 0, u = 0, tmp1 = 0, tmp2 = 0, colpart = 0;
+  size_t aw = 0, af = 0;              // S4 residual recurrence vectors (n_Y), 0 when unused
   size_t lvl[kMaxLevels][10] = {};   // x b r t s wx wy wz dinv (unused slots 0)
   int nparts = 0, colchunks = 0, levels = 0, nc = 0;
   long long n = 0, m = 0;

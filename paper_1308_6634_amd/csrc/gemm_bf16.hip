@@ -148,16 +148,19 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int col = t * 32 + li;
+    int e = epi;
+    bool skip = false;
+    if constexpr (EPI) skip = col < B && product_masked(*descs[col], e);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const long long row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
       if constexpr (!EPI) {
         out[((long long)ks * M + row) * Bpad + col] = acc[t][r];
       } else {
-        if (col < B) {
+        if (col < B && !skip) {
           const InstDesc &D = *descs[col];
           double unused = 0.0;
-          epilogue(D, epi, row, acc[t][r], nullptr, unused);
+          epilogue(D, e, row, acc[t][r], nullptr, unused);
         }
       }
     }
@@ -168,6 +171,7 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 __global__ void __launch_bounds__(kBlock) k_fwd_reduce(InstDesc *const *descs, const float *Ypart,
                                                       int ks, long long M, int Bpad, int epi) {
   const InstDesc &D = inst(descs);
+  if (product_masked(D, epi)) return;
   const int b = blockIdx.y;
   const long long row = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;

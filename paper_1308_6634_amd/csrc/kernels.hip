@@ -19,6 +19,7 @@ namespace plsqr {
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, int write_kappa) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double r = 0.0;
   if (j < sld(D.n)) {
@@ -42,6 +43,7 @@ __global__ void __launch_bounds__(kBlock) k_diffusivity(InstDesc *const *descs, 
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_level0_dinv(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= sld(D.n)) return;
   const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
@@ -73,6 +75,7 @@ __device__ __forceinline__ float face_w(const InstDesc &D, int l, int a, long lo
 // (J, J+e_a) is the sum of the fine face weights crossing it.
 __global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int l) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const LevelDesc F = level_of(D, l);
   const LevelDesc Cl = level_of(D, l + 1);
   const long long J = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -103,6 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int 
 
 __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, int l) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
@@ -197,6 +201,7 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
 constexpr int kCoarseLds = 64;
 __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const int l = sld(D.levels) - 1;
   const LevelDesc L = level_of(D, l);
   const int n = (int)L.n;
@@ -220,6 +225,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
 // thread i reads column i: coalesced). One block per instance.
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, sld(D.levels) - 1);
   const int n = (int)L.n;
   const double *__restrict__ Ai = sld(D.cfac) + (long long)n * n * 2;
@@ -241,6 +247,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(InstDesc *const *descs)
 __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l, int first,
                                                   int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
@@ -271,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(InstDesc *const *descs, int l
 __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs, int l,
                                                          int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
@@ -296,6 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_first2(InstDesc *const *descs
 __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *descs, int l,
                                                           int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const LevelDesc Cl = level_of(D, l + 1);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -321,6 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_prolong(InstDesc *const *desc
 __global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, int l, int last,
                                                       int dn_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
@@ -345,6 +355,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_first(InstDesc *const *descs, i
 __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *descs, int l,
                                                               int d_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const LevelDesc Cl = level_of(D, l + 1);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -364,6 +375,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong(InstDesc *const *
 __global__ void __launch_bounds__(kBlock) k_restrict_fine(InstDesc *const *descs, int l, int x_sel,
                                                          int use_r) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc F = level_of(D, l);
   const LevelDesc Cl = level_of(D, l + 1);
   const int nchild = (F.nz > 1) ? 8 : 4;
@@ -389,6 +401,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_fine(InstDesc *const *descs
 __global__ void __launch_bounds__(kBlock) k_cheb_start(InstDesc *const *descs, int l, int zero_x,
                                                       int d_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= L.n) return;
@@ -411,6 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step(InstDesc *const *descs, in
                                                      int update_r, int last, int d_sel, int dn_sel,
                                                      int step, int want_dot, int add_prolong) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   // rho_0 = 1/sigma, rho_{k+1} = 1/(2 sigma - rho_k); d' = rho_{k+1} rho_k d + 2 rho_{k+1}/delta D^{-1} r
@@ -453,6 +467,7 @@ __global__ void k_outer_begin(InstDesc *const *descs, int nblocks_unused) {
   const InstDesc &D = inst(descs);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double *sc = sld(D.sc);
+    if (sc[SC_HALT] != 0.0) return;   // the outer loop has stopped: this step changes nothing
     sc[SC_OUTER] += 1.0;
     sc[SC_STOP] = (sc[SC_STATUS] != 0.0) ? 1.0 : 0.0;
     sc[SC_DONE] = 0.0;
@@ -478,6 +493,7 @@ __global__ void __launch_bounds__(kBlock) k_request_begin(InstDesc *const *descs
 // u = g, partial ||g||^2 (first step of Algorithm 2).
 __global__ void __launch_bounds__(kBlock) k_copy_g_u(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_outer(D)) return;
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
   if (j < sld(D.m)) {
@@ -505,6 +521,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
   };
   switch (what) {
     case FIN_BETA_INIT: {
+      if (sc[SC_HALT] != 0.0) break;   // the partials were not written (outer loop ended)
       const double beta = sqrt(s);
       if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
       if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
@@ -561,13 +578,32 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       break;
     }
     case FIN_RESID: {
+      if (sc[SC_HALT] != 0.0) break;
       dg[DG_RESID] = sqrt(s);
       dg[DG_INNER] = sc[SC_DONE];
       dg[DG_STATUS] = sc[SC_STATUS];
       break;
     }
     case FIN_PENALTY: {
+      if (sc[SC_HALT] != 0.0) break;
       dg[DG_PENALTY] = s;
+      // outer stop (Algorithm 3, step 5): R(f^k) no longer falls by more than outer_rtol
+      if ((sld(D.stop_flags) & PLSQR_FLAG_STOP_OUTER) && k >= sld(D.outer_min)) {
+        const double prev = dg[-DG_COUNT + DG_PENALTY];
+        if (s - prev >= -sld(D.outer_rtol) * prev) {
+          sc[SC_HALT] = 1.0;
+          sc[SC_STOP] = 1.0;
+        }
+      }
+      break;
+    }
+    case FIN_S4: {
+      // discrepancy principle S4 on the iterate of the step just completed
+      if (sc[SC_STOP] != 0.0) break;
+      const double r = sqrt(s);
+      sc[SC_S4R] = r;
+      if (!isfinite(r)) { fail(PLSQR_E_NONFINITE); break; }
+      if (r <= sld(D.s4_level)) sc[SC_STOP] = 1.0;
       break;
     }
     default: break;
@@ -579,6 +615,7 @@ __global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (j >= sld(D.n)) return;
+  if (sld(D.sc)[SC_HALT] != 0.0) return;   // keep the f of the last outer step run
   const bool stop = sld(D.sc)[SC_STOP] != 0.0;
   sld(D.f)[j] = 0.f;
   sld(D.w)[j] = stop ? 0.f : (float)sld(D.sc)[SC_SV] * sld(D.v)[j];
@@ -611,9 +648,49 @@ __global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs) {
   }
 }
 
+// S4 residual by recurrence (Section 3.4 with the relations of the bidiagonalisation).
+// With u_raw = beta_{i+1} u_{i+1} = A v_i - alpha_i u_i (the stored, unnormalised u):
+//   A w_i     = u_raw + s_i,  s_i = alpha_i u_i - (theta_i / rho_{i-1}) A w_{i-1}  (s_1 = alpha_1 u_1)
+//   A f_i     = A f_{i-1} + (phi_i / rho_i) A w_i
+//   s_{i+1}   = alpha_{i+1} u_{i+1} - (theta_{i+1} / rho_i) A w_i
+// so ||g - A f_i|| needs no product with A. aw holds s_i, af holds A f_i (n_Y each).
+__global__ void __launch_bounds__(kBlock) k_s4_begin(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= sld(D.m)) return;
+  const double *sc = sld(D.sc);
+  if (sc[SC_STOP] != 0.0) return;
+  const float c = (float)(sc[SC_ALPHA] * sc[SC_SU]);
+  sld(D.aw)[j] = c * sld(D.u)[j];
+  sld(D.af)[j] = 0.f;
+}
+
+__global__ void __launch_bounds__(kBlock) k_s4_step(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const double *sc = sld(D.sc);
+  if (sc[SC_STOP] != 0.0) return;   // uniform over the block: no partial is read after a stop
+  const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW];
+  const float cu = (float)(sc[SC_ALPHA] * sc[SC_SU]);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (j < sld(D.m)) {
+    float *aw = sld(D.aw), *af = sld(D.af);
+    const float u = sld(D.u)[j];
+    const float z = u + aw[j];
+    const float q = af[j] + cf * z;
+    af[j] = q;
+    aw[j] = cu * u - cw * z;
+    const double r = (double)sld(D.g)[j] - (double)q;
+    dot = r * r;
+  }
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
+}
+
 // partial of v . p (alpha^2 when the V-cycle is a single exact solve)
 __global__ void __launch_bounds__(kBlock) k_dot_vp(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
   double dot = 0.0;
   if (j < sld(D.n)) dot = (double)sld(D.v)[j] * (double)sld(D.p)[j];
@@ -723,6 +800,14 @@ void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n) {
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n) {
   const unsigned g = blocks_for(n);
   LAUNCH(k_dot_vp, g, B, d);
+  return (int)g;
+}
+void launch_s4_begin(hipStream_t st, InstDesc *const *d, int B, long long m) {
+  LAUNCH(k_s4_begin, blocks_for(m), B, d);
+}
+int launch_s4_step(hipStream_t st, InstDesc *const *d, int B, long long m) {
+  const unsigned g = blocks_for(m);
+  LAUNCH(k_s4_step, g, B, d);
   return (int)g;
 }
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n) {

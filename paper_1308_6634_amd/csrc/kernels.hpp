@@ -63,13 +63,14 @@ void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
 // nx % 4 == 0)
 void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
 // separable blur passes (blur.hip); the x pass takes 16-byte windows when nx % 4 == 0
+// groups: 4-output groups per thread when nx % 4 == 0 (1, 2 or 4; 0: default)
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi);
-int launch_blur_strip(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                      int src, int dst, int adj, int epi, int depth);
+                  int adj, int epi, int groups);
+// y (axis 1) or z (axis 2) pass; window: outputs per thread along the axis (4, 8, 16 or 32;
+// 0: default)
+int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
+                     int src, int dst, int adj, int epi, int window);
 // x and y passes in one kernel (nx % 4 == 0, ny > 1)
-int launch_blur_xy(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int src,
-                   int dst, int adj, int epi);
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
                      int rows);
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
@@ -87,5 +88,8 @@ void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmAr
 void launch_split_matrix(hipStream_t st, const float *A, void *hi, void *lo, long long count);
 void launch_transpose16(hipStream_t st, const void *in, void *out, long long R, long long C);
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
+// S4 residual recurrence (kernels.hip)
+void launch_s4_begin(hipStream_t st, InstDesc *const *d, int B, long long m);
+int launch_s4_step(hipStream_t st, InstDesc *const *d, int B, long long m);
 
 }  // namespace plsqr

@@ -27,11 +27,14 @@ enum ScalarSlot : int {
   SC_SV,          // 1/alpha_i: scale of the stored p and v
   SC_CF,          // phi_i / rho_i   (f update)
   SC_CW,          // theta_{i+1} / rho_i (w update)
-  SC_STOP,        // 1 once the Krylov process terminated (breakdown) this outer step
+  SC_STOP,        // 1 once MLSQR ended in this outer step (breakdown or S4) or the outer
+                  // loop has stopped
   SC_DONE,        // MLSQR steps completed in this outer step
   SC_STATUS,      // 0 or a PLSQR_E_* code (sticky for the whole request)
   SC_OUTER,       // current outer index k (0 before the first)
   SC_LAMBDA,      // sqrt(tau)
+  SC_HALT,        // 1 once the outer stop has fired: later outer steps change nothing
+  SC_S4R,         // ||g - A f_i|| of the last completed step (S4 recurrence)
   SC_COUNT = 16
 };
 
@@ -57,6 +60,7 @@ struct InstDesc {
   double tau, eps;
   double cheb_theta, cheb_delta, cheb_sigma;
   float taps[kMaxTaps];
+  float taps_rev[kMaxTaps];          // taps reversed (the adjoint's correlation weights)
   const float *g;                    // data (n_Y)
   const float *A;                    // dense operator (row-major n_Y x n_X) or null
   float *f, *u, *p, *v, *w, *kappa;  // Krylov vectors (u has n_Y entries)
@@ -68,7 +72,14 @@ struct InstDesc {
   double *cfac;                      // coarsest level: Cholesky factor, L^{-1}, A^{-1} (3 x nc x nc)
   double *diag;                      // (outer + 1) x DG_COUNT records
   int nc, colchunks;
-  int gemv_rows, strip_depth;        // tiling of the dense forward product / blur passes
+  int gemv_rows;                     // rows of A per block of the dense forward product
+  int blur_window;                   // outputs per thread of the y/z blur passes (0: default)
+  int blur_xgroups;                  // 4-output groups per thread of the x pass (0: default)
+  int stop_flags;                    // PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER bits
+  int outer_min;                     // first outer step checked by the outer stop
+  double s4_level;                   // eta * delta
+  double outer_rtol;
+  float *aw, *af;                    // S4 residual recurrence (n_Y each): see k_s4_step
   LevelDesc lv[kMaxLevels];
 };
 
@@ -85,9 +96,15 @@ enum Epi : int {
   EPI_RESID         // partial ||g - y||^2 (nothing stored)
 };
 
+// Mask bits or-ed into a product's epilogue code by the driver for problems with adaptive
+// stops: the launch does nothing for an instance whose MLSQR has ended in this outer step
+// (inner products) or whose outer loop has ended (the per-outer residual product).
+constexpr int EPI_MASK_INNER = 0x100;
+constexpr int EPI_MASK_OUTER = 0x200;
+
 // Reduction finalisers (one block per instance).
 enum Fin : int {
-  FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY
+  FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY, FIN_S4
 };
 
 }  // namespace plsqr

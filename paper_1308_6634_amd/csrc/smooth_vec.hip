@@ -304,11 +304,14 @@ __device__ __forceinline__ void body_restrict(const InstDesc &D, const LevelDesc
 // ------------------------------------------------------------------------------------
 // One-pass kernels (one body per thread)
 // ------------------------------------------------------------------------------------
-#define ROW_INDEX() (4 * ((long long)blockIdx.x * kBlock + threadIdx.x))
+// the z-neighbour planes of a block's rows belong to blocks nx*ny/1024 tiles away: xcd_tile
+// keeps them on the same XCD
+#define ROW_INDEX() (4 * (xcd_tile() * kBlock + threadIdx.x))
 
 __global__ void __launch_bounds__(kBlock) k_jacobi4(InstDesc *const *descs, int l, int first,
                                                    int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   double dot = 0.0;
@@ -319,6 +322,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi4(InstDesc *const *descs, int 
 __global__ void __launch_bounds__(kBlock) k_jacobi_first2_4(InstDesc *const *descs, int l,
                                                            int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   double dot = 0.0;
@@ -329,6 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_first2_4(InstDesc *const *des
 __global__ void __launch_bounds__(kBlock) k_jacobi_prolong4(InstDesc *const *descs, int l,
                                                            int src_sel, int dst_sel, int want_dot) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
   double dot = 0.0;
@@ -339,6 +344,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_prolong4(InstDesc *const *des
 __global__ void __launch_bounds__(kBlock) k_cheb_first4(InstDesc *const *descs, int l, int last,
                                                        int dn_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   if (j >= L.n) return;
@@ -350,6 +356,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_first4(InstDesc *const *descs, 
 __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong4(InstDesc *const *descs, int l,
                                                                int d_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
   if (j < L.n) body_cheb_start_prolong(D, L, Cl, l, j, d_sel);
@@ -358,6 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_start_prolong4(InstDesc *const 
 __global__ void __launch_bounds__(kBlock) k_cheb_start4(InstDesc *const *descs, int l, int zero_x,
                                                        int d_sel) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l);
   const long long j = ROW_INDEX();
   if (j < L.n) body_cheb_start(D, L, l, j, zero_x, d_sel);
@@ -368,6 +376,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step4(InstDesc *const *descs, i
                                                       int dn_sel, int step, int want_dot,
                                                       int add_prolong) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc L = level_of(D, l), Cl = level_of(D, l + 1);
   const long long j = ROW_INDEX();
   float c_dd, c_dr;
@@ -382,6 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_step4(InstDesc *const *descs, i
 __global__ void __launch_bounds__(kBlock) k_restrict4(InstDesc *const *descs, int l, int x_sel,
                                                      int use_r) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   const LevelDesc F = level_of(D, l), Cl = level_of(D, l + 1);
   const long long J = 2 * ((long long)blockIdx.x * kBlock + threadIdx.x);
   if (J < Cl.n) body_restrict(D, F, Cl, l, J, x_sel, use_r);
@@ -433,6 +443,7 @@ __device__ void tail_coarse_solve(const InstDesc &D, const LevelDesc &L, double 
 
 __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail(InstDesc *const *descs, int t) {
   const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
   __shared__ double bs[PLSQR_MAX_COARSE];
   const int Lv = sld(D.levels);
   const int nu = sld(D.nu_pre);

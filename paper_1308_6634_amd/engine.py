@@ -13,12 +13,21 @@ from . import plsqr as P
 
 def problem_struct(p, flags=0, precision=P.PLSQR_PREC_FP32, knobs=None):
     """plsqr_problem from any object with the problem fields (dims, reg, T, tau, eps, outer,
-    inner, levels, smoother, nu_pre, nu_post, omega, cheb_degree, cheb_lo, cheb_hi);
+    inner, levels, smoother, nu_pre, nu_post, omega, cheb_degree, cheb_lo, cheb_hi, and
+    optionally the stop fields stop_s4, eta, delta, stop_outer, outer_rtol, outer_min);
     ``knobs`` sets tiling fields (tune_*)."""
+    stop = 0
+    if getattr(p, "stop_s4", False):
+        stop |= P.PLSQR_FLAG_STOP_S4
+    if getattr(p, "stop_outer", False):
+        stop |= P.PLSQR_FLAG_STOP_OUTER
     pb = P.make_problem(tuple(p.dims), reg=p.reg, T=p.T, tau=p.tau, eps=p.eps, outer=p.outer,
                         inner=p.inner, levels=p.levels, smoother=p.smoother, nu_pre=p.nu_pre,
                         nu_post=p.nu_post, omega=p.omega, cheb_degree=p.cheb_degree,
-                        cheb_lo=p.cheb_lo, cheb_hi=p.cheb_hi, precision=precision, flags=flags)
+                        cheb_lo=p.cheb_lo, cheb_hi=p.cheb_hi, precision=precision,
+                        flags=flags | stop, eta=getattr(p, "eta", 1.1),
+                        delta=getattr(p, "delta", 0.0), outer_rtol=getattr(p, "outer_rtol", 0.0),
+                        outer_min=getattr(p, "outer_min", 3))
     for k, v in (knobs or {}).items():
         if k.startswith("tune_"):
             setattr(pb, k, int(v))
@@ -101,8 +110,9 @@ class Engine:
         P.plsqr_wait_all(self.handle)
 
 
-def solve(problem, device=0, flags=0, engine=None):
-    """Run one problem (a gen.Problem-like object) and return (f as numpy, plsqr_result)."""
+def solve(problem, device=0, flags=0, engine=None, knobs=None):
+    """Run one problem (a gen.Problem-like object) and return (f as numpy, plsqr_result).
+    ``knobs``: tiling fields (tune_*) for the problem struct."""
     own = engine is None
     eng = engine or Engine(device)
     try:
@@ -113,7 +123,7 @@ def solve(problem, device=0, flags=0, engine=None):
             op_id = eng.dense_operator(tuple(problem.dims), problem.A)
         g = torch.from_numpy(np.ascontiguousarray(problem.g, dtype=np.float32).ravel()).to(dev)
         f = torch.zeros(problem.n_x, dtype=torch.float32, device=dev)
-        t = eng.submit(op_id, problem_struct(problem, flags=flags), g, f)
+        t = eng.submit(op_id, problem_struct(problem, flags=flags, knobs=knobs), g, f)
         st, res = eng.wait(t)
         if st != P.PLSQR_OK:
             raise P.PlsqrError(st, P.plsqr_last_error(eng.handle))

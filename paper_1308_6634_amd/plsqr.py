@@ -36,6 +36,8 @@ PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED, PLSQR_PREC_BF16 = 0, 1, 2
 PLSQR_ENGINE_SERVE = 1
 PLSQR_FLAG_TIME_PRODUCTS = 1
 PLSQR_FLAG_NO_GRAPHS = 2
+PLSQR_FLAG_STOP_S4 = 4
+PLSQR_FLAG_STOP_OUTER = 8
 PLSQR_MAX_LEVELS = 12
 PLSQR_MAX_OUTER = 64
 PLSQR_MAX_RADIUS = 16
@@ -67,7 +69,10 @@ class plsqr_problem(ctypes.Structure):
                 ("cheb_degree", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("tune_gemv_rows", ctypes.c_int32),
-                ("tune_col_chunks", ctypes.c_int32), ("tune_strip_depth", ctypes.c_int32)]
+                ("tune_col_chunks", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("delta", ctypes.c_double),
+                ("outer_rtol", ctypes.c_double), ("outer_min", ctypes.c_int32),
+                ("tune_blur_window", ctypes.c_int32), ("tune_blur_xgroups", ctypes.c_int32)]
 
 
 class plsqr_result(ctypes.Structure):
@@ -210,7 +215,10 @@ def dense_operator(dims, n_y, A_dev, A_hi_dev=None, A_lo_dev=None):
 
 def make_problem(dims, reg="stv", T=0.01, tau=1.0, eps=1e-6, outer=1, inner=1, levels=0,
                  smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8, cheb_degree=3,
-                 cheb_lo=1.0 / 3.0, cheb_hi=2.0, precision=PLSQR_PREC_FP32, flags=0):
+                 cheb_lo=1.0 / 3.0, cheb_hi=2.0, precision=PLSQR_PREC_FP32, flags=0,
+                 eta=1.1, delta=0.0, outer_rtol=0.0, outer_min=3):
+    """plsqr_problem; the stop parameters matter only with PLSQR_FLAG_STOP_S4 (eta, delta)
+    and PLSQR_FLAG_STOP_OUTER (outer_rtol, outer_min)."""
     pb = plsqr_problem()
     pb.nx, pb.ny, pb.nz = dims
     pb.reg = REG_CODES[reg] if isinstance(reg, str) else int(reg)
@@ -220,4 +228,5 @@ def make_problem(dims, reg="stv", T=0.01, tau=1.0, eps=1e-6, outer=1, inner=1, l
     pb.nu_pre, pb.nu_post, pb.omega = nu_pre, nu_post, omega
     pb.cheb_degree, pb.cheb_lo, pb.cheb_hi = cheb_degree, cheb_lo, cheb_hi
     pb.precision, pb.flags = precision, flags
+    pb.eta, pb.delta, pb.outer_rtol, pb.outer_min = eta, delta, outer_rtol, outer_min
     return pb

@@ -59,3 +59,40 @@ def test_create_errors_without_arguments():
         P.plsqr_create(device=-1)
     assert P.plsqr_destroy(None) == 0
     assert isinstance(P.plsqr_last_error(), str)
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a struct of include/plsqr.h, compiled by the host C compiler."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("name", ["plsqr_problem", "plsqr_operator", "plsqr_result"])
+def test_ctypes_structs_match_the_header(name, tmp_path):
+    from paper_1308_6634_amd import plsqr as P
+    cls = getattr(P, name)
+    fields = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(name, fields, tmp_path)
+    assert size == __import__("ctypes").sizeof(cls)
+    assert offs == [getattr(cls, f).offset for f in fields]
+
+
+def test_workspace_bytes_hold_the_s4_vectors():
+    from paper_1308_6634_amd import plsqr as P
+    pb = P.make_problem((64, 64, 64), outer=8, inner=40, levels=5)
+    base = P.plsqr_workspace_bytes(pb, P.PLSQR_OP_DENSE, 4096)
+    pb.flags = P.PLSQR_FLAG_STOP_S4
+    pb.eta, pb.delta = 1.1, 1.0
+    s4 = P.plsqr_workspace_bytes(pb, P.PLSQR_OP_DENSE, 4096)
+    assert s4 - base >= 2 * 4 * 4096
+    pb.flags = P.PLSQR_FLAG_STOP_OUTER
+    assert P.plsqr_workspace_bytes(pb, P.PLSQR_OP_DENSE, 4096) == base

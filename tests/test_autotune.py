@@ -31,6 +31,6 @@ def test_apply_sets_only_the_interval():
     import gen
     from paper_1308_6634_amd.autotune import apply, knob_fields
     p = gen.config_c3(n=16, outer=1, inner=2)
-    q = apply(p, {"cheb_lo": 0.25, "tune_strip_depth": 16})
+    q = apply(p, {"cheb_lo": 0.25, "tune_blur_window": 16})
     assert q.cheb_lo == 0.25 and q.cheb_hi == p.cheb_hi and q.g is p.g
-    assert knob_fields({"cheb_lo": 0.25, "tune_strip_depth": 16}) == {"tune_strip_depth": 16}
+    assert knob_fields({"cheb_lo": 0.25, "tune_blur_window": 16}) == {"tune_blur_window": 16}

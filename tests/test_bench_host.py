@@ -61,17 +61,20 @@ def test_dominant_bytes():
         pass
 
     p = P()
+    # blur: algorithmic bytes are v read, u read and written; the kernels move 2k + 1 vectors
     p.dims, p.op_kind = (8, 8, 8), "blur"
-    assert bench.dominant_bytes(p)[0] == 4 * 512 * 5        # fused xy + z: 2 reads + u, 2 writes
-    p.dims = (6, 8, 8)
-    assert bench.dominant_bytes(p)[0] == 4 * 384 * 7        # 3 separate passes
-    p.dims = (16, 8, 1)
-    assert bench.dominant_bytes(p)[0] == 4 * 128 * 3        # one fused kernel
-    p.dims = (10, 8, 1)
-    assert bench.dominant_bytes(p)[0] == 4 * 80 * 5
+    b, _, k = bench.dominant_bytes(p)
+    assert b == 4 * 512 * 3 and k == 4 * 512 * 7          # 3 passes
+    p.dims = (6, 8, 1)
+    b, _, k = bench.dominant_bytes(p)
+    assert b == 4 * 48 * 3 and k == 4 * 48 * 5            # 2 passes
+    p.dims = (16, 1, 1)
+    b, _, k = bench.dominant_bytes(p)
+    assert b == 4 * 16 * 3 and k == 4 * 16 * 3            # 1 pass
     import numpy as np
     p.dims, p.op_kind, p.A = (4, 4, 2), "dense", np.zeros((10, 32), np.float32)
-    assert bench.dominant_bytes(p)[0] == 4 * 10 * 32 + 4 * 32 + 8 * 10
+    b, _, k = bench.dominant_bytes(p)
+    assert b == k == 4 * 10 * 32 + 4 * 32 + 8 * 10
 
 
 def test_more_than_one_gpu_exits():

@@ -109,6 +109,27 @@ def test_blur_undamped(engine):
     _check(p, engine)
 
 
+@pytest.mark.parametrize("window,xgroups", [(0, 0), (4, 1), (16, 4), (32, 2)])
+def test_blur_pass_windows(engine, window, xgroups):
+    """The y and z blur passes with 4, 8, 16 or 32 outputs per thread (ragged last windows:
+    ny = 36, nz = 20; radius 9 windows reach past both ends) and the x pass with 1, 2 or 4
+    groups per thread (nx = 40: the last thread of a row is partial) give the oracle's result,
+    and the same values for every tiling up to the order of the FP64 reduction partials (the
+    per-voxel arithmetic does not depend on the tiling; the number of partial sums does)."""
+    from paper_1308_6634_amd.engine import solve
+    p = gen.small_blur_case(18, (40, 36, 20), sigma=3.0, radius=9, reg="stv", T=0.05, tau=5.0,
+                            outer=2, inner=6, levels=3)
+    _say(f"[parity] blur pass window {window or 'default'}, x groups {xgroups or 'default'}")
+    f_gpu, _ = solve(p, engine=engine, knobs={"tune_blur_window": window,
+                                              "tune_blur_xgroups": xgroups})
+    f_ref, _ = lagged.solve_problem(p)
+    err = _rel(f_gpu, f_ref)
+    _say(f"[parity] window={window} xgroups={xgroups}: rel L2 = {err:.3e}")
+    assert err <= TOL
+    base, _ = solve(p, engine=engine)
+    assert _rel(f_gpu, base) <= 1e-6
+
+
 def test_blur_non_power_of_two_levels(engine):
     p = gen.small_blur_case(17, (24, 24, 24), reg="stv", T=0.02, tau=30.0, outer=2, inner=8,
                             levels=4)   # 24 -> 12 -> 6 -> 3 (27 coarse cells)
