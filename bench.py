@@ -26,6 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Matrix-free ring product: 6 flops per entry (r_s r_d, + 1, 1/t, a c, * v, + acc). The issue
+# model: 256 CUs x 4 SIMDs at 2.4 GHz; the 157.3 TFLOP/s FP32 vector peak counts packed (two per
+# lane) FMAs on 16 lanes per SIMD per clock, so unpacked FP32 operations (this build compiles
+# without packed FP32) run 16 lanes per SIMD per clock and the reciprocal, a transcendental, at
+# a quarter of that. An entry takes 3 unpacked operations and one reciprocal, 3/16 + 1/4
+# SIMD-clocks per lane, so at most 256 * 4 * 2.4e9 / (3/16 + 1/4) = 5.6e12 entries/s.
+RING_FLOPS_PER_ENTRY = 6
+RING_ENTRY_PEAK = 256 * 4 * 2.4e9 / (3.0 / 16.0 + 1.0 / 4.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -217,6 +226,9 @@ def main():
                          "(S4 with eta = 1.1 and the drawn noise norm as delta, the configured "
                          "inner count as the cap; outer stop once R(f^k) stops decreasing, checked "
                          "from k = 3) and compare its result with the fixed-count one")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="c2: apply the ring sensitivity through its geometry (entries recomputed "
+                         "in every product) instead of the stored 4096 x 262144 matrix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) autotuning of tiling knobs before the warm-up")
@@ -265,12 +277,14 @@ def main():
     print(f"[bench] workload {args.workload}: {desc}", file=sys.stderr, flush=True)
     eng = Engine(0)
     settings, tune_report = {}, None
-    if not args.no_tune:
+    if not args.no_tune and not args.matrix_free:   # no tiling knob applies to the ring products
         from paper_1308_6634_amd import autotune
         settings, tune_report = autotune.tune(p, eng)
         p = autotune.apply(p, settings)
         print(f"[bench] autotuned: {settings}", file=sys.stderr, flush=True)
-    if p.op_kind == "dense":
+    if p.op_kind == "dense" and args.matrix_free:
+        op = eng.ring_operator(p.dims, *p.extra["ring"])
+    elif p.op_kind == "dense":
         op = eng.dense_operator(p.dims, p.A)
     else:
         op = eng.blur_operator(p.dims, p.taps)
@@ -301,6 +315,22 @@ def main():
     avg_fwd_s = fwd_ms / max(fwd_n, 1) / 1e3
     nbytes, kname, pass_bytes = dominant_bytes(p)
     achieved = nbytes / avg_fwd_s / 1e9 if avg_fwd_s > 0 else None
+    roofline = None
+    if args.matrix_free:
+        # ALU-bound: per entry r_s r_d + 1 (FMA), 1/t, a c (multiply), times v, accumulate
+        entries = int(p.n_y) * n
+        # peak: the entry issue limit (3 unpacked FP32 operations and a reciprocal per entry)
+        # expressed in the same 6 flops per entry as the achieved figure
+        alu_peak = RING_FLOPS_PER_ENTRY * RING_ENTRY_PEAK / 1e12
+        alu = RING_FLOPS_PER_ENTRY * entries / avg_fwd_s / 1e12
+        roofline = {"bound": "alu", "kernel": "k_ring_fwd + k_ring_fwd_sum + k_ring_fwd_reduce "
+                    "(forward product, entries regenerated)", "achieved": alu, "peak": alu_peak,
+                    "unit": "TFLOP/s", "frac": alu / alu_peak,
+                    "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                    "traffic": None, "entries_per_launch": entries,
+                    "entries_per_s": entries / avg_fwd_s, "entry_peak_per_s": RING_ENTRY_PEAK,
+                    "entry_frac": entries / avg_fwd_s / RING_ENTRY_PEAK,
+                    "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)}
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -328,14 +358,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "n_x": n, "n_y": int(p.n_y),
+        "config": {"workload": f"{args.workload}: {desc}" + (
+                       "; matrix-free: entries regenerated from the source/detector positions in "
+                       "every product" if args.matrix_free else ""), "n_x": n, "n_y": int(p.n_y),
                    "outer": p.outer, "inner": p.inner, "precision": "fp32 vectors, fp64 scalars",
                    "autotuned": settings},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "bytes_per_launch": nbytes,
-                     "kernel_bytes_per_launch": pass_bytes,
-                     "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)},
+        "roofline": roofline or {
+            "bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic, "bytes_per_launch": nbytes, "kernel_bytes_per_launch": pass_bytes,
+            "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)},
     }
     if args.stop:
         out["adaptive"] = adaptive_run(args, eng, op, p, settings, g, f)

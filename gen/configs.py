@@ -97,11 +97,13 @@ def make_blur_problem(name, f_true, rng, sigma, radius, noise_frac, **kw):
                    noise_sd=sd, delta=delta, extra={"sigma": sigma}, **kw)
 
 
-def make_dense_problem(name, f_true, rng, A, noise_frac, **kw):
+def make_dense_problem(name, f_true, rng, A, noise_frac, ring=None, **kw):
+    """``ring`` = (sources, detectors, mu) of the sensitivity A, kept for the matrix-free form."""
     g, sd, delta = ops.dense_data(rng, A, f_true, noise_frac)
     nz, ny, nx = f_true.shape
+    extra = {"ring": ring} if ring is not None else {}
     return Problem(name=name, dims=(nx, ny, nz), f_true=f_true, g=g, op_kind="dense", A=A,
-                   noise_sd=sd, delta=delta, **kw)
+                   noise_sd=sd, delta=delta, extra=extra, **kw)
 
 
 def config_c1(seed=0, n=64, outer=10, inner=50):
@@ -116,9 +118,11 @@ def config_c1(seed=0, n=64, outer=10, inner=50):
 def config_c2(seed=1, n=64, outer=8, inner=40, A=None):
     rng = np.random.default_rng(seed)
     f = phantoms.ellipsoids_3d(rng, n, count=5)
+    mu = 0.5 * 64.0 / n
     if A is None:
-        A = ops.dense_sensitivity(n, mu=0.5 * 64.0 / n)
-    return make_dense_problem("c2", f, rng, A, noise_frac=0.01, reg="pm_log", T=0.05, tau=20.0,
+        A = ops.dense_sensitivity(n, mu=mu)
+    return make_dense_problem("c2", f, rng, A, noise_frac=0.01, ring=(*ops.ring_points(n), mu),
+                              reg="pm_log", T=0.05, tau=20.0,
                               eps=1e-6, outer=outer, inner=inner, levels=auto_levels((n, n, n)),
                               smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8)
 
@@ -146,7 +150,8 @@ def config_c4(i, A, n=64, outer=8, inner=40):
     else:
         reg, T = "pm_log", 0.05
     f = phantoms.ellipsoids_3d(rng, n, count=5)
-    return make_dense_problem(f"c4_{i}", f, rng, A, noise_frac=0.01, reg=reg, T=T, tau=20.0,
+    return make_dense_problem(f"c4_{i}", f, rng, A, noise_frac=0.01,
+                              ring=(*ops.ring_points(n, 8, 4), 0.5 * 64.0 / n), reg=reg, T=T, tau=20.0,
                               eps=1e-6, outer=outer, inner=inner, levels=auto_levels((n, n, n)),
                               smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8)
 
@@ -205,11 +210,12 @@ def small_dense_case(seed, n, reg="pm_log", T=0.05, tau=20.0, outer=3, inner=8, 
     """Small cubic dense problem (ring sensitivity scaled to n) with an ellipsoid phantom."""
     rng = np.random.default_rng(seed)
     f = phantoms.ellipsoids_3d(rng, n, count=3)
+    mu = 0.5 * 64.0 / n / 4.0
     if A is None:
-        A = ops.dense_sensitivity(n, mu=0.5 * 64.0 / n / 4.0, n_src_rings=n_src_rings,
-                                  n_det_rings=n_det_rings)
+        A = ops.dense_sensitivity(n, mu=mu, n_src_rings=n_src_rings, n_det_rings=n_det_rings)
     if levels is None:
         levels = auto_levels((n, n, n))
-    return make_dense_problem(f"dense_{n}_s{seed}", f, rng, A, noise_frac=noise_frac, reg=reg,
+    return make_dense_problem(f"dense_{n}_s{seed}", f, rng, A, noise_frac=noise_frac,
+                              ring=(*ops.ring_points(n, n_src_rings, n_det_rings), mu), reg=reg,
                               T=T, tau=tau, eps=eps, outer=outer, inner=inner, levels=levels,
                               smoother=smoother, nu_pre=2, nu_post=2, omega=0.8)

@@ -80,10 +80,15 @@ def _voxel_distances(points, n):
     return out
 
 
+def ring_points(n, n_src_rings=4, n_det_rings=4, per_ring=16):
+    """Source and detector positions of the default ring layout."""
+    src_z, det_z = default_rings(n, n_src_rings, n_det_rings)
+    return ring_geometry(n, src_z, det_z, per_ring)
+
+
 def dense_sensitivity(n, mu=0.5, n_src_rings=4, n_det_rings=4, per_ring=16, threads=8):
     """Row-major float32 matrix of shape (n_src*n_det, n^3); row index = s*n_det + d."""
-    src_z, det_z = default_rings(n, n_src_rings, n_det_rings)
-    src, det = ring_geometry(n, src_z, det_z, per_ring)
+    src, det = ring_points(n, n_src_rings, n_det_rings, per_ring)
     ds = _voxel_distances(src, n)
     dd = _voxel_distances(det, n)
     es, ed = np.exp(-mu * ds), np.exp(-mu * dd)

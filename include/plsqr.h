@@ -50,7 +50,7 @@ enum {
 };
 
 /* ---- enumerations ---------------------------------------------------------------- */
-enum { PLSQR_OP_BLUR = 1, PLSQR_OP_DENSE = 2 };
+enum { PLSQR_OP_BLUR = 1, PLSQR_OP_DENSE = 2, PLSQR_OP_RING = 3 };
 /* r(t) of eq. (1.3) (Tikhonov), (1.4) smoothed TV, (1.5) Perona-Malik log / exp forms */
 enum { PLSQR_REG_TIKHONOV = 0, PLSQR_REG_STV = 1, PLSQR_REG_PM_LOG = 2, PLSQR_REG_PM_EXP = 3 };
 enum { PLSQR_SMOOTH_JACOBI = 0, PLSQR_SMOOTH_CHEBYSHEV = 1 };
@@ -107,6 +107,15 @@ typedef struct plsqr_engine plsqr_engine;   /* opaque; owns all internal device 
  *                  (BORROWED). A_hi_dev / A_lo_dev are optional bf16 (uint16 bit
  *                  pattern) copies with the same layout: A_hi = bf16(A),
  *                  A_lo = bf16(A - A_hi); they are used by PLSQR_PREC_BF16_REFINED.
+ *  PLSQR_OP_RING : the dense source-detector sensitivity of PLSQR_OP_DENSE's workloads,
+ *                  never stored: entry (s * n_det + d, j) is
+ *                      exp(-mu (r_sj + r_dj)) / (r_sj r_dj + 1),
+ *                  r_sj, r_dj the distances from voxel centre j = (x, y, z) (integer
+ *                  coordinates, x fastest) to source s and detector d. src_xyz (3 n_src
+ *                  floats) and det_xyz (3 n_det) are HOST pointers copied during the call;
+ *                  n_y = n_src * n_det (at most 16384), mu > 0. The products recompute the
+ *                  entries (a stand-in for a forward map available only by its action,
+ *                  Section 1, as the FEM solves of Section 5 are).
  */
 typedef struct {
   int32_t kind;
@@ -118,6 +127,11 @@ typedef struct {
   const float *A_dev;
   const uint16_t *A_hi_dev;
   const uint16_t *A_lo_dev;
+  /* PLSQR_OP_RING */
+  int32_t n_src, n_det;
+  const float *src_xyz;
+  const float *det_xyz;
+  double mu;
 } plsqr_operator;
 
 /* One reconstruction. Grid must equal the operator's grid.
@@ -241,7 +255,9 @@ const char *plsqr_last_error(const plsqr_engine *eng);
 int plsqr_auto_levels(int32_t nx, int32_t ny, int32_t nz);
 
 /* Bytes of device workspace one request of this problem needs (for HBM budgeting);
- * 0 if the arguments are invalid. op_kind is PLSQR_OP_*, n_y the operator's row count. */
+ * 0 if the arguments are invalid (the problem is validated as plsqr_solve does, against an
+ * operator of kind op_kind on the problem's grid). op_kind is PLSQR_OP_*, n_y the operator's
+ * row count. */
 uint64_t plsqr_workspace_bytes(const plsqr_problem *prob, int32_t op_kind, int64_t n_y);
 
 #ifdef __cplusplus

@@ -107,6 +107,17 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.outer_min = pb.outer_min;
   D.aw = Ly.aw ? F(Ly.aw) : nullptr;
   D.af = Ly.af ? F(Ly.af) : nullptr;
+  if (op.op.kind == PLSQR_OP_RING) {
+    D.ring = op.ring;
+    D.ringpart = F(Ly.ringpart);
+    D.n_src = op.op.n_src;
+    D.n_det = op.op.n_det;
+    D.ring_chunk = Ly.ring_chunk;
+    D.ring_chunks = Ly.ring_chunks;
+    D.ring_groups = Ly.ring_groups;
+    D.ringpart2 = F(Ly.ringpart2);
+    D.ring_mu = (float)op.op.mu;
+  }
   const int d = pb.nz > 1 ? 3 : 2;
   for (int l = 0; l < Ly.levels; ++l) {
     LevelDesc &L = D.lv[l];
@@ -758,9 +769,18 @@ int plsqr_auto_levels(int32_t nx, int32_t ny, int32_t nz) {
 
 uint64_t plsqr_workspace_bytes(const plsqr_problem *prob, int32_t op_kind, int64_t n_y) {
   if (!prob || n_y < 1) return 0;
-  if (op_kind != PLSQR_OP_BLUR && op_kind != PLSQR_OP_DENSE) return 0;
-  int levels = prob->mg_levels ? prob->mg_levels : plsqr_auto_levels(prob->nx, prob->ny, prob->nz);
-  if (levels < 1 || levels > kMaxLevels) return 0;
+  if (op_kind != PLSQR_OP_BLUR && op_kind != PLSQR_OP_DENSE && op_kind != PLSQR_OP_RING) return 0;
+  if (op_kind == PLSQR_OP_RING && n_y > kRingMaxRows) return 0;
+  // the full problem validation against an operator of this kind on the problem's grid
+  Operator op;
+  op.op.kind = op_kind;
+  op.op.nx = prob->nx;
+  op.op.ny = prob->ny;
+  op.op.nz = prob->nz;
+  op.op.n_y = n_y;
+  int levels = 0;
+  std::string why;
+  if (validate(*prob, &op, &levels, &why) != PLSQR_OK) return 0;
   return make_layout(*prob, n_y, levels, op_kind).total;
 }
 
@@ -809,6 +829,26 @@ int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_
   } else if (op->kind == PLSQR_OP_DENSE) {
     if (op->n_y < 1) return set_error(PLSQR_E_INVALID, "dense operator needs n_y >= 1");
     if (!op->A_dev) return set_error(PLSQR_E_INVALID, "dense operator needs A_dev");
+  } else if (op->kind == PLSQR_OP_RING) {
+    if (op->n_src < 1 || op->n_det < 1 || (int64_t)op->n_src * op->n_det > kRingMaxRows)
+      return set_error(PLSQR_E_INVALID, "ring operator needs n_src, n_det >= 1, n_src * n_det <= 16384");
+    if (!op->src_xyz || !op->det_xyz) return set_error(PLSQR_E_INVALID, "ring positions are NULL");
+    if (!(op->mu > 0.0 && std::isfinite(op->mu))) return set_error(PLSQR_E_INVALID, "ring mu must be > 0");
+    std::vector<float> geo(op->src_xyz, op->src_xyz + 3 * op->n_src);
+    geo.insert(geo.end(), op->det_xyz, op->det_xyz + 3 * op->n_det);
+    for (float c : geo)
+      if (!std::isfinite(c)) return set_error(PLSQR_E_INVALID, "ring positions must be finite");
+    DeviceGuard dg(eng->device);
+    if (hipMalloc(&o.ring, geo.size() * sizeof(float)) != hipSuccess)
+      return set_error(PLSQR_E_NOMEM, "allocation of the ring positions failed");
+    if (hipMemcpy(o.ring, geo.data(), geo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(o.ring);
+      return set_error(PLSQR_E_HIP, "copy of the ring positions failed");
+    }
+    o.op.n_y = (int64_t)op->n_src * op->n_det;
+    o.op.src_xyz = o.op.det_xyz = nullptr;
+    o.op.A_dev = nullptr;
+    o.op.A_hi_dev = o.op.A_lo_dev = nullptr;
   } else {
     return set_error(PLSQR_E_INVALID, "unknown operator kind");
   }
@@ -942,6 +982,7 @@ int plsqr_destroy(plsqr_engine *eng) {
       if (op.own_A_lo && op.A_lo) hipFree(op.A_lo);
       if (op.At_hi) hipFree(op.At_hi);
       if (op.At_lo) hipFree(op.At_lo);
+      if (op.ring) hipFree(op.ring);
     }
     eng->ops.clear();
     eng->pool.trim();

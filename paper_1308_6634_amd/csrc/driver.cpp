@@ -136,7 +136,17 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
     L.af = take((size_t)L.m * sizeof(float));
   }
   L.colchunks = 0;
-  if (!dense) {
+  if (op_kind == PLSQR_OP_RING) {
+    // forward product: one block per chunk of voxels (a multiple of the 32-voxel staging step)
+    // writes all n_Y partial sums; about 1024 blocks per instance keep 4 waves per SIMD
+    long long ch = (L.n + 1023) / 1024;
+    ch = std::max(32LL, (ch + 31) / 32 * 32);
+    L.ring_chunk = (int)ch;
+    L.ring_chunks = (int)((L.n + ch - 1) / ch);
+    L.ringpart = take((size_t)L.ring_chunks * L.m * sizeof(float));
+    L.ring_groups = std::min(L.ring_chunks, 32);
+    L.ringpart2 = take((size_t)L.ring_groups * L.m * sizeof(float));
+  } else if (!dense) {
     L.tmp1 = take(vb);
     L.tmp2 = take(vb);
   } else {
@@ -222,6 +232,8 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR)
     np = blur_chain(st, bv, src, 0, em);
+  else if (H.op_kind == PLSQR_OP_RING)
+    np = launch_ring_forward(st, bv.d_descs, bv.B, H, src, em);
   else if (bv.gemm)
     np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, em);
   else
@@ -239,6 +251,8 @@ static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR) {
     blur_chain(st, bv, V_U, 1, em);
+  } else if (H.op_kind == PLSQR_OP_RING) {
+    launch_ring_adjoint(st, bv.d_descs, bv.B, H, em);
   } else if (bv.gemm) {
     launch_gemm_adjoint(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, em);
   } else {

@@ -23,6 +23,8 @@ struct Operator {
   // BF16 copies for batched MFMA products (built on first use; owned unless borrowed)
   void *A_hi = nullptr, *A_lo = nullptr, *At_hi = nullptr, *At_lo = nullptr;
   bool own_A_hi = false, own_A_lo = false;
+  // ring sensitivity: source then detector positions (x, y, z floats) on the device
+  float *ring = nullptr;
 };
 
 // Byte offsets of every buffer inside one request's workspace.
@@ -31,6 +33,8 @@ struct Layout {
   size_t desc = 0, descptr = 0, sc = 0, diag = 0, part = 0, cfac = 0;
   size_t f = 0, p = 0, v = 0, w = 0, kappa = 0, u = 0, tmp1 = 0, tmp2 = 0, colpart = 0;
   size_t aw = 0, af = 0;              // S4 residual recurrence vectors (n_Y), 0 when unused
+  size_t ringpart = 0, ringpart2 = 0;  // ring forward product: per-chunk and per-group partials
+  int ring_chunk = 0, ring_chunks = 0, ring_groups = 0;  // voxels per block, chunks, groups
   size_t lvl[kMaxLevels][10] = {};   // x b r t s wx wy wz dinv (unused slots 0)
   int nparts = 0, colchunks = 0, levels = 0, nc = 0;
   long long n = 0, m = 0;

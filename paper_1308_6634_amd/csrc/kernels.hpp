@@ -88,6 +88,10 @@ void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmAr
 void launch_split_matrix(hipStream_t st, const float *A, void *hi, void *lo, long long count);
 void launch_transpose16(hipStream_t st, const void *in, void *out, long long R, long long C);
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
+// matrix-free ring sensitivity products (ring.hip); the forward returns its partial count
+int launch_ring_forward(hipStream_t st, InstDesc *const *d, int B, const InstDesc &H, int src,
+                        int epi);
+void launch_ring_adjoint(hipStream_t st, InstDesc *const *d, int B, const InstDesc &H, int epi);
 // S4 residual recurrence (kernels.hip)
 void launch_s4_begin(hipStream_t st, InstDesc *const *d, int B, long long m);
 int launch_s4_step(hipStream_t st, InstDesc *const *d, int B, long long m);

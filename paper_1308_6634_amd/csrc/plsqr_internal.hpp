@@ -16,6 +16,7 @@ constexpr int kMaxLevels = PLSQR_MAX_LEVELS;
 constexpr int kMaxTaps = 2 * PLSQR_MAX_RADIUS + 1;
 constexpr int kBlock = 256;          // threads per block for grid kernels (4 wave64)
 constexpr double kTiny = 1e-300;     // exact-termination threshold for alpha, beta
+constexpr int kRingMaxRows = 16384;  // n_src * n_det of a ring operator (u staged in LDS)
 
 // FP64 scalar block of one instance (MLSQR state of Algorithm 2 with damping).
 enum ScalarSlot : int {
@@ -80,6 +81,11 @@ struct InstDesc {
   double s4_level;                   // eta * delta
   double outer_rtol;
   float *aw, *af;                    // S4 residual recurrence (n_Y each): see k_s4_step
+  const float *ring;                 // ring sensitivity: 3 n_src source, 3 n_det detector coords
+  float *ringpart;                   // ring forward product partials (ring_chunks x n_Y)
+  float *ringpart2;                  // their sums over groups of chunks (ring_groups x n_Y)
+  int n_src, n_det, ring_chunk, ring_chunks, ring_groups;
+  float ring_mu;
   LevelDesc lv[kMaxLevels];
 };
 

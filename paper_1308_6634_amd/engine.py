@@ -58,6 +58,10 @@ class Engine:
         op_id = P.plsqr_set_operator(self.handle, P.blur_operator(dims, taps))
         return op_id
 
+    def ring_operator(self, dims, src_xyz, det_xyz, mu):
+        """Matrix-free ring sensitivity (entries recomputed in every product)."""
+        return P.plsqr_set_operator(self.handle, P.ring_operator(dims, src_xyz, det_xyz, mu))
+
     def dense_operator(self, dims, A, A_hi=None, A_lo=None):
         """A: float32 (n_Y, n_X) numpy array or CUDA tensor (kept alive by the engine)."""
         if not torch.is_tensor(A):
@@ -110,15 +114,18 @@ class Engine:
         P.plsqr_wait_all(self.handle)
 
 
-def solve(problem, device=0, flags=0, engine=None, knobs=None):
+def solve(problem, device=0, flags=0, engine=None, knobs=None, matrix_free=False):
     """Run one problem (a gen.Problem-like object) and return (f as numpy, plsqr_result).
-    ``knobs``: tiling fields (tune_*) for the problem struct."""
+    ``knobs``: tiling fields (tune_*) for the problem struct; ``matrix_free``: apply a dense
+    ring sensitivity through its geometry (problem.extra["ring"]) instead of the matrix."""
     own = engine is None
     eng = engine or Engine(device)
     try:
         dev = eng.device
         if problem.op_kind == "blur":
             op_id = eng.blur_operator(tuple(problem.dims), problem.taps)
+        elif matrix_free:
+            op_id = eng.ring_operator(tuple(problem.dims), *problem.extra["ring"])
         else:
             op_id = eng.dense_operator(tuple(problem.dims), problem.A)
         g = torch.from_numpy(np.ascontiguousarray(problem.g, dtype=np.float32).ravel()).to(dev)

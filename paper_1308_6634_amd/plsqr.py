@@ -30,6 +30,7 @@ PLSQR_E_UNKNOWN_TICKET = -7
 
 PLSQR_OP_BLUR = 1
 PLSQR_OP_DENSE = 2
+PLSQR_OP_RING = 3
 PLSQR_REG_TIKHONOV, PLSQR_REG_STV, PLSQR_REG_PM_LOG, PLSQR_REG_PM_EXP = 0, 1, 2, 3
 PLSQR_SMOOTH_JACOBI, PLSQR_SMOOTH_CHEBYSHEV = 0, 1
 PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED, PLSQR_PREC_BF16 = 0, 1, 2
@@ -57,7 +58,9 @@ class plsqr_operator(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("radius", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("taps", ctypes.POINTER(ctypes.c_float)), ("n_y", ctypes.c_int64),
                 ("A_dev", ctypes.c_void_p), ("A_hi_dev", ctypes.c_void_p),
-                ("A_lo_dev", ctypes.c_void_p)]
+                ("A_lo_dev", ctypes.c_void_p), ("n_src", ctypes.c_int32), ("n_det", ctypes.c_int32),
+                ("src_xyz", ctypes.POINTER(ctypes.c_float)),
+                ("det_xyz", ctypes.POINTER(ctypes.c_float)), ("mu", ctypes.c_double)]
 
 
 class plsqr_problem(ctypes.Structure):
@@ -210,6 +213,24 @@ def dense_operator(dims, n_y, A_dev, A_hi_dev=None, A_lo_dev=None):
     op.A_dev = A_dev
     op.A_hi_dev = A_hi_dev
     op.A_lo_dev = A_lo_dev
+    return op
+
+
+def ring_operator(dims, src_xyz, det_xyz, mu):
+    """plsqr_operator for the matrix-free ring sensitivity: src_xyz (n_src, 3) and det_xyz
+    (n_det, 3) positions in voxel units, attenuation mu."""
+    import numpy as np
+    s = np.ascontiguousarray(src_xyz, dtype=np.float32).reshape(-1, 3)
+    d = np.ascontiguousarray(det_xyz, dtype=np.float32).reshape(-1, 3)
+    op = plsqr_operator()
+    op.kind = PLSQR_OP_RING
+    op.nx, op.ny, op.nz = dims
+    op.n_src, op.n_det = s.shape[0], d.shape[0]
+    op.n_y = s.shape[0] * d.shape[0]
+    op.src_xyz = s.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    op.det_xyz = d.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    op.mu = float(mu)
+    op._keep = (s, d)
     return op
 
 
