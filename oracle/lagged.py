@@ -74,6 +74,24 @@ def solve(shape, op, g, reg, T, tau, eps, outer, inner, levels, smoother, histor
     return f, records
 
 
+def solve_taus(shape, op, g, reg, T, tau, eps, outer, inner, levels, smoother, taus):
+    """Algorithm 3 with the damping tau for outer steps 1..K-1, then the last outer step's
+    MLSQR solve for every damping in ``taus`` from one bidiagonalisation (Section 3.3):
+    returns the list of f^K(tau_t) and the iterations completed in the last step."""
+    g = np.asarray(g, dtype=np.float64)
+    f = np.zeros(shape)
+    if outer > 1:
+        f, _ = solve(shape, op, g, reg, T, tau, eps, outer - 1, inner, levels, smoother)
+    kappa = regularizers.diffusivity(reg, grid.grad_norm(f), T)
+    h = multigrid.Hierarchy(grid.prior_matrix(kappa, eps), shape, levels)
+
+    def apply_Minv(p):
+        return multigrid.vcycle(h, np.asarray(p).ravel(), smoother).reshape(shape)
+
+    fs, done = mlsqr.mlsqr_taus(op.apply, op.apply_T, apply_Minv, g, taus, inner)
+    return [np.asarray(x).reshape(shape) for x in fs], done
+
+
 def solve_problem(prob, history=None, outer=None, inner=None):
     """Convenience wrapper taking a ``gen.Problem``-like object (fields only, no behaviour)."""
     nx, ny, nz = prob.dims

@@ -105,3 +105,71 @@ def mlsqr(apply_A, apply_AT, apply_Minv, g, tau, iters, history=None, resid_stop
         if resid is not None and resid <= resid_stop:
             break
     return f, done
+
+
+def mlsqr_taus(apply_A, apply_AT, apply_Minv, g, taus, iters):
+    """The iterate after ``iters`` steps for every damping tau in ``taus`` from one Krylov run.
+
+    Section 3.3: the bidiagonalisation does not depend on tau, so the basis (here the
+    M-weighted vectors v_i that MLSQR combines into f) and the bidiagonal B_i are formed once;
+    for each tau the projected problem (3.6),
+        min_y || [B_i; sqrt(tau) I] y - beta_1 e_1 ||,
+    is solved (a dense least-squares solve of the stacked (2i+1) x i matrix, its definition)
+    and f(tau) = V_i y. Returns (list of f, iterations completed).
+    """
+    g = np.asarray(g, dtype=np.float64)
+    beta = float(np.linalg.norm(g))
+    shape = np.shape(apply_AT(g))
+    if beta <= TINY:
+        return [np.zeros(shape) for _ in taus], 0
+    u = g / beta
+    p = apply_AT(u)
+    v = apply_Minv(p)
+    a2 = float(np.vdot(v, p))
+    if a2 < 0.0:
+        raise NotSPD(a2)
+    alpha = math.sqrt(a2)
+    if alpha <= TINY:
+        return [np.zeros(shape) for _ in taus], 0
+    p = p / alpha
+    v = v / alpha
+    alphas, betas, basis = [alpha], [beta], [v]
+    done = 0
+    for i in range(1, iters + 1):
+        # the steps of mlsqr() (same stops): step i needs beta_{i+1} and alpha_{i+1}, and f_i
+        # combines v_1..v_i
+        u = apply_A(v) - alpha * u
+        beta = float(np.linalg.norm(u))
+        if beta <= TINY:
+            break
+        u = u / beta
+        p = apply_AT(u) - beta * p
+        v = apply_Minv(p)
+        a2 = float(np.vdot(v, p))
+        if a2 < 0.0:
+            raise NotSPD(a2)
+        alpha = math.sqrt(a2)
+        if alpha <= TINY:
+            break
+        p = p / alpha
+        v = v / alpha
+        betas.append(beta)                      # beta_{i+1}
+        alphas.append(alpha)                    # alpha_{i+1}
+        basis.append(v)                         # v_{i+1} (used from step i+1 on)
+        done = i
+    k = done
+    if k == 0:
+        return [np.zeros(shape) for _ in taus], 0
+    B = np.zeros((k + 1, k))
+    for c in range(k):
+        B[c, c] = alphas[c]
+        B[c + 1, c] = betas[c + 1]
+    rhs = np.zeros(2 * k + 1)
+    rhs[0] = betas[0]
+    V = np.stack([np.ravel(b) for b in basis[:k]], axis=1)
+    out = []
+    for tau in taus:
+        S = np.vstack([B, math.sqrt(tau) * np.eye(k)])
+        y = np.linalg.lstsq(S, rhs, rcond=None)[0]
+        out.append((V @ y).reshape(shape))
+    return out, k
