@@ -225,6 +225,17 @@ int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_
 int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, const float *g_dev,
                 float *f_dev, uint64_t *ticket);
 
+/* Several dampings from one Krylov run (Section 3.3). Runs as plsqr_solve (f_dev receives
+ * f^outer for prob->tau; outer steps 1..outer-1 use prob->tau), and in the last outer step
+ * keeps the vectors of the bidiagonalisation, which does not depend on tau: for each
+ * taus[t] (HOST array of n_tau values >= 0, copied during the call) the projected problem
+ * (3.6) is solved and f(taus[t]) = V y written to row t of f_taus_dev (DEVICE, n_tau x n_X
+ * floats, BORROWED like f_dev, written only on success). 1 <= n_tau <= 64, inner <= 1024,
+ * no stop flags, not on a serving engine. The extra workspace is inner x n_X floats. */
+int plsqr_solve_taus(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob,
+                     const float *g_dev, float *f_dev, int32_t n_tau, const double *taus,
+                     float *f_taus_dev, uint64_t *ticket);
+
 /* Submit `count` reconstructions that run in lockstep on one operator (one set of
  * launches serves all of them; with a BF16 precision the dense products become MFMA
  * GEMMs over the batch, reading A once per product for the whole batch). The problems

@@ -107,6 +107,17 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.outer_min = pb.outer_min;
   D.aw = Ly.aw ? F(Ly.aw) : nullptr;
   D.af = Ly.af ? F(Ly.af) : nullptr;
+  D.outer_count = pb.outer;
+  D.inner_count = pb.inner;
+  if (!r.taus.empty()) {
+    D.n_tau = (int)r.taus.size();
+    for (int t = 0; t < D.n_tau; ++t) D.taus[t] = r.taus[t];
+    D.basis = F(Ly.basis);
+    D.hist = reinterpret_cast<double *>(ws + Ly.hist);
+    D.tau_scr = reinterpret_cast<double *>(ws + Ly.tau_scr);
+    D.ycoef = F(Ly.ycoef);
+    D.f_taus = r.f_taus;
+  }
   if (op.op.kind == PLSQR_OP_RING) {
     D.ring = op.ring;
     D.ringpart = F(Ly.ringpart);
@@ -417,7 +428,8 @@ void progress(plsqr_engine *eng) {
 
 // Validate and register a group of requests; returns PLSQR_OK and the tickets.
 int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_problem *probs,
-                 const float *const *g_devs, float *const *f_devs, uint64_t *tickets) {
+                 const float *const *g_devs, float *const *f_devs, uint64_t *tickets,
+                 const std::vector<double> *taus = nullptr, float *f_taus = nullptr) {
   const Operator *op = (op_id >= 0 && op_id < (int)eng->ops.size()) ? &eng->ops[op_id] : nullptr;
   std::vector<Layout> lays(count);
   for (int b = 0; b < count; ++b) {
@@ -426,7 +438,7 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
     std::string why;
     const int rc = validate(probs[b], op, &levels, &why);
     if (rc != PLSQR_OK) return set_error(rc, why);
-    lays[b] = make_layout(probs[b], op->op.n_y, levels, op->op.kind);
+    lays[b] = make_layout(probs[b], op->op.n_y, levels, op->op.kind, taus ? (int)taus->size() : 0);
     const plsqr_problem &a = probs[0], &c = probs[b];
     if (c.outer != a.outer || c.inner != a.inner || lays[b].levels != lays[0].levels ||
         c.smoother != a.smoother || c.nu_pre != a.nu_pre || c.cheb_degree != a.cheb_degree ||
@@ -458,6 +470,10 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
     r->g = g_devs[b];
     r->f_out = f_devs[b];
     r->lay = lays[b];
+    if (taus) {
+      r->taus = *taus;
+      r->f_taus = f_taus;
+    }
     r->t_submit = t;
     G->members.push_back(r->ticket);
     G->bytes += r->lay.total;
@@ -855,6 +871,27 @@ int plsqr_set_operator(plsqr_engine *eng, const plsqr_operator *op, int32_t *op_
   eng->ops.push_back(o);
   *op_id = (int32_t)eng->ops.size() - 1;
   return PLSQR_OK;
+}
+
+int plsqr_solve_taus(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob,
+                     const float *g_dev, float *f_dev, int32_t n_tau, const double *taus,
+                     float *f_taus_dev, uint64_t *ticket) {
+  if (!eng || !prob || !ticket || !taus) return set_error(PLSQR_E_INVALID, "null argument");
+  if (eng->flags & PLSQR_ENGINE_SERVE)
+    return set_error(PLSQR_E_INVALID, "a serving engine takes single-damping requests");
+  if (prob->precision != PLSQR_PREC_FP32)
+    return set_error(PLSQR_E_INVALID, "single requests run in PLSQR_PREC_FP32");
+  if (n_tau < 1 || n_tau > kMaxTaus) return set_error(PLSQR_E_INVALID, "n_tau must be in [1, 64]");
+  if (!f_taus_dev) return set_error(PLSQR_E_INVALID, "f_taus_dev must be a device pointer");
+  if (prob->inner > kMaxTauInner) return set_error(PLSQR_E_INVALID, "a multi-tau solve takes inner <= 1024");
+  if (prob->flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER))
+    return set_error(PLSQR_E_INVALID, "a multi-tau solve runs fixed counts (no stop flags)");
+  std::vector<double> tv(taus, taus + n_tau);
+  for (double t : tv)
+    if (!(t >= 0.0 && std::isfinite(t))) return set_error(PLSQR_E_INVALID, "every tau must be >= 0 and finite");
+  std::lock_guard<std::mutex> lk(eng->mu);
+  DeviceGuard dg(eng->device);
+  return submit_group(eng, op_id, 1, prob, &g_dev, &f_dev, ticket, &tv, f_taus_dev);
 }
 
 int plsqr_solve(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob, const float *g_dev,

@@ -84,7 +84,7 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   return PLSQR_OK;
 }
 
-Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind) {
+Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind, int n_tau) {
   Layout L;
   L.levels = levels;
   L.n = (long long)pb.nx * pb.ny * pb.nz;
@@ -134,6 +134,12 @@ Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_ki
   if (pb.flags & PLSQR_FLAG_STOP_S4) {
     L.aw = take((size_t)L.m * sizeof(float));
     L.af = take((size_t)L.m * sizeof(float));
+  }
+  if (n_tau > 0) {
+    L.basis = take((size_t)pb.inner * L.n * sizeof(float));
+    L.hist = take((size_t)2 * (pb.inner + 1) * sizeof(double));
+    L.tau_scr = take((size_t)n_tau * pb.inner * 3 * sizeof(double));
+    L.ycoef = take((size_t)n_tau * pb.inner * sizeof(float));
   }
   L.colchunks = 0;
   if (op_kind == PLSQR_OP_RING) {
@@ -457,6 +463,7 @@ void enqueue_mlsqr_init(hipStream_t st, const BatchView &bv) {
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA_INIT);
   launch_init_wf(st, bv.d_descs, bv.B, H.n);
   if (H.stop_flags & PLSQR_FLAG_STOP_S4) launch_s4_begin(st, bv.d_descs, bv.B, H.m);
+  if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
 }
 
 // After the f/w update: the S4 residual of the new iterate, and the stop test.
@@ -476,6 +483,7 @@ void enqueue_inner(hipStream_t st, const BatchView &bv) {
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
   launch_update_fw(st, bv.d_descs, bv.B, H.n);
   enqueue_s4(st, bv);
+  if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
 }
 
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
@@ -487,6 +495,7 @@ void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
 }
 
 void enqueue_request_end(hipStream_t st, const BatchView &bv) {
+  if (bv.h->n_tau > 0) launch_tau_finish(st, bv.d_descs, bv.B, bv.h->n, bv.h->n_tau);
   launch_copy_out(st, bv.d_descs, bv.B, bv.h->n);
 }
 
@@ -527,6 +536,7 @@ static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
       launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
       launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
       enqueue_s4(s, quiet);
+      if (H.n_tau > 0) launch_basis_store(s, quiet.d_descs, quiet.B, H.n);
     });
   } else {
     ex = capture_graph(gc.cap, [&](hipStream_t s) { enqueue_inner(s, quiet); });

@@ -35,6 +35,7 @@ struct Layout {
   size_t aw = 0, af = 0;              // S4 residual recurrence vectors (n_Y), 0 when unused
   size_t ringpart = 0, ringpart2 = 0;  // ring forward product: per-chunk and per-group partials
   int ring_chunk = 0, ring_chunks = 0, ring_groups = 0;  // voxels per block, chunks, groups
+  size_t basis = 0, hist = 0, tau_scr = 0, ycoef = 0;  // multi-tau solve, 0 when unused
   size_t lvl[kMaxLevels][10] = {};   // x b r t s wx wy wz dinv (unused slots 0)
   int nparts = 0, colchunks = 0, levels = 0, nc = 0;
   long long n = 0, m = 0;
@@ -45,7 +46,7 @@ struct Layout {
 // Validate a problem against an operator; fills *levels. Returns PLSQR_OK or an error
 // with a message in *why.
 int validate(const plsqr_problem &pb, const Operator *op, int *levels, std::string *why);
-Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind);
+Layout make_layout(const plsqr_problem &pb, long long n_y, int levels, int op_kind, int n_tau = 0);
 
 // Workspace cache: freed workspaces are kept for reuse by requests of the same size.
 class Pool {
@@ -74,6 +75,8 @@ struct Request {
   plsqr_problem pb{};
   const float *g = nullptr;
   float *f_out = nullptr;
+  std::vector<double> taus;          // multi-tau solve: dampings and the caller's outputs
+  float *f_taus = nullptr;
   Layout lay;
   char *ws = nullptr;                // device workspace
   InstDesc host{};                   // host copy of the descriptor

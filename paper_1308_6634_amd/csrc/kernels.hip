@@ -528,6 +528,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       sc[SC_BETA] = beta;
       sc[SC_SU] = 1.0 / beta;
       sc[SC_PHIBAR] = beta;
+      if (double *h = sld(D.hist)) h[sld(D.inner_count) + 1] = beta;   // beta_1
       break;
     }
     case FIN_ALPHA_INIT: {
@@ -539,6 +540,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       sc[SC_ALPHA] = alpha;
       sc[SC_SV] = 1.0 / alpha;
       sc[SC_RHOBAR] = alpha;
+      if (double *h = sld(D.hist)) h[0] = alpha;   // alpha_1
       break;
     }
     case FIN_BETA: {
@@ -548,6 +550,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
       sc[SC_BETA] = beta;
       sc[SC_SU] = 1.0 / beta;
+      // beta_{i+1} of step i (SC_DONE = i - 1 steps completed so far)
+      if (double *h = sld(D.hist)) {
+        const int i = (int)sc[SC_DONE] + 1;
+        if (i <= sld(D.inner_count)) h[sld(D.inner_count) + 1 + i] = beta;
+      }
       break;
     }
     case FIN_ALPHA: {
@@ -558,6 +565,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       if (alpha <= kTiny) { sc[SC_STOP] = 1.0; break; }
       const double beta = sc[SC_BETA], lam = sc[SC_LAMBDA];
       double rhobar = sc[SC_RHOBAR], phibar = sc[SC_PHIBAR];
+      if (double *h = sld(D.hist)) {   // alpha_{i+1} of step i
+        const int i = (int)sc[SC_DONE] + 1;
+        if (i <= sld(D.inner_count)) h[i] = alpha;
+      }
       // damping rotation (row sqrt(tau) of (3.6)), then the Givens rotation with beta
       const double rhohat = hypot(rhobar, lam);
       const double c1 = rhobar / rhohat;
@@ -687,6 +698,98 @@ __global__ void __launch_bounds__(kBlock) k_s4_step(InstDesc *const *descs) {
   if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
+// ------------------------------------------------------------------------------------
+// Several dampings from one Krylov run (Section 3.3): the bidiagonalisation of the last outer
+// step does not depend on tau, so its vectors v_1.. (scaled to the normalised v of
+// Algorithm 2) are kept, and for each tau the projected problem (3.6) is solved and f(tau)
+// formed from them.
+// ------------------------------------------------------------------------------------
+// v_{i+1} (after step i; v_1 after the initialisation) into basis slot i, last outer step only.
+__global__ void __launch_bounds__(kBlock) k_basis_store(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  float *basis = sld(D.basis);
+  const double *sc = sld(D.sc);
+  if (!basis || sc[SC_STOP] != 0.0) return;
+  if ((int)sc[SC_OUTER] != sld(D.outer_count)) return;
+  const int slot = (int)sc[SC_DONE];
+  if (slot >= sld(D.inner_count)) return;
+  const long long n = sld(D.n);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  basis[(long long)slot * n + j] = (float)sc[SC_SV] * sld(D.v)[j];
+}
+
+// y(tau_t) for thread t: the damped QR of [B_k; sqrt(tau) I] by the rotations of Algorithm 2
+// with the damping of Section 3.3 (FP64, over the k = SC_DONE completed steps), then the
+// bidiagonal back substitution R y = phi; stored as float coefficients of v_1..v_k.
+__global__ void __launch_bounds__(kBlock) k_tau_solve(InstDesc *const *descs) {
+  const InstDesc &D = inst(descs);
+  const int t = threadIdx.x;
+  if (t >= sld(D.n_tau) || !sld(D.basis)) return;
+  const double *sc = sld(D.sc);
+  const int inner = sld(D.inner_count);
+  const int k = sc[SC_STATUS] != 0.0 ? 0 : (int)sc[SC_DONE];
+  const double *ha = sld(D.hist), *hb = ha + inner + 1;
+  double *scr = sld(D.tau_scr) + (long long)t * inner * 3;   // rho, theta, phi per step
+  float *y = sld(D.ycoef) + (long long)t * inner;
+  const double lam = sqrt(sld(D.taus[t]));
+  double rhobar = ha[0], phibar = hb[0];
+  for (int i = 1; i <= k; ++i) {
+    const double beta = hb[i], alpha = ha[i];
+    const double rhohat = hypot(rhobar, lam);
+    phibar = (rhobar / rhohat) * phibar;
+    const double rho = hypot(rhohat, beta);
+    const double c = rhohat / rho, s = beta / rho;
+    scr[3 * (i - 1)] = rho;
+    scr[3 * (i - 1) + 1] = s * alpha;   // theta_{i+1}
+    scr[3 * (i - 1) + 2] = c * phibar;  // phi_i
+    rhobar = -c * alpha;
+    phibar = s * phibar;
+  }
+  double next = 0.0;
+  for (int i = k; i >= 1; --i) {
+    const double rho = scr[3 * (i - 1)], phi = scr[3 * (i - 1) + 2];
+    const double theta = i < k ? scr[3 * (i - 1) + 1] : 0.0;
+    next = (phi - theta * next) / rho;
+    y[i - 1] = (float)next;
+  }
+}
+
+// f(tau_t)[j] = sum_{i < k} y_t[i] v_i[j] for up to 8 dampings per pass (coefficients in LDS,
+// the basis read once per pass); written to the caller's rows only if the request succeeded.
+constexpr int kTauPass = 8;
+__global__ void __launch_bounds__(kBlock) k_tau_combine(InstDesc *const *descs, int t0) {
+  const InstDesc &D = inst(descs);
+  __shared__ float ys[kTauPass * kMaxTauInner];
+  const double *sc = sld(D.sc);
+  if (!sld(D.basis) || sc[SC_STATUS] != 0.0) return;
+  const int inner = sld(D.inner_count);
+  const int k = (int)sc[SC_DONE];
+  const int nt = min(kTauPass, sld(D.n_tau) - t0);
+  if (nt <= 0) return;
+  const float *y = sld(D.ycoef);
+  for (int q = threadIdx.x; q < nt * k; q += kBlock)
+    ys[q] = y[(long long)(t0 + q / k) * inner + q % k];
+  __syncthreads();
+  const long long n = sld(D.n);
+  const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const float *basis = sld(D.basis);
+  float acc[kTauPass];
+#pragma unroll
+  for (int t = 0; t < kTauPass; ++t) acc[t] = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float b = basis[(long long)i * n + j];
+#pragma unroll
+    for (int t = 0; t < kTauPass; ++t)
+      if (t < nt) acc[t] += ys[t * k + i] * b;
+  }
+  float *out = sld(D.f_taus);
+#pragma unroll
+  for (int t = 0; t < kTauPass; ++t)
+    if (t < nt) out[(long long)(t0 + t) * n + j] = acc[t];
+}
+
 // partial of v . p (alpha^2 when the V-cycle is a single exact solve)
 __global__ void __launch_bounds__(kBlock) k_dot_vp(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
@@ -809,6 +912,13 @@ int launch_s4_step(hipStream_t st, InstDesc *const *d, int B, long long m) {
   const unsigned g = blocks_for(m);
   LAUNCH(k_s4_step, g, B, d);
   return (int)g;
+}
+void launch_basis_store(hipStream_t st, InstDesc *const *d, int B, long long n) {
+  LAUNCH(k_basis_store, blocks_for(n), B, d);
+}
+void launch_tau_finish(hipStream_t st, InstDesc *const *d, int B, long long n, int n_tau) {
+  LAUNCH(k_tau_solve, 1, B, d);
+  for (int t0 = 0; t0 < n_tau; t0 += kTauPass) LAUNCH(k_tau_combine, blocks_for(n), B, d, t0);
 }
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n) {
   LAUNCH(k_copy_out, blocks_for(n), B, d);

@@ -92,6 +92,9 @@ void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
 int launch_ring_forward(hipStream_t st, InstDesc *const *d, int B, const InstDesc &H, int src,
                         int epi);
 void launch_ring_adjoint(hipStream_t st, InstDesc *const *d, int B, const InstDesc &H, int epi);
+// several dampings from one Krylov run (kernels.hip)
+void launch_basis_store(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_tau_finish(hipStream_t st, InstDesc *const *d, int B, long long n, int n_tau);
 // S4 residual recurrence (kernels.hip)
 void launch_s4_begin(hipStream_t st, InstDesc *const *d, int B, long long m);
 int launch_s4_step(hipStream_t st, InstDesc *const *d, int B, long long m);

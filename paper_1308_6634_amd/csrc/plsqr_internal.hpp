@@ -17,6 +17,8 @@ constexpr int kMaxTaps = 2 * PLSQR_MAX_RADIUS + 1;
 constexpr int kBlock = 256;          // threads per block for grid kernels (4 wave64)
 constexpr double kTiny = 1e-300;     // exact-termination threshold for alpha, beta
 constexpr int kRingMaxRows = 16384;  // n_src * n_det of a ring operator (u staged in LDS)
+constexpr int kMaxTaus = 64;         // dampings of one multi-tau solve
+constexpr int kMaxTauInner = 1024;   // MLSQR steps of a multi-tau solve (coefficients in LDS)
 
 // FP64 scalar block of one instance (MLSQR state of Algorithm 2 with damping).
 enum ScalarSlot : int {
@@ -86,6 +88,14 @@ struct InstDesc {
   float *ringpart2;                  // their sums over groups of chunks (ring_groups x n_Y)
   int n_src, n_det, ring_chunk, ring_chunks, ring_groups;
   float ring_mu;
+  // several dampings from the last outer step's Krylov run (Section 3.3); n_tau = 0: off
+  int n_tau, outer_count, inner_count;
+  float *basis;                      // inner x n_X: the vectors v_1.. that f combines
+  double *hist;                      // 2 x (inner + 1): alpha_1.., beta_1..
+  double *tau_scr;                   // n_tau x inner x 3: rho, theta, phi / solution y
+  float *ycoef;                      // n_tau x inner: f(tau_t) = sum_i ycoef[t][i] v_i
+  float *f_taus;                     // caller's n_tau x n_X output
+  double taus[kMaxTaus];
   LevelDesc lv[kMaxLevels];
 };
 

@@ -83,6 +83,16 @@ class Engine:
         self._keep[("req", t)] = (g, f)
         return t
 
+    def submit_taus(self, op_id, prob, g, f, taus, f_taus):
+        """One request plus f for every damping in taus (Section 3.3); f_taus: contiguous
+        float32 CUDA tensor of len(taus) x n_X."""
+        for x in (g, f, f_taus):
+            assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+        t = P.plsqr_solve_taus(self.handle, op_id, prob, g.data_ptr(), f.data_ptr(), list(taus),
+                               f_taus.data_ptr())
+        self._keep[("req", t)] = (g, f, f_taus)
+        return t
+
     def submit_batch(self, op_id, probs, gs, fs):
         """Lockstep batch; returns one ticket per instance."""
         for g, f in zip(gs, fs):

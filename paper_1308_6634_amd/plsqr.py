@@ -49,6 +49,7 @@ REG_CODES = {"tikhonov": PLSQR_REG_TIKHONOV, "stv": PLSQR_REG_STV, "pm_log": PLS
 SMOOTHER_CODES = {"jacobi": PLSQR_SMOOTH_JACOBI, "chebyshev": PLSQR_SMOOTH_CHEBYSHEV}
 
 EXPORTED = ("plsqr_create", "plsqr_set_operator", "plsqr_solve", "plsqr_solve_batch", "plsqr_poll",
+            "plsqr_solve_taus",
             "plsqr_wait_all",
             "plsqr_destroy", "plsqr_last_error", "plsqr_auto_levels", "plsqr_workspace_bytes")
 
@@ -107,6 +108,9 @@ def _load():
     lib.plsqr_set_operator.argtypes = [ctypes.c_void_p, P(plsqr_operator), P(ctypes.c_int32)]
     lib.plsqr_solve.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(plsqr_problem), ctypes.c_void_p,
                                 ctypes.c_void_p, P(ctypes.c_uint64)]
+    lib.plsqr_solve_taus.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(plsqr_problem),
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     P(ctypes.c_double), ctypes.c_void_p, P(ctypes.c_uint64)]
     lib.plsqr_solve_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                       P(plsqr_problem), P(ctypes.c_void_p), P(ctypes.c_void_p),
                                       P(ctypes.c_uint64)]
@@ -147,6 +151,15 @@ def plsqr_set_operator(eng, op):
 def plsqr_solve(eng, op_id, prob, g_dev, f_dev):
     ticket = ctypes.c_uint64()
     _check(_lib.plsqr_solve(eng, op_id, ctypes.byref(prob), g_dev, f_dev, ctypes.byref(ticket)), eng)
+    return ticket.value
+
+
+def plsqr_solve_taus(eng, op_id, prob, g_dev, f_dev, taus, f_taus_dev):
+    n = len(taus)
+    arr = (ctypes.c_double * n)(*[float(t) for t in taus])
+    ticket = ctypes.c_uint64()
+    _check(_lib.plsqr_solve_taus(eng, op_id, ctypes.byref(prob), g_dev, f_dev, n, arr, f_taus_dev,
+                                 ctypes.byref(ticket)), eng)
     return ticket.value
 
 
