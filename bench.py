@@ -206,6 +206,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1", "c4", "c5"])
+    ap.add_argument("--latency-solves", type=int, default=20,
+                    help="c1-c3: solves issued one at a time after the timed run for the p50/p99 "
+                         "solve latency (0: skip)")
     ap.add_argument("--requests", type=int, default=2000, help="c5 only: requests in the stream")
     ap.add_argument("--templates", type=int, default=40,
                     help="c5 only: distinct pre-generated reconstructions the stream cycles through")
@@ -369,6 +372,10 @@ def main():
             "traffic": traffic, "bytes_per_launch": nbytes, "kernel_bytes_per_launch": pass_bytes,
             "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)},
     }
+    if args.latency_solves > 0:
+        pb_plain = problem_struct(p, flags=P.PLSQR_FLAG_NO_GRAPHS if args.no_graphs else 0,
+                                  knobs=settings)   # products inside the graphs, no events
+        out["latency_ms"] = solve_latency(args.latency_solves, eng, op, pb_plain, g, f)
     if args.stop:
         out["adaptive"] = adaptive_run(args, eng, op, p, settings, g, f)
     if not args.no_cpu_baseline:
@@ -384,6 +391,23 @@ def main():
         out["parity_sample_rel_l2"] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
     eng.close()
     print(json.dumps(out), flush=True)
+
+
+def solve_latency(k, eng, op, pb, g, f):
+    """p50 / p99 of the host wall time from plsqr_solve to completion over k solves issued one
+    at a time (nothing else queued), after the throughput run."""
+    import numpy as np
+    lat = []
+    for _ in range(k):
+        t = time.perf_counter()
+        st, _ = eng.wait(eng.submit(op, pb, g, f))
+        lat.append((time.perf_counter() - t) * 1e3)
+        assert st == 0
+    print(f"[bench] latency over {k} solves: p50 {np.percentile(lat, 50):.2f} ms, p99 "
+          f"{np.percentile(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "min": float(min(lat)), "max": float(max(lat)), "n": k,
+            "mode": "one solve at a time, submit to completion"}
 
 
 def adaptive_run(args, eng, op, p, settings, g, f):
