@@ -129,7 +129,7 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
     D.ringpart2 = F(Ly.ringpart2);
     D.ring_mu = (float)op.op.mu;
   }
-  const int d = pb.nz > 1 ? 3 : 2;
+  double eps_l = pb.eps;
   for (int l = 0; l < Ly.levels; ++l) {
     LevelDesc &L = D.lv[l];
     L.nx = Ly.lnx[l];
@@ -145,7 +145,10 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
     L.wy = l > 0 ? F(Ly.lvl[l][6]) : nullptr;
     L.wz = (l > 0 && Ly.lvl[l][7]) ? F(Ly.lvl[l][7]) : nullptr;
     L.dinv = F(Ly.lvl[l][8]);
-    L.eps = pb.eps * std::ldexp(1.0, d * l);   // Galerkin: P^T (eps I) P = 2^d eps I
+    // Galerkin: P^T (eps I) P = (children per coarse cell) eps I, 8 while the finer level has
+    // more than one z-plane, else 4
+    if (l > 0) eps_l *= (Ly.lnz[l - 1] > 1) ? 8.0 : 4.0;
+    L.eps = eps_l;
   }
   (void)eng;
 }

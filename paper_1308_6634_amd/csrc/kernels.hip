@@ -82,7 +82,9 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(InstDesc *const *descs, int 
   if (J >= Cl.n) return;
   const Coord cc = coord_of(J, Cl.nx, Cl.ny);
   const int cz = (F.nz > 1) ? 2 : 1;
-  const int naxes = (F.nz > 1) ? 3 : 2;
+  // a coarse level with one z-plane (a 3D grid coarsened to nz = 1) has no z faces and no wz
+  // array; its cells still have 2 z children when the fine level has two planes
+  const int naxes = (Cl.nz > 1) ? 3 : 2;
   for (int a = 0; a < naxes; ++a) {
     float s = 0.f;
     // children of J with local coordinate 1 along a (their +a face leaves J)
