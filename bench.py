@@ -39,13 +39,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 # Sources that determine the device code of the dense forward-product kernel (the dominant
-# kernel of the dense workloads): HBM traffic counted for it stays valid while these are
-# unchanged. (kernels.hpp only declares host launchers and constants the kernel does not use.)
+# kernel of the dense workloads): HBM traffic counted for it stays valid while these and the
+# device compile flags are unchanged. (kernels.hpp only declares host launchers and constants
+# the kernel does not use.)
 DENSE_KERNEL_SOURCES = ("dense.hip", "device_common.hpp", "plsqr_internal.hpp")
 
 
 def kernel_source_hash(files=DENSE_KERNEL_SOURCES):
-    h = hashlib.sha256()
+    """Hash of the sources and of the device compile flags that determine the kernel's code."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_plsqr_build_flags", os.path.join(ROOT, "paper_1308_6634_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    h = hashlib.sha256(" ".join(mod.DEVICE_FLAGS).encode())
     for name in files:
         with open(os.path.join(ROOT, "paper_1308_6634_amd", "csrc", name), "rb") as f:
             h.update(f.read())
@@ -241,6 +248,9 @@ def main():
                     help="host only: turn four rocprofv3 --pmc CSV output folders (FETCH_SIZE and "
                          "WRITE_SIZE of a bench run, then of --copy-calibration) into the HBM "
                          "traffic record of --traffic-kernel read by later bench runs")
+    ap.add_argument("--stream", action="store_true",
+                    help="practical HBM ceiling: a 2 GiB device copy and a 4 GiB read-only sum "
+                         "(library kernels of PyTorch), timed with events")
     ap.add_argument("--traffic-kernel", default=None,
                     help="exact kernel name for --write-traffic, e.g. 'k_gemv_rows<2>'")
     args = ap.parse_args()
@@ -255,6 +265,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "launches": 3}))
         return
+    if args.stream:
+        return stream_ceiling()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(instances shard across GPUs without communication, see the "
@@ -391,6 +403,32 @@ def main():
         out["parity_sample_rel_l2"] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
     eng.close()
     print(json.dumps(out), flush=True)
+
+
+def stream_ceiling(reps=10):
+    """STREAM-like practical ceiling of HBM bandwidth on this GPU: a device-to-device copy of
+    2 GiB (reads and writes 2 GiB each) and a sum over 4 GiB (reads 4 GiB), both far larger than
+    the last-level cache, timed with events on the current stream."""
+    import torch
+    n = 1 << 29                                   # 2 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    big = torch.ones(2 * n, dtype=torch.float32, device="cuda")
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: dst.copy_(src), 2 * 4 * n),
+                             ("read_sum", lambda: big.sum(), 4 * 2 * n)):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name] = {"bytes": nbytes, "ms": ms, "GB_per_s": nbytes / ms / 1e6,
+                     "frac_of_8TBps": nbytes / ms / 1e6 / HBM_PEAK_GBS}
+    print(json.dumps({"stream_ceiling": out, "reps": reps}), flush=True)
 
 
 def solve_latency(k, eng, op, pb, g, f):

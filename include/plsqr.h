@@ -106,7 +106,10 @@ typedef struct plsqr_engine plsqr_engine;   /* opaque; owns all internal device 
  *  PLSQR_OP_DENSE: A_dev is a row-major n_y x (nx*ny*nz) float32 DEVICE matrix
  *                  (BORROWED). A_hi_dev / A_lo_dev are optional bf16 (uint16 bit
  *                  pattern) copies with the same layout: A_hi = bf16(A),
- *                  A_lo = bf16(A - A_hi); they are used by PLSQR_PREC_BF16_REFINED.
+ *                  A_lo = bf16(A - A_hi). The batched BF16 products (PLSQR_PREC_BF16,
+ *                  PLSQR_PREC_BF16_REFINED) take their operands from them when given
+ *                  (else from A), copied once into library-owned tiled buffers when the
+ *                  first such batch starts.
  *  PLSQR_OP_RING : the dense source-detector sensitivity of PLSQR_OP_DENSE's workloads,
  *                  never stored: entry (s * n_det + d, j) is
  *                      exp(-mu (r_sj + r_dj)) / (r_sj r_dj + 1),

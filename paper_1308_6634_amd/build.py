@@ -24,9 +24,13 @@ HOST_SOURCES = ["driver.cpp", "api.cpp"]
 HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp", "device_common.hpp"]
 
 # Packed-FP32 instructions are disabled for every device compile (the compiler would
-# otherwise form v_pk_* FP32 ops from ordinary float code).
+# otherwise form v_pk_* FP32 ops from ordinary float code). Kernel arguments are preloaded
+# into SGPRs at wave launch (gfx950), so a kernel's first descriptor load does not wait for a
+# load of its own arguments; the code object keeps a prologue that loads them from memory when
+# the firmware does not preload.
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
-                "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result"]
+                "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics", "-mllvm",
+                "-amdgpu-kernarg-preload-count=16", "-Wall", "-Wno-unused-result"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-Wall", "-Wno-unused-value"]
 
 

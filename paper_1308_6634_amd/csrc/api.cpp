@@ -193,7 +193,10 @@ size_t plan_group(Group &G, const Operator &op, const Layout &Ly) {
   return (off + 255) / 256 * 256;
 }
 
-// Build (once) the BF16 copies of a dense operator: A_hi, A_lo and their transposes.
+// Build (once) the tiled BF16 left operands of the batched products: A_hi, A_lo (forward,
+// L = A) and At_hi, At_lo (adjoint, L = A^T), all owned by the library. The hi parts come from
+// the caller's A_hi_dev when given, else hi = bf16(A); the lo parts from A_lo_dev when given,
+// else lo = bf16(A - bf16(A)).
 int ensure_bf16(plsqr_engine *eng, Operator &op, bool need_lo) {
   const long long m = op.op.n_y, n = (long long)op.op.nx * op.op.ny * op.op.nz;
   const size_t bytes = (size_t)m * n * 2;
@@ -205,34 +208,24 @@ int ensure_bf16(plsqr_engine *eng, Operator &op, bool need_lo) {
     }
     return PLSQR_OK;
   };
-  const bool have_hi = op.A_hi != nullptr, have_lo = op.A_lo != nullptr;
-  if (!have_hi && op.op.A_hi_dev) op.A_hi = const_cast<uint16_t *>(op.op.A_hi_dev);
-  if (!have_lo && op.op.A_lo_dev) op.A_lo = const_cast<uint16_t *>(op.op.A_lo_dev);
   int rc;
   if (!op.A_hi) {
-    if ((rc = alloc(&op.A_hi)) != PLSQR_OK) return rc;
+    if ((rc = alloc(&op.A_hi)) != PLSQR_OK || (rc = alloc(&op.At_hi)) != PLSQR_OK) return rc;
     op.own_A_hi = true;
-    if (!op.A_lo && (rc = alloc(&op.A_lo)) != PLSQR_OK) return rc;
-    op.own_A_lo = true;
-    launch_split_matrix(eng->stream, op.op.A_dev, op.A_hi, op.A_lo, m * n);
+    for (int tr = 0; tr < 2; ++tr) {
+      void *dst = tr ? op.At_hi : op.A_hi;
+      if (op.op.A_hi_dev) launch_retile16(eng->stream, op.op.A_hi_dev, m, n, tr, dst);
+      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, dst, nullptr);
+    }
   }
   if (need_lo && !op.A_lo) {
-    if ((rc = alloc(&op.A_lo)) != PLSQR_OK) return rc;
+    if ((rc = alloc(&op.A_lo)) != PLSQR_OK || (rc = alloc(&op.At_lo)) != PLSQR_OK) return rc;
     op.own_A_lo = true;
-    // recompute the pair so that lo matches hi exactly
-    void *tmp = nullptr;
-    if ((rc = alloc(&tmp)) != PLSQR_OK) return rc;
-    launch_split_matrix(eng->stream, op.op.A_dev, tmp, op.A_lo, m * n);
-    HIP_TRY(hipStreamSynchronize(eng->stream));
-    HIP_TRY(hipFree(tmp));
-  }
-  if (!op.At_hi) {
-    if ((rc = alloc(&op.At_hi)) != PLSQR_OK) return rc;
-    launch_transpose16(eng->stream, op.A_hi, op.At_hi, m, n);
-  }
-  if (need_lo && !op.At_lo) {
-    if ((rc = alloc(&op.At_lo)) != PLSQR_OK) return rc;
-    launch_transpose16(eng->stream, op.A_lo, op.At_lo, m, n);
+    for (int tr = 0; tr < 2; ++tr) {
+      void *dst = tr ? op.At_lo : op.A_lo;
+      if (op.op.A_lo_dev) launch_retile16(eng->stream, op.op.A_lo_dev, m, n, tr, dst);
+      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, nullptr, dst);
+    }
   }
   HIP_TRY(hipGetLastError());
   return PLSQR_OK;

@@ -9,7 +9,13 @@
 // Tiling (gfx950, v_mfma_f32_32x32x16_bf16, wave64): a block of 8 waves owns 256 rows of
 // the left operand; each wave owns 32 rows and all Bpad (= 32 * NT) columns. Per step of
 // 128 along K, lane (i, h) (i = lane % 32, h = lane / 32) loads 64 contiguous K values of
-// its row (8 x 16-byte loads, prefetched one step ahead) and feeds them to 8 MFMAs; the
+// its row (8 x 16-byte loads, prefetched one step ahead) and feeds them to 8 MFMAs. The left
+// operand is stored tiled (the library builds it once per operator, see k_split_tiled): each
+// 32-row x 128-K tile is 8 KB contiguous with lane (i, h)'s 16-byte vector for load s at
+// vector index s * 64 + lane, so each load instruction of a wave reads 1 KB contiguous and a
+// wave streams its row tile's K range front to back (a row-major operand would make every
+// load instruction gather 16 bytes from 32 rows 2 K apart, re-requesting each cache line 8
+// times and scattering DRAM accesses over all rows of the tile); the
 // right-operand block of the step (hi and lo, Bpad x 128) is staged once per block in
 // LDS (double-buffered, rows padded against bank conflicts) and lane (j, h) reads the
 // same 64 K indices of column j, so every MFMA pairs identical K indices (the K order
@@ -27,6 +33,7 @@ constexpr int kGemmWaves = 8;                 // waves per block
 constexpr int kGemmRows = 32 * kGemmWaves;    // rows of the left operand per block
 constexpr int kKStep = 128;                   // K per step
 constexpr int kLdsRow = kKStep + 8;           // bf16 per LDS column row (padded: no bank conflicts)
+constexpr int kTileElems = 32 * kKStep;       // elements of one 32-row x 128-K left-operand tile
 
 // Right-operand block of one K step in LDS: [hi | lo][Bpad columns][kLdsRow]. Each of
 // the 512 threads moves NT * 2 chunks of 16 bytes (held in named registers, not an array,
@@ -86,17 +93,23 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
-  const __bf16 *pa = Lhi + (row0 + li) * K + h * 64;
-  const __bf16 *pal = LO_L ? Llo + (row0 + li) * K + h * 64 : nullptr;
+  // this wave's row tile in the tiled operand; step k0 is tile k0 / kKStep of it, load s of
+  // lane `lane` is vector s * 64 + lane of that tile
+  const long long tile0 = (row0 / 32) * (K / kKStep);
+  const __bf16 *pa = Lhi + tile0 * kTileElems + lane * 8;
+  const __bf16 *pal = LO_L ? Llo + tile0 * kTileElems + lane * 8 : nullptr;
+  auto at_step = [](const __bf16 *p, long long k0, int s) {
+    return *reinterpret_cast<const bf16x8 *>(p + (k0 / kKStep) * kTileElems + s * 512);
+  };
   bf16x8 a[8], al[LO_L ? 8 : 1];
   XChunks xr;
   // prologue: step kbeg
   if (kbeg < kend) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = *reinterpret_cast<const bf16x8 *>(pa + kbeg + s * 8);
+    for (int s = 0; s < 8; ++s) a[s] = at_step(pa, kbeg, s);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) al[s] = *reinterpret_cast<const bf16x8 *>(pal + kbeg + s * 8);
+      for (int s = 0; s < 8; ++s) al[s] = at_step(pal, kbeg, s);
     }
     xr = stage_right<NT>(Rhi, Rlo, K, kbeg);
     store_right<NT>(lds[0], xr);
@@ -110,10 +123,10 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
     bf16x8 an[8], aln[LO_L ? 8 : 1];
     if (more) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) an[s] = *reinterpret_cast<const bf16x8 *>(pa + kn + s * 8);
+      for (int s = 0; s < 8; ++s) an[s] = at_step(pa, kn, s);
       if constexpr (LO_L) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) aln[s] = *reinterpret_cast<const bf16x8 *>(pal + kn + s * 8);
+        for (int s = 0; s < 8; ++s) aln[s] = at_step(pal, kn, s);
       }
       xr = stage_right<NT>(Rhi, Rlo, K, kn);
     }
@@ -199,32 +212,64 @@ __global__ void __launch_bounds__(kBlock) k_pack_split(InstDesc *const *descs, i
   Rlo[(long long)b * len + k] = lo;
 }
 
-// A = hi + lo split of a float32 matrix (elementwise).
-__global__ void __launch_bounds__(kBlock) k_split_matrix(const float *A, __bf16 *hi, __bf16 *lo,
-                                                        long long count) {
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count;
-       i += (long long)gridDim.x * kBlock) {
-    const float a = A[i];
-    const __bf16 h = (__bf16)a;
-    hi[i] = h;
-    if (lo) lo[i] = (__bf16)(a - (float)h);
+// Tiled left operands (layout described at the top of this file). Vector v (16 bytes, 8
+// elements) of the tiled M x K operand L is vector s * 64 + lane of tile (rt, kt), with
+// v = ((rt * K/128 + kt) * 8 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
+// row = 32 rt + lane % 32 and k0 = 128 kt + 64 (lane / 32) + 8 s. L is A (n_y x n_x) for the
+// forward product (transposed = 0) or A^T for the adjoint (transposed = 1).
+__device__ __forceinline__ void tiled_coords(long long v, long long K, int transposed,
+                                             long long n_x, long long &row, long long &k0,
+                                             long long &stride) {
+  const int lane = (int)(v % 64);
+  const long long q = v / 64;
+  const int s = (int)(q % 8);
+  const long long tile = q / 8;
+  const long long nkt = K / kKStep;
+  row = (tile / nkt) * 32 + (lane & 31);
+  k0 = (tile % nkt) * kKStep + (lane >> 5) * 64 + s * 8;
+  stride = transposed ? n_x : 1;     // distance between L[row][k] and L[row][k + 1] in A
+}
+
+// hi = bf16(L), lo = bf16(L - hi) in the tiled layout, from the float32 row-major A
+// (either output may be null).
+__global__ void __launch_bounds__(kBlock) k_split_tiled(const float *A, long long n_y,
+                                                       long long n_x, int transposed, __bf16 *hi,
+                                                       __bf16 *lo) {
+  const long long M = transposed ? n_x : n_y, K = transposed ? n_y : n_x;
+  const long long nvec = M * K / 8;
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nvec;
+       v += (long long)gridDim.x * kBlock) {
+    long long row, k0, stride;
+    tiled_coords(v, K, transposed, n_x, row, k0, stride);
+    const float *src = transposed ? A + k0 * n_x + row : A + row * n_x + k0;
+    bf16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float a = src[e * stride];
+      h[e] = (__bf16)a;
+      l[e] = (__bf16)(a - (float)h[e]);
+    }
+    if (hi) *reinterpret_cast<bf16x8 *>(hi + v * 8) = h;
+    if (lo) *reinterpret_cast<bf16x8 *>(lo + v * 8) = l;
   }
 }
 
-// out (C x R) = in (R x C)^T for 16-bit elements, 64 x 64 tiles through LDS.
-__global__ void __launch_bounds__(kBlock) k_transpose16(const uint16_t *in, uint16_t *out,
-                                                       long long R, long long C) {
-  __shared__ uint16_t tile[64][65];
-  const long long c0 = (long long)blockIdx.x * 64, r0 = (long long)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
-  for (int i = ty; i < 64; i += 4) {
-    const long long r = r0 + i, c = c0 + tx;
-    tile[i][tx] = (r < R && c < C) ? in[r * C + c] : (uint16_t)0;
-  }
-  __syncthreads();
-  for (int i = ty; i < 64; i += 4) {
-    const long long c = c0 + i, r = r0 + tx;
-    if (c < C && r < R) out[c * R + r] = tile[tx][i];
+// The tiled layout of a 16-bit row-major copy of A (n_y x n_x), as L = A or L = A^T.
+__global__ void __launch_bounds__(kBlock) k_retile16(const uint16_t *src16, long long n_y,
+                                                    long long n_x, int transposed, uint16_t *dst) {
+  const long long M = transposed ? n_x : n_y, K = transposed ? n_y : n_x;
+  const long long nvec = M * K / 8;
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nvec;
+       v += (long long)gridDim.x * kBlock) {
+    long long row, k0, stride;
+    tiled_coords(v, K, transposed, n_x, row, k0, stride);
+    const uint16_t *src = transposed ? src16 + k0 * n_x + row : src16 + row * n_x + k0;
+    uint16_t w[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = src[e * stride];
+    *reinterpret_cast<uint4 *>(dst + v * 8) =
+        make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
+                   w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
   }
 }
 
@@ -279,14 +324,16 @@ void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmAr
                       1, g.Bpad, nullptr, d, B, epi);
 }
 
-void launch_split_matrix(hipStream_t st, const float *A, void *hi, void *lo, long long count) {
-  hipLaunchKernelGGL(k_split_matrix, dim3(8192), dim3(kBlock), 0, st, A, (__bf16 *)hi, (__bf16 *)lo,
-                     count);
+void launch_split_tiled(hipStream_t st, const float *A, long long n_y, long long n_x,
+                        int transposed, void *hi, void *lo) {
+  hipLaunchKernelGGL(k_split_tiled, dim3(8192), dim3(kBlock), 0, st, A, n_y, n_x, transposed,
+                     (__bf16 *)hi, (__bf16 *)lo);
 }
 
-void launch_transpose16(hipStream_t st, const void *in, void *out, long long R, long long C) {
-  hipLaunchKernelGGL(k_transpose16, dim3((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64)),
-                     dim3(kBlock), 0, st, (const uint16_t *)in, (uint16_t *)out, R, C);
+void launch_retile16(hipStream_t st, const void *src, long long n_y, long long n_x,
+                     int transposed, void *dst) {
+  hipLaunchKernelGGL(k_retile16, dim3(8192), dim3(kBlock), 0, st, (const uint16_t *)src, n_y, n_x,
+                     transposed, (uint16_t *)dst);
 }
 
 }  // namespace plsqr

@@ -349,6 +349,24 @@ def test_batch_bf16_alone_equals_in_batch(engine):
     assert _rel(many[32], many[0]) <= 1e-6
 
 
+def test_batch_bf16_caller_copies_equal_library_split(engine):
+    """BF16 copies of A supplied by the caller (row-major hi and lo, split by torch with the
+    same round-to-nearest-even rule) give bitwise the same batch as the library's own split of
+    A: both are copied into the same tiled operands of the MFMA products."""
+    import torch
+    A = gen.small_dense_case(85, 16).A
+    probs = [gen.small_dense_case(85 + i, 16, outer=2, inner=5, levels=3, A=A) for i in range(3)]
+    At = torch.from_numpy(A).cuda()
+    hi = At.to(torch.bfloat16)
+    lo = (At - hi.float()).to(torch.bfloat16)
+    op_own = engine.dense_operator(probs[0].dims, At)
+    op_given = engine.dense_operator(probs[0].dims, At, A_hi=hi, A_lo=lo)
+    own = _run_batch(engine, probs, precision=1, op_id=op_own)
+    given = _run_batch(engine, probs, precision=1, op_id=op_given)
+    for a, b in zip(own, given):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_full_size_c4_batch_first_iterations(engine):
     """The 64-instance batch at full size (8192 x 262144 shared A, MFMA products with
     refinement), first outer step with two inner steps; instances 0 and 63 against the
