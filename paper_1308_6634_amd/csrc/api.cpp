@@ -208,25 +208,29 @@ int ensure_bf16(plsqr_engine *eng, Operator &op, bool need_lo) {
     }
     return PLSQR_OK;
   };
-  int rc;
-  if (!op.A_hi) {
-    if ((rc = alloc(&op.A_hi)) != PLSQR_OK || (rc = alloc(&op.At_hi)) != PLSQR_OK) return rc;
-    op.own_A_hi = true;
-    for (int tr = 0; tr < 2; ++tr) {
-      void *dst = tr ? op.At_hi : op.A_hi;
-      if (op.op.A_hi_dev) launch_retile16(eng->stream, op.op.A_hi_dev, m, n, tr, dst);
-      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, dst, nullptr);
+  // both tiled copies of a part or neither: a failed allocation leaves none behind, so a later
+  // call builds the pair again
+  auto build = [&](void *&fwd, void *&adj, const uint16_t *given, bool is_lo) -> int {
+    if (fwd && adj) return PLSQR_OK;
+    int rc = alloc(&fwd);
+    if (rc == PLSQR_OK) rc = alloc(&adj);
+    if (rc != PLSQR_OK) {
+      if (fwd) hipFree(fwd);
+      if (adj) hipFree(adj);
+      fwd = adj = nullptr;
+      return rc;
     }
-  }
-  if (need_lo && !op.A_lo) {
-    if ((rc = alloc(&op.A_lo)) != PLSQR_OK || (rc = alloc(&op.At_lo)) != PLSQR_OK) return rc;
-    op.own_A_lo = true;
     for (int tr = 0; tr < 2; ++tr) {
-      void *dst = tr ? op.At_lo : op.A_lo;
-      if (op.op.A_lo_dev) launch_retile16(eng->stream, op.op.A_lo_dev, m, n, tr, dst);
-      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, nullptr, dst);
+      void *dst = tr ? adj : fwd;
+      if (given) launch_retile16(eng->stream, given, m, n, tr, dst);
+      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, is_lo ? nullptr : dst,
+                              is_lo ? dst : nullptr);
     }
-  }
+    return PLSQR_OK;
+  };
+  int rc = build(op.A_hi, op.At_hi, op.op.A_hi_dev, false);
+  if (rc != PLSQR_OK) return rc;
+  if (need_lo && (rc = build(op.A_lo, op.At_lo, op.op.A_lo_dev, true)) != PLSQR_OK) return rc;
   HIP_TRY(hipGetLastError());
   return PLSQR_OK;
 }
@@ -1011,8 +1015,8 @@ int plsqr_destroy(plsqr_engine *eng) {
     eng->groups.clear();
     eng->reqs.clear();
     for (auto &op : eng->ops) {
-      if (op.own_A_hi && op.A_hi) hipFree(op.A_hi);
-      if (op.own_A_lo && op.A_lo) hipFree(op.A_lo);
+      if (op.A_hi) hipFree(op.A_hi);
+      if (op.A_lo) hipFree(op.A_lo);
       if (op.At_hi) hipFree(op.At_hi);
       if (op.At_lo) hipFree(op.At_lo);
       if (op.ring) hipFree(op.ring);

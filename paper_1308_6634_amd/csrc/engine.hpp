@@ -20,9 +20,8 @@ namespace plsqr {
 struct Operator {
   plsqr_operator op{};
   std::vector<float> taps;
-  // BF16 copies for batched MFMA products (built on first use; owned unless borrowed)
+  // tiled BF16 left operands of the batched MFMA products (built on first use, owned)
   void *A_hi = nullptr, *A_lo = nullptr, *At_hi = nullptr, *At_lo = nullptr;
-  bool own_A_hi = false, own_A_lo = false;
   // ring sensitivity: source then detector positions (x, y, z floats) on the device
   float *ring = nullptr;
 };
