@@ -177,8 +177,10 @@ size_t plan_group(Group &G, const Operator &op, const Layout &Ly) {
     g.Bpad = B <= 32 ? 32 : 64;
     const long long m = Ly.m, n = Ly.n;
     const long long rowtiles = m / 256;      // forward GEMM blocks own 256 rows of A
-    long long ks = std::max(1LL, std::min(n / 128, (1024 + rowtiles - 1) / rowtiles));
-    long long kchunk = ((n + ks - 1) / ks + 127) / 128 * 128;
+    // K chunks are multiples of 256 (four 64-K steps of the GEMM pipeline); n % 256 == 0, so
+    // the last chunk is one too
+    long long ks = std::max(1LL, std::min(n / 256, (1024 + rowtiles - 1) / rowtiles));
+    long long kchunk = ((n + ks - 1) / ks + 255) / 256 * 256;
     ks = (n + kchunk - 1) / kchunk;
     g.ks = (int)ks;
     g.kchunk = kchunk;

@@ -8,18 +8,18 @@
 //
 // Tiling (gfx950, v_mfma_f32_32x32x16_bf16, wave64): a block of 8 waves owns 256 rows of
 // the left operand; each wave owns 32 rows and all Bpad (= 32 * NT) columns. Per step of
-// 128 along K, lane (i, h) (i = lane % 32, h = lane / 32) loads 64 contiguous K values of
-// its row (8 x 16-byte loads, prefetched one step ahead) and feeds them to 8 MFMAs. The left
+// 64 along K, lane (i, h) (i = lane % 32, h = lane / 32) loads 32 contiguous K values of
+// its row (4 x 16-byte loads, issued three steps ahead) and feeds them to 4 MFMAs. The left
 // operand is stored tiled (the library builds it once per operator, see k_split_tiled): each
-// 32-row x 128-K tile is 8 KB contiguous with lane (i, h)'s 16-byte vector for load s at
+// 32-row x 64-K tile is 4 KB contiguous with lane (i, h)'s 16-byte vector for load s at
 // vector index s * 64 + lane, so each load instruction of a wave reads 1 KB contiguous and a
 // wave streams its row tile's K range front to back (a row-major operand would make every
 // load instruction gather 16 bytes from 32 rows 2 K apart, re-requesting each cache line 8
 // times and scattering DRAM accesses over all rows of the tile); the
-// right-operand block of the step (hi and lo, Bpad x 128) is staged once per block in
+// right-operand block of the step (hi and lo, Bpad x 64) is staged once per block in
 // LDS (double-buffered, rows padded against bank conflicts) and lane (j, h) reads the
-// same 64 K indices of column j, so every MFMA pairs identical K indices (the K order
-// inside one 128-step is a permutation, which the sum does not see).
+// same 32 K indices of column j, so every MFMA pairs identical K indices (the K order
+// inside one 64-step is a permutation, which the sum does not see).
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -31,23 +31,25 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kGemmWaves = 8;                 // waves per block
 constexpr int kGemmRows = 32 * kGemmWaves;    // rows of the left operand per block
-constexpr int kKStep = 128;                   // K per step
+constexpr int kKStep = 64;                    // K per step
+constexpr int kSlots = kKStep / 16;           // MFMAs along K per step (8 K per lane half)
 constexpr int kLdsRow = kKStep + 8;           // bf16 per LDS column row (padded: no bank conflicts)
-constexpr int kTileElems = 32 * kKStep;       // elements of one 32-row x 128-K left-operand tile
+constexpr int kTileElems = 32 * kKStep;       // elements of one 32-row x 64-K left-operand tile
+constexpr int kChunks = kKStep / 8;           // 16-byte chunks of one column per step
 
 // Right-operand block of one K step in LDS: [hi | lo][Bpad columns][kLdsRow]. Each of
-// the 512 threads moves NT * 2 chunks of 16 bytes (held in named registers, not an array,
-// so that they never go to scratch).
+// the 512 threads moves NT * kKStep / 64 chunks of 16 bytes (held in named registers, not an
+// array, so that they never go to scratch).
 struct XChunks {
-  uint4 v[4];
+  uint4 v[2];
 };
 
 __device__ __forceinline__ void chunk_coords(int q, int NT, int &half, int &col, int &chunk) {
   const int idx = q * 512 + (int)threadIdx.x;   // 16-byte chunk index
-  half = idx / (NT * 32 * 16);                   // 0: hi, 1: lo
-  const int rem = idx % (NT * 32 * 16);
-  col = rem / 16;
-  chunk = rem % 16;
+  half = idx / (NT * 32 * kChunks);              // 0: hi, 1: lo
+  const int rem = idx % (NT * 32 * kChunks);
+  col = rem / kChunks;
+  chunk = rem % kChunks;
 }
 
 template <int NT>
@@ -56,7 +58,7 @@ __device__ __forceinline__ XChunks stage_right(const __bf16 *__restrict__ Rhi,
                                                long long k0) {
   XChunks x;
 #pragma unroll
-  for (int q = 0; q < NT * 2; ++q) {
+  for (int q = 0; q < NT * kKStep / 64; ++q) {
     int half, col, chunk;
     chunk_coords(q, NT, half, col, chunk);
     const __bf16 *src = (half ? Rlo : Rhi) + (long long)col * K + k0 + chunk * 8;
@@ -68,7 +70,7 @@ __device__ __forceinline__ XChunks stage_right(const __bf16 *__restrict__ Rhi,
 template <int NT>
 __device__ __forceinline__ void store_right(__bf16 *lds, const XChunks &x) {
 #pragma unroll
-  for (int q = 0; q < NT * 2; ++q) {
+  for (int q = 0; q < NT * kKStep / 64; ++q) {
     int half, col, chunk;
     chunk_coords(q, NT, half, col, chunk);
     *reinterpret_cast<uint4 *>(lds + ((half * NT * 32 + col) * kLdsRow + chunk * 8)) = x.v[q];
@@ -93,69 +95,89 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
-  // this wave's row tile in the tiled operand; step k0 is tile k0 / kKStep of it, load s of
-  // lane `lane` is vector s * 64 + lane of that tile
-  const long long tile0 = (row0 / 32) * (K / kKStep);
+  // this wave's row tile in the tiled operand; step st is tile (kbeg / kKStep + st) of it,
+  // load s of lane `lane` is vector s * 64 + lane of that tile
+  const long long tile0 = (row0 / 32) * (K / kKStep) + kbeg / kKStep;
   const __bf16 *pa = Lhi + tile0 * kTileElems + lane * 8;
   const __bf16 *pal = LO_L ? Llo + tile0 * kTileElems + lane * 8 : nullptr;
-  auto at_step = [](const __bf16 *p, long long k0, int s) {
-    return *reinterpret_cast<const bf16x8 *>(p + (k0 / kKStep) * kTileElems + s * 512);
+  const long long nsteps = (kend - kbeg) / kKStep;   // kchunk and K are multiples of kKStep
+  // Pipeline: the left operand of step st + 3 and the right operand of step st + 2 are
+  // issued while step st computes, in that order of issue per step (right, then left), so
+  // that every wait retires only loads that are due: the right operand of step st + 1 is
+  // awaited at the end of step st (it was issued before the left operand of step st + 2),
+  // the left operand of step st + 1 at the start of step st + 1. Left operands rotate through
+  // four register sets, right operands through two, the LDS copy of the right operand through
+  // two buffers.
+  struct AStep {
+    bf16x8 hi[kSlots], lo[LO_L ? kSlots : 1];
   };
-  bf16x8 a[8], al[LO_L ? 8 : 1];
-  XChunks xr;
-  // prologue: step kbeg
-  if (kbeg < kend) {
+  // loads past the last step re-read the last step (clamped index): the loop body has no
+  // branches, so the compiler's wait counts follow the order of issue exactly
+  auto load_a = [&](AStep &a, long long st) {
+    st = min(st, nsteps - 1);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = at_step(pa, kbeg, s);
+    for (int q = 0; q < kSlots; ++q)
+      a.hi[q] = *reinterpret_cast<const bf16x8 *>(pa + st * kTileElems + q * 512);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) al[s] = at_step(pal, kbeg, s);
+      for (int q = 0; q < kSlots; ++q)
+        a.lo[q] = *reinterpret_cast<const bf16x8 *>(pal + st * kTileElems + q * 512);
     }
-    xr = stage_right<NT>(Rhi, Rlo, K, kbeg);
-    store_right<NT>(lds[0], xr);
+  };
+  auto load_x = [&](XChunks &x, long long st) {
+    x = stage_right<NT>(Rhi, Rlo, K, kbeg + min(st, nsteps - 1) * kKStep);
+  };
+  AStep a0, a1, a2, a3;
+  XChunks x0, x1;
+  // (scheduling barriers keep the loads in this order of issue: the waits below rely on it;
+  // the host plans every block's K range as a positive multiple of 4 steps)
+  {
+    XChunks xf;
+    load_x(xf, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_x(x1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(a0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(a1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(a2, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    store_right<NT>(lds[0], xf);
   }
   __syncthreads();
-  int buf = 0;
-  for (long long k0 = kbeg; k0 < kend; k0 += kKStep) {
-    const long long kn = k0 + kKStep;
-    const bool more = kn < kend;
-    // prefetch the next step's operands while this step computes
-    bf16x8 an[8], aln[LO_L ? 8 : 1];
-    if (more) {
+  // step st computes with left set `cur` and LDS buffer st % 2; it issues the right operand of
+  // step st + 2 into `xn` and the left operand of step st + 3 into `an` (both free now), then
+  // stores the right operand of step st + 1 (held in `xs`) into LDS buffer (st + 1) % 2.
+  auto step = [&](const AStep &cur, AStep &an, XChunks &xn, const XChunks &xs, long long st) {
+    load_x(xn, st + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(an, st + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    const __bf16 *L0 = lds[st & 1];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) an[s] = at_step(pa, kn, s);
-      if constexpr (LO_L) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) aln[s] = at_step(pal, kn, s);
-      }
-      xr = stage_right<NT>(Rhi, Rlo, K, kn);
-    }
-    const __bf16 *L0 = lds[buf];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int q = 0; q < kSlots; ++q) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int col = t * 32 + li;
-        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(L0 + col * kLdsRow + h * 64 + s * 8);
-        const bf16x8 bl =
-            *reinterpret_cast<const bf16x8 *>(L0 + (NT * 32 + col) * kLdsRow + h * 64 + s * 8);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], b, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], bl, acc[t], 0, 0, 0);
+        const int ko = h * (kKStep / 2) + q * 8;
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(L0 + col * kLdsRow + ko);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(L0 + (NT * 32 + col) * kLdsRow + ko);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.hi[q], b, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.hi[q], bl, acc[t], 0, 0, 0);
         if constexpr (LO_L)
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], b, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.lo[q], b, acc[t], 0, 0, 0);
       }
     }
-    if (more) {
-      store_right<NT>(lds[buf ^ 1], xr);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) a[s] = an[s];
-      if constexpr (LO_L) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) al[s] = aln[s];
-      }
-    }
+    store_right<NT>(lds[(st + 1) & 1], xs);   // past the last step: unused, harmless
     __syncthreads();
-    buf ^= 1;
+  };
+  // four steps per trip: the register sets rotate with period 4 (left) and 2 (right)
+  for (long long st = 0; st < nsteps; st += 4) {
+    step(a0, a3, x0, x1, st);
+    step(a1, a0, x1, x0, st + 1);
+    step(a2, a1, x0, x1, st + 2);
+    step(a3, a2, x1, x0, st + 3);
   }
   // accumulator element r of lane (li, h) is (row 8*(r/4) + 4*h + r%4, column li) of the tile
 #pragma unroll
@@ -214,19 +236,19 @@ __global__ void __launch_bounds__(kBlock) k_pack_split(InstDesc *const *descs, i
 
 // Tiled left operands (layout described at the top of this file). Vector v (16 bytes, 8
 // elements) of the tiled M x K operand L is vector s * 64 + lane of tile (rt, kt), with
-// v = ((rt * K/128 + kt) * 8 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
-// row = 32 rt + lane % 32 and k0 = 128 kt + 64 (lane / 32) + 8 s. L is A (n_y x n_x) for the
+// v = ((rt * K/64 + kt) * 4 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
+// row = 32 rt + lane % 32 and k0 = 64 kt + 32 (lane / 32) + 8 s. L is A (n_y x n_x) for the
 // forward product (transposed = 0) or A^T for the adjoint (transposed = 1).
 __device__ __forceinline__ void tiled_coords(long long v, long long K, int transposed,
                                              long long n_x, long long &row, long long &k0,
                                              long long &stride) {
   const int lane = (int)(v % 64);
   const long long q = v / 64;
-  const int s = (int)(q % 8);
-  const long long tile = q / 8;
+  const int s = (int)(q % kSlots);
+  const long long tile = q / kSlots;
   const long long nkt = K / kKStep;
   row = (tile / nkt) * 32 + (lane & 31);
-  k0 = (tile % nkt) * kKStep + (lane >> 5) * 64 + s * 8;
+  k0 = (tile % nkt) * kKStep + (lane >> 5) * (kKStep / 2) + s * 8;
   stride = transposed ? n_x : 1;     // distance between L[row][k] and L[row][k + 1] in A
 }
 
