@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Matrix-free ring product: 6 flops per entry (r_s r_d, + 1, 1/t, a c, * v, + acc). The issue
 # model: 256 CUs x 4 SIMDs at 2.4 GHz; the 157.3 TFLOP/s FP32 vector peak counts packed (two per
-# lane) FMAs on 16 lanes per SIMD per clock, so unpacked FP32 operations (this build compiles
-# without packed FP32) run 16 lanes per SIMD per clock and the reciprocal, a transcendental, at
+# lane) FMAs on 16 lanes per SIMD per clock, so unpacked FP32 operations (the library is
+# compiled without packed FP32) run 16 lanes per SIMD per clock and the reciprocal, a transcendental, at
 # a quarter of that. An entry takes 3 unpacked operations and one reciprocal, 3/16 + 1/4
 # SIMD-clocks per lane, so at most 256 * 4 * 2.4e9 / (3/16 + 1/4) = 5.6e12 entries/s.
 RING_FLOPS_PER_ENTRY = 6
@@ -268,7 +268,7 @@ def main():
     if args.stream:
         return stream_ceiling()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
                                    "(instances shard across GPUs without communication, see the "
                                    "design notes)"}), flush=True)
         sys.exit(2)
