@@ -502,11 +502,16 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
 // regulariser, tau, eps and scalars come from their own descriptors), so requests that
 // arrive while others run join the next tick. Only this thread issues HIP calls.
 // ------------------------------------------------------------------------------------
+// Everything a subgroup's launches take from its first member: grid and hierarchy, smoother
+// schedule, step type, stop flags (masks, S4 kernels), the tuned launch shapes, and for a
+// dense or ring operator the operator itself (its row count sizes grids, column chunks and
+// the ring adjoint's LDS). Blur requests of one grid share launches whatever their taps.
 struct ClassKey {
-  int nx, ny, nz, levels, smoother, nu, deg, kind, type, s4;
+  int nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win, xg;
   bool operator<(const ClassKey &o) const {
-    return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type, s4) <
-           std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type, o.s4);
+    return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win,
+                    xg) < std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind,
+                                   o.type, o.stop, o.op, o.gemv, o.cols, o.win, o.xg);
   }
 };
 
@@ -579,25 +584,64 @@ void serve_admit(plsqr_engine *eng) {
   }
 }
 
+// End every resident request with status rc (a tick could not be built). The device is
+// drained first: earlier ticks may still run on their workspaces. Caller holds the lock.
+void serve_fail_resident(plsqr_engine *eng, int rc, const std::string &msg) {
+  hipStreamSynchronize(eng->stream);
+  for (uint64_t t : eng->resident) {
+    Request &r = *eng->reqs[t];
+    if (r.ev_start) hipEventDestroy(r.ev_start);
+    if (r.ev_done) hipEventDestroy(r.ev_done);
+    r.ev_start = r.ev_done = nullptr;
+    if (r.pinned) hipHostFree(r.pinned);
+    r.pinned = nullptr;
+    if (r.ws) {
+      eng->pool.put(r.ws, r.lay.total);
+      eng->used -= r.lay.total;
+    }
+    r.ws = nullptr;
+    std::memset(&r.result, 0, sizeof(r.result));
+    r.result.status = rc;
+    r.status = rc;
+    r.err = msg;
+    r.done = true;
+  }
+  eng->resident.clear();
+}
+
 // Build and enqueue one tick. Caller holds the lock.
 void serve_tick(plsqr_engine *eng) {
   std::map<ClassKey, std::vector<Request *>> groups;
   for (uint64_t t : eng->resident) {
     Request &r = *eng->reqs[t];
     const plsqr_problem &pb = r.pb;
-    // the S4 kernels run only for subgroups whose members all carry the S4 vectors
+    // in serving mode `group` holds the operator id
+    const int op_key = r.host.op_kind == PLSQR_OP_BLUR ? -1 : (int)r.group;
     ClassKey key{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
-                 r.host.op_kind, step_type(pb, r.step), (int)(pb.flags & PLSQR_FLAG_STOP_S4)};
+                 r.host.op_kind, step_type(pb, r.step),
+                 (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)), op_key,
+                 pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window, pb.tune_blur_xgroups};
     groups[key].push_back(&r);
   }
   plsqr_engine::TickSlot &slot = eng->ring[eng->ring_next];
   const size_t need = eng->resident.size() * sizeof(void *) + groups.size() * 256;
   if (slot.cap < need) {
+    // the slot's last tick has finished: at most max_inflight_ticks (< ring size) are queued
     if (slot.pinned) hipHostFree(slot.pinned);
     if (slot.dev) hipFree(slot.dev);
-    slot.cap = std::max<size_t>(need * 2, 1 << 16);
-    hipHostMalloc(reinterpret_cast<void **>(&slot.pinned), slot.cap, hipHostMallocDefault);
-    hipMalloc(reinterpret_cast<void **>(&slot.dev), slot.cap);
+    slot.pinned = slot.dev = nullptr;
+    slot.cap = 0;
+    const size_t cap = std::max<size_t>(need * 2, 1 << 16);
+    if (hipHostMalloc(reinterpret_cast<void **>(&slot.pinned), cap, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&slot.dev), cap) != hipSuccess) {
+      if (slot.pinned) hipHostFree(slot.pinned);
+      slot.pinned = nullptr;
+      slot.dev = nullptr;
+      serve_fail_resident(eng, PLSQR_E_NOMEM, "allocation of a serving tick's pointer arrays failed");
+      return;
+    }
+    slot.cap = cap;
   }
   size_t off = 0;
   std::vector<std::pair<size_t, std::vector<Request *> *>> plan;

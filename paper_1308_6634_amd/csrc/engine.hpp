@@ -181,5 +181,5 @@ struct plsqr_engine {
   hipEvent_t ev_upload = nullptr;     // pointer arrays of the tick are on the device
   int ring_next = 0;
   uint64_t ticks = 0;
-  int max_inflight_ticks = 2;
+  int max_inflight_ticks = 2;         // below the ring size (4): a reused slot has finished
 };

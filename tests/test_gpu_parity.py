@@ -445,6 +445,38 @@ def test_served_mix_equals_alone(engine, budget_factor):
         assert r.submit_to_done_ms > 0.0
 
 
+def test_served_distinct_operators_on_one_grid(engine):
+    """Dense and ring requests on one 8^3 grid whose operators differ in row count (2 x 2,
+    4 x 2 and 4 x 4 rings of sources and detectors), all resident in a serving engine at once:
+    requests of different dense or ring operators never share a launch (the row count sizes the
+    grids, column chunks and the ring adjoint's LDS), so each gives the f it gives alone."""
+    import torch
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import Engine, problem_struct, solve
+    rings = [(2, 2), (4, 2), (4, 4), (2, 2), (4, 2)]
+    free = [False, False, True, True, False]
+    probs = [gen.small_dense_case(950 + i, 8, n_src_rings=s, n_det_rings=d, outer=2, inner=5)
+             for i, (s, d) in enumerate(rings)]
+    assert len({p.A.shape[0] for p in probs}) == 3
+    alone = [solve(p, engine=engine, matrix_free=mf)[0] for p, mf in zip(probs, free)]
+    _say(f"[serve] {len(probs)} dense/ring requests, rows {[p.A.shape[0] for p in probs]}")
+    with Engine(0, flags=P.PLSQR_ENGINE_SERVE) as srv:
+        ts, fs = [], []
+        for p, mf in zip(probs, free):
+            op = (srv.ring_operator(p.dims, *p.extra["ring"]) if mf
+                  else srv.dense_operator(p.dims, p.A))
+            g = torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda()
+            f = torch.zeros(p.n_x, device="cuda")
+            ts.append(srv.submit(op, problem_struct(p), g, f))
+            fs.append(f)
+        res = [srv.wait(t) for t in ts]
+        srv.wait_all()
+    for (st, _), p, a, f in zip(res, probs, alone, fs):
+        assert st == 0
+        err = _rel(f.cpu().numpy().reshape(a.shape), a)
+        assert err <= 1e-6, (p.name, err)
+
+
 def test_served_rejects_batch_calls(engine):
     import torch
     from paper_1308_6634_amd import plsqr as P
