@@ -28,6 +28,7 @@ namespace plsqr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmWaves = 8;                 // waves per block
 constexpr int kGemmRows = 32 * kGemmWaves;    // rows of the left operand per block
@@ -113,15 +114,18 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   };
   // loads past the last step re-read the last step (clamped index): the loop body has no
   // branches, so the compiler's wait counts follow the order of issue exactly
+  // the left operand is read exactly once: non-temporal loads stream it past the caches,
+  // which keep the right operand that every row block re-reads
+  auto ld_nt = [](const __bf16 *p) {
+    return __builtin_bit_cast(bf16x8, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p)));
+  };
   auto load_a = [&](AStep &a, long long st) {
     st = min(st, nsteps - 1);
 #pragma unroll
-    for (int q = 0; q < kSlots; ++q)
-      a.hi[q] = *reinterpret_cast<const bf16x8 *>(pa + st * kTileElems + q * 512);
+    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * kTileElems + q * 512);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q)
-        a.lo[q] = *reinterpret_cast<const bf16x8 *>(pal + st * kTileElems + q * 512);
+      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * kTileElems + q * 512);
     }
   };
   auto load_x = [&](XChunks &x, long long st) {
