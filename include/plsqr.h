@@ -109,7 +109,8 @@ typedef struct plsqr_engine plsqr_engine;   /* opaque; owns all internal device 
  *                  A_lo = bf16(A - A_hi). The batched BF16 products (PLSQR_PREC_BF16,
  *                  PLSQR_PREC_BF16_REFINED) take their operands from them when given
  *                  (else from A), copied once into library-owned tiled buffers when the
- *                  first such batch starts.
+ *                  first such batch starts: hi and lo parts of A and of A^T, 4 x n_y x
+ *                  nx*ny*nz x 2 bytes of device memory held until plsqr_destroy.
  *  PLSQR_OP_RING : the dense source-detector sensitivity of PLSQR_OP_DENSE's workloads,
  *                  never stored: entry (s * n_det + d, j) is
  *                      exp(-mu (r_sj + r_dj)) / (r_sj r_dj + 1),

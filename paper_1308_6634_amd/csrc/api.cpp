@@ -195,44 +195,30 @@ size_t plan_group(Group &G, const Operator &op, const Layout &Ly) {
   return (off + 255) / 256 * 256;
 }
 
-// Build (once) the tiled BF16 left operands of the batched products: A_hi, A_lo (forward,
-// L = A) and At_hi, At_lo (adjoint, L = A^T), all owned by the library. The hi parts come from
+// Build (once) the tiled BF16 left operands of the batched products, A (forward) and A^T
+// (adjoint), each as interleaved hi/lo tile pairs owned by the library. The hi parts come from
 // the caller's A_hi_dev when given, else hi = bf16(A); the lo parts from A_lo_dev when given,
-// else lo = bf16(A - bf16(A)).
-int ensure_bf16(plsqr_engine *eng, Operator &op, bool need_lo) {
+// else lo = bf16(A - bf16(A)). Both parts are built whatever the precision, so one copy serves
+// BF16 and BF16_REFINED groups alike.
+int ensure_bf16(plsqr_engine *eng, Operator &op) {
+  if (op.A_t && op.At_t) return PLSQR_OK;
   const long long m = op.op.n_y, n = (long long)op.op.nx * op.op.ny * op.op.nz;
-  const size_t bytes = (size_t)m * n * 2;
-  auto alloc = [&](void **p) -> int {
-    if (*p) return PLSQR_OK;
-    if (hipMalloc(p, bytes) != hipSuccess) {
-      *p = nullptr;
-      return set_error(PLSQR_E_NOMEM, "allocation of the BF16 operator copies failed");
-    }
-    return PLSQR_OK;
-  };
-  // both tiled copies of a part or neither: a failed allocation leaves none behind, so a later
-  // call builds the pair again
-  auto build = [&](void *&fwd, void *&adj, const uint16_t *given, bool is_lo) -> int {
-    if (fwd && adj) return PLSQR_OK;
-    int rc = alloc(&fwd);
-    if (rc == PLSQR_OK) rc = alloc(&adj);
-    if (rc != PLSQR_OK) {
-      if (fwd) hipFree(fwd);
-      if (adj) hipFree(adj);
-      fwd = adj = nullptr;
-      return rc;
-    }
-    for (int tr = 0; tr < 2; ++tr) {
-      void *dst = tr ? adj : fwd;
-      if (given) launch_retile16(eng->stream, given, m, n, tr, dst);
-      else launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, is_lo ? nullptr : dst,
-                              is_lo ? dst : nullptr);
-    }
-    return PLSQR_OK;
-  };
-  int rc = build(op.A_hi, op.At_hi, op.op.A_hi_dev, false);
-  if (rc != PLSQR_OK) return rc;
-  if (need_lo && (rc = build(op.A_lo, op.At_lo, op.op.A_lo_dev, true)) != PLSQR_OK) return rc;
+  const size_t bytes = (size_t)m * n * 2 * 2;
+  // both copies or neither: a failed allocation leaves none behind, so a later call builds
+  // the pair again
+  if (hipMalloc(&op.A_t, bytes) != hipSuccess || hipMalloc(&op.At_t, bytes) != hipSuccess) {
+    if (op.A_t) hipFree(op.A_t);
+    if (op.At_t) hipFree(op.At_t);
+    op.A_t = op.At_t = nullptr;
+    return set_error(PLSQR_E_NOMEM, "allocation of the BF16 operator copies failed");
+  }
+  const uint16_t *hi = op.op.A_hi_dev, *lo = op.op.A_lo_dev;
+  for (int tr = 0; tr < 2; ++tr) {
+    void *dst = tr ? op.At_t : op.A_t;
+    if (!hi || !lo) launch_split_tiled(eng->stream, op.op.A_dev, m, n, tr, dst);
+    if (hi) launch_retile16(eng->stream, hi, m, n, tr, 0, dst);
+    if (lo) launch_retile16(eng->stream, lo, m, n, tr, 1, dst);
+  }
   HIP_TRY(hipGetLastError());
   return PLSQR_OK;
 }
@@ -273,7 +259,7 @@ int start_group_impl(plsqr_engine *eng, Group &G) {
   const int B = (int)G.members.size();
   Request &r0 = *eng->reqs[G.members[0]];
   if (G.use_gemm) {
-    const int rc = ensure_bf16(eng, op, G.gemm.use_A_lo != 0);
+    const int rc = ensure_bf16(eng, op);
     if (rc != PLSQR_OK) return rc;
   }
   G.state = Group::RUNNING;        // from here on release_group returns the budget
@@ -289,10 +275,8 @@ int start_group_impl(plsqr_engine *eng, Group &G) {
     fix(g.U_hi);
     fix(g.U_lo);
     g.Ypart = reinterpret_cast<float *>(G.gws + reinterpret_cast<size_t>(g.Ypart));
-    g.A_hi = op.A_hi;
-    g.A_lo = op.A_lo;
-    g.At_hi = op.At_hi;
-    g.At_lo = op.At_lo;
+    g.A_t = op.A_t;
+    g.At_t = op.At_t;
   }
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&G.pinned), (size_t)B * sizeof(void *),
                         hipHostMallocDefault));
@@ -1061,10 +1045,8 @@ int plsqr_destroy(plsqr_engine *eng) {
     eng->groups.clear();
     eng->reqs.clear();
     for (auto &op : eng->ops) {
-      if (op.A_hi) hipFree(op.A_hi);
-      if (op.A_lo) hipFree(op.A_lo);
-      if (op.At_hi) hipFree(op.At_hi);
-      if (op.At_lo) hipFree(op.At_lo);
+      if (op.A_t) hipFree(op.A_t);
+      if (op.At_t) hipFree(op.At_t);
       if (op.ring) hipFree(op.ring);
     }
     eng->ops.clear();

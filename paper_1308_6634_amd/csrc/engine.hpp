@@ -20,8 +20,9 @@ namespace plsqr {
 struct Operator {
   plsqr_operator op{};
   std::vector<float> taps;
-  // tiled BF16 left operands of the batched MFMA products (built on first use, owned)
-  void *A_hi = nullptr, *A_lo = nullptr, *At_hi = nullptr, *At_lo = nullptr;
+  // tiled BF16 left operands of the batched MFMA products, A and A^T, each holding its hi and
+  // lo parts as interleaved tile pairs (built on first use, owned)
+  void *A_t = nullptr, *At_t = nullptr;
   // ring sensitivity: source then detector positions (x, y, z floats) on the device
   float *ring = nullptr;
 };

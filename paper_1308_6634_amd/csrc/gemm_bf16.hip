@@ -9,13 +9,15 @@
 // Tiling (gfx950, v_mfma_f32_32x32x16_bf16, wave64): a block of 8 waves owns 256 rows of
 // the left operand; each wave owns 32 rows and all Bpad (= 32 * NT) columns. Per step of
 // 64 along K, lane (i, h) (i = lane % 32, h = lane / 32) loads 32 contiguous K values of
-// its row (4 x 16-byte loads, issued three steps ahead) and feeds them to 4 MFMAs. The left
-// operand is stored tiled (the library builds it once per operator, see k_split_tiled): each
-// 32-row x 64-K tile is 4 KB contiguous with lane (i, h)'s 16-byte vector for load s at
-// vector index s * 64 + lane, so each load instruction of a wave reads 1 KB contiguous and a
-// wave streams its row tile's K range front to back (a row-major operand would make every
-// load instruction gather 16 bytes from 32 rows 2 K apart, re-requesting each cache line 8
-// times and scattering DRAM accesses over all rows of the tile); the
+// its row (4 x 16-byte loads per part, issued three steps ahead) and feeds them to 4 MFMAs.
+// The left operand is stored tiled (the library builds it once per operator, see
+// k_split_tiled): each 32-row x 64-K tile of one part is 4 KB contiguous with lane (i, h)'s
+// 16-byte vector for load s at vector index s * 64 + lane, and the hi tile is followed by the
+// lo tile of the same rows and K range, so each load instruction of a wave reads 1 KB
+// contiguous and a wave streams one 8 KB run per step, its row tile's K range front to back
+// (a row-major operand would make every load instruction gather 16 bytes from 32 rows 2 K
+// apart, re-requesting each cache line 8 times and scattering DRAM accesses over all rows of
+// the tile; separate hi and lo arrays would give each wave two streams 4 GiB apart); the
 // right-operand block of the step (hi and lo, Bpad x 64) is staged once per block in
 // LDS (double-buffered, rows padded against bank conflicts) and lane (j, h) reads the
 // same 32 K indices of column j, so every MFMA pairs identical K indices (the K order
@@ -36,6 +38,7 @@ constexpr int kKStep = 64;                    // K per step
 constexpr int kSlots = kKStep / 16;           // MFMAs along K per step (8 K per lane half)
 constexpr int kLdsRow = kKStep + 8;           // bf16 per LDS column row (padded: no bank conflicts)
 constexpr int kTileElems = 32 * kKStep;       // elements of one 32-row x 64-K left-operand tile
+constexpr int kPairElems = 2 * kTileElems;    // a hi tile and its lo tile
 constexpr int kChunks = kKStep / 8;           // 16-byte chunks of one column per step
 
 // Right-operand block of one K step in LDS: [hi | lo][Bpad columns][kLdsRow]. Each of
@@ -80,8 +83,7 @@ __device__ __forceinline__ void store_right(__bf16 *lds, const XChunks &x) {
 
 template <int NT, bool LO_L, bool EPI>
 __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
-    const __bf16 *__restrict__ Lhi, const __bf16 *__restrict__ Llo,
-    const __bf16 *__restrict__ Rhi, const __bf16 *__restrict__ Rlo, long long M, long long K,
+    const __bf16 *__restrict__ L, const __bf16 *__restrict__ Rhi, const __bf16 *__restrict__ Rlo, long long M, long long K,
     long long kchunk, int Bpad, float *__restrict__ out, InstDesc *const *descs, int B, int epi) {
   __shared__ __bf16 lds[2][2 * NT * 32 * kLdsRow];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -96,11 +98,11 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
-  // this wave's row tile in the tiled operand; step st is tile (kbeg / kKStep + st) of it,
-  // load s of lane `lane` is vector s * 64 + lane of that tile
+  // this wave's row tile in the tiled operand; step st is tile pair (kbeg / kKStep + st) of
+  // it, load s of lane `lane` is vector s * 64 + lane of the pair's hi and lo tiles
   const long long tile0 = (row0 / 32) * (K / kKStep) + kbeg / kKStep;
-  const __bf16 *pa = Lhi + tile0 * kTileElems + lane * 8;
-  const __bf16 *pal = LO_L ? Llo + tile0 * kTileElems + lane * 8 : nullptr;
+  const __bf16 *pa = L + tile0 * kPairElems + lane * 8;
+  const __bf16 *pal = pa + kTileElems;
   const long long nsteps = (kend - kbeg) / kKStep;   // kchunk and K are multiples of kKStep
   // Pipeline: the left operand of step st + 3 and the right operand of step st + 2 are
   // issued while step st computes, in that order of issue per step (right, then left), so
@@ -122,10 +124,10 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   auto load_a = [&](AStep &a, long long st) {
     st = min(st, nsteps - 1);
 #pragma unroll
-    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * kTileElems + q * 512);
+    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * kPairElems + q * 512);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * kTileElems + q * 512);
+      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * kPairElems + q * 512);
     }
   };
   auto load_x = [&](XChunks &x, long long st) {
@@ -184,23 +186,31 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
     step(a3, a2, x1, x0, st + 3);
   }
   // accumulator element r of lane (li, h) is (row 8*(r/4) + 4*h + r%4, column li) of the tile
+  auto row_of = [&](int r) { return row0 + (r >> 2) * 8 + h * 4 + (r & 3); };
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int col = t * 32 + li;
-    int e = epi;
-    bool skip = false;
-    if constexpr (EPI) skip = col < B && product_masked(*descs[col], e);
+    if constexpr (!EPI) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const long long row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
-      if constexpr (!EPI) {
-        out[((long long)ks * M + row) * Bpad + col] = acc[t][r];
-      } else {
-        if (col < B && !skip) {
-          const InstDesc &D = *descs[col];
-          double unused = 0.0;
-          epilogue(D, e, row, acc[t][r], nullptr, unused);
-        }
+      for (int r = 0; r < 16; ++r) out[((long long)ks * M + row_of(r)) * Bpad + col] = acc[t][r];
+    } else {
+      // The adjoint epilogue of instance `col` on this lane's 16 rows (EPI_ADJ_INIT: p = su y;
+      // EPI_ADJ: p = su y - (beta sv) p, the only codes this kernel is launched with). The
+      // instance's scalars are read once and the 16 old values of p are loaded before any is
+      // stored, so the lane waits on memory once rather than once per row.
+      int e = epi;
+      if (col < B && !product_masked(*descs[col], e)) {
+        const InstDesc &D = *descs[col];
+        float *p = sld(D.p);
+        const double *sc = sld(D.sc);
+        const float c1 = (float)sc[SC_SU];
+        const bool upd = (e == EPI_ADJ);
+        const float c2 = upd ? (float)(sc[SC_BETA] * sc[SC_SV]) : 0.f;
+        float old[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) old[r] = upd ? p[row_of(r)] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) p[row_of(r)] = upd ? c1 * acc[t][r] - c2 * old[r] : c1 * acc[t][r];
       }
     }
   }
@@ -239,10 +249,11 @@ __global__ void __launch_bounds__(kBlock) k_pack_split(InstDesc *const *descs, i
 }
 
 // Tiled left operands (layout described at the top of this file). Vector v (16 bytes, 8
-// elements) of the tiled M x K operand L is vector s * 64 + lane of tile (rt, kt), with
-// v = ((rt * K/64 + kt) * 4 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
-// row = 32 rt + lane % 32 and k0 = 64 kt + 32 (lane / 32) + 8 s. L is A (n_y x n_x) for the
-// forward product (transposed = 0) or A^T for the adjoint (transposed = 1).
+// elements) of one part of the tiled M x K operand L is vector s * 64 + lane of tile (rt, kt),
+// with v = ((rt * K/64 + kt) * 4 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
+// row = 32 rt + lane % 32 and k0 = 64 kt + 32 (lane / 32) + 8 s. It sits at element
+// pair_offset(v) of the hi/lo pair array (hi part), kTileElems further on (lo part). L is A
+// (n_y x n_x) for the forward product (transposed = 0) or A^T for the adjoint (transposed = 1).
 __device__ __forceinline__ void tiled_coords(long long v, long long K, int transposed,
                                              long long n_x, long long &row, long long &k0,
                                              long long &stride) {
@@ -256,11 +267,15 @@ __device__ __forceinline__ void tiled_coords(long long v, long long K, int trans
   stride = transposed ? n_x : 1;     // distance between L[row][k] and L[row][k + 1] in A
 }
 
-// hi = bf16(L), lo = bf16(L - hi) in the tiled layout, from the float32 row-major A
-// (either output may be null).
+__device__ __forceinline__ long long pair_offset(long long v) {
+  constexpr int kTileVecs = kTileElems / 8;
+  return (v / kTileVecs) * kPairElems + (v % kTileVecs) * 8;
+}
+
+// hi = bf16(L), lo = bf16(L - hi) in the tiled pair layout, from the float32 row-major A.
 __global__ void __launch_bounds__(kBlock) k_split_tiled(const float *A, long long n_y,
-                                                       long long n_x, int transposed, __bf16 *hi,
-                                                       __bf16 *lo) {
+                                                       long long n_x, int transposed,
+                                                       __bf16 *dst) {
   const long long M = transposed ? n_x : n_y, K = transposed ? n_y : n_x;
   const long long nvec = M * K / 8;
   for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nvec;
@@ -275,14 +290,17 @@ __global__ void __launch_bounds__(kBlock) k_split_tiled(const float *A, long lon
       h[e] = (__bf16)a;
       l[e] = (__bf16)(a - (float)h[e]);
     }
-    if (hi) *reinterpret_cast<bf16x8 *>(hi + v * 8) = h;
-    if (lo) *reinterpret_cast<bf16x8 *>(lo + v * 8) = l;
+    __bf16 *o = dst + pair_offset(v);
+    *reinterpret_cast<bf16x8 *>(o) = h;
+    *reinterpret_cast<bf16x8 *>(o + kTileElems) = l;
   }
 }
 
-// The tiled layout of a 16-bit row-major copy of A (n_y x n_x), as L = A or L = A^T.
+// The tiled layout of a 16-bit row-major copy of A (n_y x n_x), as L = A or L = A^T, into
+// part `part` (0: hi, 1: lo) of the tile pairs.
 __global__ void __launch_bounds__(kBlock) k_retile16(const uint16_t *src16, long long n_y,
-                                                    long long n_x, int transposed, uint16_t *dst) {
+                                                    long long n_x, int transposed, int part,
+                                                    uint16_t *dst) {
   const long long M = transposed ? n_x : n_y, K = transposed ? n_y : n_x;
   const long long nvec = M * K / 8;
   for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nvec;
@@ -293,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_retile16(const uint16_t *src16, long
     uint16_t w[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) w[e] = src[e * stride];
-    *reinterpret_cast<uint4 *>(dst + v * 8) =
+    *reinterpret_cast<uint4 *>(dst + pair_offset(v) + part * kTileElems) =
         make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
                    w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
   }
@@ -303,26 +321,24 @@ __global__ void __launch_bounds__(kBlock) k_retile16(const uint16_t *src16, long
 // launchers
 // ------------------------------------------------------------------------------------
 template <int NT, bool LO_L, bool EPI>
-static void gemm_launch(hipStream_t st, const void *Lhi, const void *Llo, const void *Rhi,
-                        const void *Rlo, long long M, long long K, long long kchunk, int ks,
-                        int Bpad, float *out, InstDesc *const *descs, int B, int epi) {
+static void gemm_launch(hipStream_t st, const void *L, const void *Rhi, const void *Rlo,
+                        long long M, long long K, long long kchunk, int ks, int Bpad, float *out,
+                        InstDesc *const *descs, int B, int epi) {
   hipLaunchKernelGGL((k_gemm_bf16<NT, LO_L, EPI>), dim3((unsigned)(M / kGemmRows), ks),
-                     dim3(64 * kGemmWaves), 0, st, (const __bf16 *)Lhi, (const __bf16 *)Llo,
-                     (const __bf16 *)Rhi, (const __bf16 *)Rlo, M, K, kchunk, Bpad, out, descs, B,
-                     epi);
+                     dim3(64 * kGemmWaves), 0, st, (const __bf16 *)L, (const __bf16 *)Rhi,
+                     (const __bf16 *)Rlo, M, K, kchunk, Bpad, out, descs, B, epi);
 }
 
 template <bool EPI>
-static void gemm_dispatch(hipStream_t st, int NT, bool lo_l, const void *Lhi, const void *Llo,
-                          const void *Rhi, const void *Rlo, long long M, long long K,
-                          long long kchunk, int ks, int Bpad, float *out, InstDesc *const *descs,
-                          int B, int epi) {
+static void gemm_dispatch(hipStream_t st, int NT, bool lo_l, const void *L, const void *Rhi,
+                          const void *Rlo, long long M, long long K, long long kchunk, int ks,
+                          int Bpad, float *out, InstDesc *const *descs, int B, int epi) {
   if (NT == 1) {
-    if (lo_l) gemm_launch<1, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
-    else gemm_launch<1, false, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    if (lo_l) gemm_launch<1, true, EPI>(st, L, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    else gemm_launch<1, false, EPI>(st, L, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
   } else {
-    if (lo_l) gemm_launch<2, true, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
-    else gemm_launch<2, false, EPI>(st, Lhi, Llo, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    if (lo_l) gemm_launch<2, true, EPI>(st, L, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
+    else gemm_launch<2, false, EPI>(st, L, Rhi, Rlo, M, K, kchunk, ks, Bpad, out, descs, B, epi);
   }
 }
 
@@ -332,8 +348,8 @@ int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArg
   const unsigned pb = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_pack_split, dim3(pb, g.Bpad), dim3(kBlock), 0, st, d, B, src_sel, n,
                      (__bf16 *)g.X_hi, (__bf16 *)g.X_lo);
-  gemm_dispatch<false>(st, g.Bpad / 32, g.use_A_lo != 0, g.A_hi, g.A_lo, g.X_hi, g.X_lo, m, n,
-                       g.kchunk, g.ks, g.Bpad, g.Ypart, d, B, epi);
+  gemm_dispatch<false>(st, g.Bpad / 32, g.use_A_lo != 0, g.A_t, g.X_hi, g.X_lo, m, n, g.kchunk,
+                       g.ks, g.Bpad, g.Ypart, d, B, epi);
   const unsigned rb = (unsigned)((m + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_fwd_reduce, dim3(rb, B), dim3(kBlock), 0, st, d, (const float *)g.Ypart, g.ks,
                      m, g.Bpad, epi);
@@ -346,20 +362,20 @@ void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmAr
   const unsigned pb = (unsigned)((m + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_pack_split, dim3(pb, g.Bpad), dim3(kBlock), 0, st, d, B, (int)V_U, m,
                      (__bf16 *)g.U_hi, (__bf16 *)g.U_lo);
-  gemm_dispatch<true>(st, g.Bpad / 32, g.use_A_lo != 0, g.At_hi, g.At_lo, g.U_hi, g.U_lo, n, m, m,
-                      1, g.Bpad, nullptr, d, B, epi);
+  gemm_dispatch<true>(st, g.Bpad / 32, g.use_A_lo != 0, g.At_t, g.U_hi, g.U_lo, n, m, m, 1,
+                      g.Bpad, nullptr, d, B, epi);
 }
 
 void launch_split_tiled(hipStream_t st, const float *A, long long n_y, long long n_x,
-                        int transposed, void *hi, void *lo) {
+                        int transposed, void *dst) {
   hipLaunchKernelGGL(k_split_tiled, dim3(8192), dim3(kBlock), 0, st, A, n_y, n_x, transposed,
-                     (__bf16 *)hi, (__bf16 *)lo);
+                     (__bf16 *)dst);
 }
 
 void launch_retile16(hipStream_t st, const void *src, long long n_y, long long n_x,
-                     int transposed, void *dst) {
+                     int transposed, int part, void *dst) {
   hipLaunchKernelGGL(k_retile16, dim3(8192), dim3(kBlock), 0, st, (const uint16_t *)src, n_y, n_x,
-                     transposed, (uint16_t *)dst);
+                     transposed, part, (uint16_t *)dst);
 }
 
 }  // namespace plsqr

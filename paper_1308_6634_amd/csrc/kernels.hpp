@@ -85,13 +85,14 @@ int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArg
                         long long n, int src_sel, int epi);
 void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
                          long long n, int epi);
-// Tiled BF16 left operands of the batched products (n_y, n_x divisible by 256): the split
-// hi = bf16(L), lo = bf16(L - hi) of L = A (transposed = 0) or L = A^T (transposed = 1) from the
-// float32 row-major A (either output may be null), or the tiled copy of a 16-bit row-major A.
+// Tiled BF16 left operands of the batched products (n_y, n_x divisible by 256), stored as
+// interleaved hi/lo tile pairs (2 x n_y x n_x bf16): the split hi = bf16(L), lo = bf16(L - hi)
+// of L = A (transposed = 0) or L = A^T (transposed = 1) from the float32 row-major A, or the
+// tiled copy of a 16-bit row-major A into the pairs' hi (part 0) or lo (part 1) halves.
 void launch_split_tiled(hipStream_t st, const float *A, long long n_y, long long n_x,
-                        int transposed, void *hi, void *lo);
+                        int transposed, void *dst);
 void launch_retile16(hipStream_t st, const void *src, long long n_y, long long n_x,
-                     int transposed, void *dst);
+                     int transposed, int part, void *dst);
 void launch_copy_out(hipStream_t st, InstDesc *const *d, int B, long long n);
 // matrix-free ring sensitivity products (ring.hip); the forward returns its partial count
 int launch_ring_forward(hipStream_t st, InstDesc *const *d, int B, const InstDesc &H, int src,

@@ -128,13 +128,13 @@ enum Fin : int {
 namespace plsqr {
 // Dense products of a lockstep batch on MFMA (BF16 operands, FP32 accumulation).
 struct GemmArgs {
-  const void *A_hi, *A_lo;     // n_Y x n_X bf16 row-major (forward left operand)
-  const void *At_hi, *At_lo;   // n_X x n_Y bf16 row-major (adjoint left operand)
+  const void *A_t;             // A (n_Y x n_X) as tiled bf16 hi/lo tile pairs (forward)
+  const void *At_t;            // A^T (n_X x n_Y), the same layout (adjoint)
   void *X_hi, *X_lo;           // packed right operand, Bpad x n_X (forward)
   void *U_hi, *U_lo;           // packed right operand, Bpad x n_Y (adjoint)
   float *Ypart;                // forward split-K partials, ks x n_Y x Bpad
   int Bpad, ks;                // padded batch (multiple of 32), K splits of the forward GEMM
-  long long kchunk;            // forward K chunk (multiple of 128)
+  long long kchunk;            // forward K chunk (multiple of 256)
   int use_A_lo;                // add the A_lo x X_hi refinement term
 };
 }  // namespace plsqr
