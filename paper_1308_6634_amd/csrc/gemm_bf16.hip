@@ -13,11 +13,16 @@
 // The left operand is stored tiled (the library builds it once per operator, see
 // k_split_tiled): each 32-row x 64-K tile of one part is 4 KB contiguous with lane (i, h)'s
 // 16-byte vector for load s at vector index s * 64 + lane, and the hi tile is followed by the
-// lo tile of the same rows and K range, so each load instruction of a wave reads 1 KB
-// contiguous and a wave streams one 8 KB run per step, its row tile's K range front to back
-// (a row-major operand would make every load instruction gather 16 bytes from 32 rows 2 K
-// apart, re-requesting each cache line 8 times and scattering DRAM accesses over all rows of
-// the tile; separate hi and lo arrays would give each wave two streams 4 GiB apart); the
+// lo tile of the same rows and K range. In the forward operand the 8 KB tile pairs of the 8
+// row tiles of one block (256 rows) at one K step are adjacent and the K steps follow each
+// other, so a block streams one 64 KB run per step; in the adjoint operand each row tile's
+// pairs follow each other along K, so each wave streams its own 8 KB per step (measured on the
+// 8192 x 262144 batch: the forward product, one round of 256 blocks, is 4% faster grouped; the
+// adjoint, four rounds of 256, 4% slower). Each load instruction of a wave reads 1 KB
+// contiguous (a row-major operand would make every load instruction gather 16 bytes from 32
+// rows 2 K apart, re-requesting each cache line 8 times and scattering DRAM accesses over all
+// rows of the tile; separate hi and lo arrays would give each wave two streams 4 GiB apart);
+// the
 // right-operand block of the step (hi and lo, Bpad x 64) is staged once per block in
 // LDS (double-buffered, rows padded against bank conflicts) and lane (j, h) reads the
 // same 32 K indices of column j, so every MFMA pairs identical K indices (the K order
@@ -39,6 +44,8 @@ constexpr int kSlots = kKStep / 16;           // MFMAs along K per step (8 K per
 constexpr int kLdsRow = kKStep + 8;           // bf16 per LDS column row (padded: no bank conflicts)
 constexpr int kTileElems = 32 * kKStep;       // elements of one 32-row x 64-K left-operand tile
 constexpr int kPairElems = 2 * kTileElems;    // a hi tile and its lo tile
+constexpr int kGroupFwd = kGemmWaves;         // row tiles whose pairs interleave per K step:
+constexpr int kGroupAdj = 1;                  // forward operand, adjoint operand
 constexpr int kChunks = kKStep / 8;           // 16-byte chunks of one column per step
 
 // Right-operand block of one K step in LDS: [hi | lo][Bpad columns][kLdsRow]. Each of
@@ -84,7 +91,8 @@ __device__ __forceinline__ void store_right(__bf16 *lds, const XChunks &x) {
 template <int NT, bool LO_L, bool EPI>
 __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
     const __bf16 *__restrict__ L, const __bf16 *__restrict__ Rhi, const __bf16 *__restrict__ Rlo, long long M, long long K,
-    long long kchunk, int Bpad, float *__restrict__ out, InstDesc *const *descs, int B, int epi) {
+    long long kchunk, int group, int Bpad, float *__restrict__ out, InstDesc *const *descs, int B,
+    int epi) {
   __shared__ __bf16 lds[2][2 * NT * 32 * kLdsRow];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, h = lane >> 5;
@@ -98,11 +106,14 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
-  // this wave's row tile in the tiled operand; step st is tile pair (kbeg / kKStep + st) of
-  // it, load s of lane `lane` is vector s * 64 + lane of the pair's hi and lo tiles
-  const long long tile0 = (row0 / 32) * (K / kKStep) + kbeg / kKStep;
-  const __bf16 *pa = L + tile0 * kPairElems + lane * 8;
+  // this wave's row tile rt in the tiled operand: step st is pair
+  // (rt / group * K/64 + kbeg / kKStep + st) * group + rt % group, load s of lane `lane` is
+  // vector s * 64 + lane of the pair's hi and lo tiles
+  const long long rt = row0 / 32;
+  const long long pair0 = ((rt / group) * (K / kKStep) + kbeg / kKStep) * group + rt % group;
+  const __bf16 *pa = L + pair0 * kPairElems + lane * 8;
   const __bf16 *pal = pa + kTileElems;
+  const long long step_elems = (long long)group * kPairElems;
   const long long nsteps = (kend - kbeg) / kKStep;   // kchunk and K are multiples of kKStep
   // Pipeline: the left operand of step st + 3 and the right operand of step st + 2 are
   // issued while step st computes, in that order of issue per step (right, then left), so
@@ -124,10 +135,10 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   auto load_a = [&](AStep &a, long long st) {
     st = min(st, nsteps - 1);
 #pragma unroll
-    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * kPairElems + q * 512);
+    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * step_elems + q * 512);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * kPairElems + q * 512);
+      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * step_elems + q * 512);
     }
   };
   auto load_x = [&](XChunks &x, long long st) {
@@ -252,8 +263,10 @@ __global__ void __launch_bounds__(kBlock) k_pack_split(InstDesc *const *descs, i
 // elements) of one part of the tiled M x K operand L is vector s * 64 + lane of tile (rt, kt),
 // with v = ((rt * K/64 + kt) * 4 + s) * 64 + lane; it holds L[row][k0 .. k0 + 7] with
 // row = 32 rt + lane % 32 and k0 = 64 kt + 32 (lane / 32) + 8 s. It sits at element
-// pair_offset(v) of the hi/lo pair array (hi part), kTileElems further on (lo part). L is A
-// (n_y x n_x) for the forward product (transposed = 0) or A^T for the adjoint (transposed = 1).
+// pair_offset(v, K, group) of the hi/lo pair array (hi part), kTileElems further on (lo part):
+// tile (rt, kt) is pair (rt / group * K/64 + kt) * group + rt % group. L is A (n_y x n_x) for
+// the forward product (transposed = 0, group kGroupFwd) or A^T for the adjoint
+// (transposed = 1, group kGroupAdj).
 __device__ __forceinline__ void tiled_coords(long long v, long long K, int transposed,
                                              long long n_x, long long &row, long long &k0,
                                              long long &stride) {
@@ -267,9 +280,12 @@ __device__ __forceinline__ void tiled_coords(long long v, long long K, int trans
   stride = transposed ? n_x : 1;     // distance between L[row][k] and L[row][k + 1] in A
 }
 
-__device__ __forceinline__ long long pair_offset(long long v) {
+__device__ __forceinline__ long long pair_offset(long long v, long long K, int group) {
   constexpr int kTileVecs = kTileElems / 8;
-  return (v / kTileVecs) * kPairElems + (v % kTileVecs) * 8;
+  const long long tile = v / kTileVecs, nkt = K / kKStep;
+  const long long rt = tile / nkt, kt = tile % nkt;
+  const long long pair = ((rt / group) * nkt + kt) * group + rt % group;
+  return pair * kPairElems + (v % kTileVecs) * 8;
 }
 
 // hi = bf16(L), lo = bf16(L - hi) in the tiled pair layout, from the float32 row-major A.
@@ -290,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_split_tiled(const float *A, long lon
       h[e] = (__bf16)a;
       l[e] = (__bf16)(a - (float)h[e]);
     }
-    __bf16 *o = dst + pair_offset(v);
+    __bf16 *o = dst + pair_offset(v, K, transposed ? kGroupAdj : kGroupFwd);
     *reinterpret_cast<bf16x8 *>(o) = h;
     *reinterpret_cast<bf16x8 *>(o + kTileElems) = l;
   }
@@ -311,7 +327,8 @@ __global__ void __launch_bounds__(kBlock) k_retile16(const uint16_t *src16, long
     uint16_t w[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) w[e] = src[e * stride];
-    *reinterpret_cast<uint4 *>(dst + pair_offset(v) + part * kTileElems) =
+    *reinterpret_cast<uint4 *>(dst + pair_offset(v, K, transposed ? kGroupAdj : kGroupFwd) +
+                               part * kTileElems) =
         make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
                    w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
   }
@@ -324,9 +341,11 @@ template <int NT, bool LO_L, bool EPI>
 static void gemm_launch(hipStream_t st, const void *L, const void *Rhi, const void *Rlo,
                         long long M, long long K, long long kchunk, int ks, int Bpad, float *out,
                         InstDesc *const *descs, int B, int epi) {
+  // the epilogue variant is the adjoint product, whose operand is tiled with kGroupAdj
   hipLaunchKernelGGL((k_gemm_bf16<NT, LO_L, EPI>), dim3((unsigned)(M / kGemmRows), ks),
                      dim3(64 * kGemmWaves), 0, st, (const __bf16 *)L, (const __bf16 *)Rhi,
-                     (const __bf16 *)Rlo, M, K, kchunk, Bpad, out, descs, B, epi);
+                     (const __bf16 *)Rlo, M, K, kchunk, EPI ? kGroupAdj : kGroupFwd, Bpad, out,
+                     descs, B, epi);
 }
 
 template <bool EPI>
