@@ -245,9 +245,10 @@ int plsqr_solve_taus(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob
  * GEMMs over the batch, reading A once per product for the whole batch). The problems
  * may differ in reg, T, tau, eps, omega and the Chebyshev interval but must share grid,
  * counts, levels, smoother kind and steps, precision and flags. BF16 batches need a
- * dense operator, count <= 64 and n_X, n_Y divisible by 256; the BF16 copies of A
- * (A_hi, A_lo and their transposes) are taken from the operator if given, else built
- * by the library on first use and kept until plsqr_destroy. tickets[i] receives the
+ * dense operator, count <= 64 and n_X, n_Y divisible by 256; the library builds tiled
+ * BF16 copies of A and A^T (hi and lo parts) on first use, from the operator's
+ * A_hi_dev / A_lo_dev when given, else from A, and keeps them until plsqr_destroy
+ * (4 x n_Y x n_X x 2 bytes of device memory). tickets[i] receives the
  * ticket of request i; every ticket completes when the whole batch does. */
 int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const plsqr_problem *probs,
                       const float *const *g_devs, float *const *f_devs, uint64_t *tickets);
