@@ -335,6 +335,32 @@ def test_batch_bf16_dense_matches_oracle(engine, precision, tol):
     assert max(errs) <= tol, errs
 
 
+@pytest.mark.parametrize("precision", [1, 2])
+def test_batch_bf16_exact_inputs_match_oracle(engine, precision):
+    """The MFMA products against exact arithmetic on the same BF16 inputs: A is rounded to
+    BF16 values first (round to nearest even, by torch on the CPU), so the library's split is
+    exact (hi = A, lo = 0) and the FP64 oracle runs on the very matrix the GEMMs read. What
+    remains is the split of the vectors (x_hi + x_lo within 2^-18 of x) and FP32
+    accumulation. In FP64 on the CPU the split alone moves these solves by 4e-7 to 7e-7 and
+    dropping the x_lo term (2^-9 per entry) by 5e-5 to 4e-4, so the bar is 1e-5: that slip, a
+    transposed tile or a misplaced K range misses it."""
+    import torch
+    A = gen.small_dense_case(87, 16).A
+    A_r = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float32)).to(torch.bfloat16)
+    A_r = A_r.float().numpy().astype(np.float64)
+    assert np.array_equal(A_r.astype(np.float32).astype(np.float64), A_r)
+    probs = [gen.small_dense_case(87 + i, 16, reg=("stv", "pm_log")[i % 2],
+                                  T=(0.02, 0.05)[i % 2], tau=20.0, outer=3, inner=10, levels=3,
+                                  A=A_r) for i in range(3)]
+    _say(f"[batch] bf16 precision={precision} on BF16-valued A, dense x3 (16^3)")
+    errs = []
+    for p, f in zip(probs, _run_batch(engine, probs, precision=precision)):
+        f_ref, _ = lagged.solve_problem(p)
+        errs.append(_rel(f, f_ref))
+    _say(f"[batch] bf16 exact inputs precision={precision}: rel L2 = {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-5, errs
+
+
 def test_batch_bf16_alone_equals_in_batch(engine):
     """An instance gives the same f alone (batch of one) and inside a batch of 33
     (two MFMA column tiles): its column of the GEMM does not see the others."""
