@@ -320,8 +320,12 @@ def test_batch_fp32_dense_matches_oracle(engine):
         assert _rel(f, f_ref) <= TOL
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 5e-3), (2, 5e-3)])
+@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (2, 1e-3)])
 def test_batch_bf16_dense_matches_oracle(engine, precision, tol):
+    """Whole solves against the FP64 oracle on the exact A. BF16_REFINED keeps the terms whose
+    error is ~2^-16 relative per entry (measured up to 2.6e-6 here); dropping its A_lo term
+    leaves the 2^-9 rounding of A, which BF16 keeps by design (measured 2.4e-4 to 2.8e-4), so
+    the refined bar of 2e-5 also catches a lost refinement term."""
     A = gen.small_dense_case(80, 16).A            # 1024 x 4096: both divisible by 128
     probs = [gen.small_dense_case(80 + i, 16, reg=("stv", "pm_log")[i % 2],
                                   T=(0.02, 0.05)[i % 2], tau=20.0, outer=3, inner=10, levels=3,
