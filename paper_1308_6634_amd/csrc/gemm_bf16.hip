@@ -96,8 +96,13 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   __shared__ __bf16 lds[2][2 * NT * 32 * kLdsRow];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, h = lane >> 5;
-  const long long row0 = (long long)blockIdx.x * kGemmRows + wave * 32;
-  const int ks = blockIdx.y;
+  // (row group, K split) of this block: workgroups are dealt to the 8 XCDs round-robin in
+  // linear order, so taking the split from the low part of the linear index puts the blocks of
+  // one split on one XCD (with 8 splits), whose L2 then serves that split's right operand
+  const long long bid = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+  const long long rgrp = bid / gridDim.y;
+  const int ks = (int)(bid % gridDim.y);
+  const long long row0 = rgrp * kGemmRows + wave * 32;
   const long long kbeg = (long long)ks * kchunk;
   const long long kend = min(K, kbeg + kchunk);
   f32x16 acc[NT];
@@ -111,6 +116,8 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   // vector s * 64 + lane of the pair's hi and lo tiles
   const long long rt = row0 / 32;
   const long long pair0 = ((rt / group) * (K / kKStep) + kbeg / kKStep) * group + rt % group;
+  // loads issued past the last step read the first 4 KB of the right operand instead (valid,
+  // cached, never used): re-reading the left operand would fetch it from memory again
   const __bf16 *pa = L + pair0 * kPairElems + lane * 8;
   const __bf16 *pal = pa + kTileElems;
   const long long step_elems = (long long)group * kPairElems;
@@ -125,7 +132,7 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
   struct AStep {
     bf16x8 hi[kSlots], lo[LO_L ? kSlots : 1];
   };
-  // loads past the last step re-read the last step (clamped index): the loop body has no
+  // loads past the last step are redirected (a select, not a branch): the loop body has no
   // branches, so the compiler's wait counts follow the order of issue exactly
   // the left operand is read exactly once: non-temporal loads stream it past the caches,
   // which keep the right operand that every row block re-reads
@@ -133,12 +140,14 @@ __global__ void __launch_bounds__(512, 1) k_gemm_bf16(
     return __builtin_bit_cast(bf16x8, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p)));
   };
   auto load_a = [&](AStep &a, long long st) {
-    st = min(st, nsteps - 1);
+    const bool in = st < nsteps;
+    const __bf16 *ph = in ? pa + st * step_elems : Rhi + lane * 8;
+    const __bf16 *pl = in ? pal + st * step_elems : Rhi + lane * 8;
 #pragma unroll
-    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(pa + st * step_elems + q * 512);
+    for (int q = 0; q < kSlots; ++q) a.hi[q] = ld_nt(ph + q * 512);
     if constexpr (LO_L) {
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pal + st * step_elems + q * 512);
+      for (int q = 0; q < kSlots; ++q) a.lo[q] = ld_nt(pl + q * 512);
     }
   };
   auto load_x = [&](XChunks &x, long long st) {
