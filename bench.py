@@ -35,17 +35,20 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # SIMD-clocks per lane, so at most 256 * 4 * 2.4e9 / (3/16 + 1/4) = 5.6e12 entries/s.
 RING_FLOPS_PER_ENTRY = 6
 RING_ENTRY_PEAK = 256 * 4 * 2.4e9 / (3.0 / 16.0 + 1.0 / 4.0)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# HBM traffic records (rocprofv3 FETCH_SIZE / WRITE_SIZE passes, copy-calibrated), one file per
+# workload, keyed by a hash of the sources that determine the counted kernels' device code.
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 
 
-# Sources that determine the device code of the dense forward-product kernel (the dominant
-# kernel of the dense workloads): HBM traffic counted for it stays valid while these and the
-# device compile flags are unchanged. (kernels.hpp only declares host launchers and constants
-# the kernel does not use.)
-DENSE_KERNEL_SOURCES = ("dense.hip", "device_common.hpp", "plsqr_internal.hpp")
+# Sources that determine the device code of each workload's dominant kernel: HBM traffic counted
+# for it stays valid while these and the device compile flags are unchanged. (kernels.hpp only
+# declares host launchers and constants the kernels do not use.)
+KERNEL_SOURCES = {"c2": ("dense.hip", "device_common.hpp", "plsqr_internal.hpp"),
+                  "c4": ("gemm_bf16.hip", "device_common.hpp", "plsqr_internal.hpp")}
 
 
-def kernel_source_hash(files=DENSE_KERNEL_SOURCES):
+def kernel_source_hash(files):
     """Hash of the sources and of the device compile flags that determine the kernel's code."""
     import importlib.util
     spec = importlib.util.spec_from_file_location(
@@ -57,6 +60,22 @@ def kernel_source_hash(files=DENSE_KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_1308_6634_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def traffic_for(workload, key):
+    """HBM bytes per launch of variant ``key`` from the workload's traffic record, or None when
+    there is none or the kernel's sources have changed since the counters were taken."""
+    fn = traffic_file(workload)
+    if not os.path.exists(fn):
+        return None
+    try:
+        tr = json.load(open(fn))
+        var = tr.get("variants", {}).get(str(key))
+        if var is None or tr.get("source_sha") != kernel_source_hash(tuple(tr["source_files"])):
+            return None
+        return var["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def workload(name):
@@ -135,25 +154,49 @@ def cpu_baseline(p, target_s=20.0):
                       f"host cores: {len(os.sched_getaffinity(0))}"}, K, S, f
 
 
-def _counter_per_dispatch(folder, counter, match):
-    """{kernel name: per-dispatch values} of one rocprofv3 counter, for kernels whose (short)
-    name satisfies match."""
+def _counter_rows(folder, counter):
+    """[(dispatch key, short kernel name, value)] of one rocprofv3 counter, in dispatch order."""
     import csv
     import glob
     vals = {}
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no counter_collection.csv under {folder}")
-    for fn in files:
+    for fn in sorted(files):
         with open(fn, newline="") as fh:
             for row in csv.DictReader(fh):
-                name = _short_kernel(row.get("Kernel_Name", ""))
-                if row.get("Counter_Name") != counter or not match(name):
+                if row.get("Counter_Name") != counter:
                     continue
-                key = (fn, row.get("Dispatch_Id") or row.get("Correlation_Id"))
-                d = vals.setdefault(name, {})
-                d[key] = d.get(key, 0.0) + float(row["Counter_Value"])
-    return {k: list(v.values()) for k, v in vals.items()}
+                did = row.get("Dispatch_Id") or row.get("Correlation_Id")
+                key = (fn, int(did) if did and did.isdigit() else did)
+                name = _short_kernel(row.get("Kernel_Name", ""))
+                old = vals.get(key, (name, 0.0))
+                vals[key] = (name, old[1] + float(row["Counter_Value"]))
+    return [(k, v[0], v[1]) for k, v in sorted(vals.items(), key=lambda kv: kv[0])]
+
+
+def _counter_per_dispatch(folder, counter, match):
+    """{kernel name: per-dispatch values} of one rocprofv3 counter, for kernels whose (short)
+    name satisfies match."""
+    out = {}
+    for _, name, v in _counter_rows(folder, counter):
+        if match(name):
+            out.setdefault(name, []).append(v)
+    return out
+
+
+def _sequence_sums(folder, counter, seq):
+    """Per occurrence of the consecutive dispatch sequence ``seq`` (exact short kernel names),
+    the counter summed over its dispatches."""
+    rows = _counter_rows(folder, counter)
+    sums, i = [], 0
+    while i + len(seq) <= len(rows):
+        if all(rows[i + k][1] == seq[k] for k in range(len(seq))):
+            sums.append(sum(rows[i + k][2] for k in range(len(seq))))
+            i += len(seq)
+        else:
+            i += 1
+    return sums
 
 
 def _short_kernel(full):
@@ -162,47 +205,60 @@ def _short_kernel(full):
     return s.split("::")[-1] if "::" in s.split("<")[0] else s
 
 
-def write_traffic(args, out=TRAFFIC_FILE):
-    """HBM bytes per launch of each template variant of one kernel (e.g. every k_gemv_rows<R>
-    the autotuner ran) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), each
-    scaled so that a plain 1 GiB device copy reads and writes 1 GiB."""
+def write_traffic(args, out=None):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch),
+    each scaled so that a plain 1 GiB device copy reads and writes 1 GiB. Either every template
+    variant of one kernel (--traffic-kernel, e.g. each k_gemv_rows<R> the autotuner ran), or one
+    sequence of consecutive dispatches that make up one product (--traffic-sequence, comma
+    separated exact names, recorded under --traffic-key)."""
     import re
-    if not args.traffic_kernel:
-        raise SystemExit("--write-traffic needs --traffic-kernel")
-    base = args.traffic_kernel.split("<")[0]
-
-    def is_kernel(k):
-        return k == base or k.startswith(base + "<")
-
     fdir, wdir, cfdir, cwdir = args.write_traffic
-    fetch = _counter_per_dispatch(fdir, "FETCH_SIZE", is_kernel)
-    write = _counter_per_dispatch(wdir, "WRITE_SIZE", is_kernel)
     cfetch = sum(_counter_per_dispatch(cfdir, "FETCH_SIZE", lambda k: "copyBuffer" in k).values(), [])
     cwrite = sum(_counter_per_dispatch(cwdir, "WRITE_SIZE", lambda k: "copyBuffer" in k).values(), [])
-    if not (fetch and write and cfetch and cwrite):
-        raise SystemExit("a counter pass holds no matching dispatch")
+    if not (cfetch and cwrite):
+        raise SystemExit("the copy calibration passes hold no copy dispatch")
     gib_kib = float(1 << 20)
     fscale = gib_kib / (sum(cfetch) / len(cfetch))
     wscale = gib_kib / (sum(cwrite) / len(cwrite))
+    groups = {}          # key -> (name, fetch values, write values)
+    if args.traffic_sequence:
+        seq = [x.strip() for x in args.traffic_sequence.split(";")]
+        key = args.traffic_key or "sequence"
+        groups[key] = (" + ".join(seq), _sequence_sums(fdir, "FETCH_SIZE", seq),
+                       _sequence_sums(wdir, "WRITE_SIZE", seq))
+        base = " + ".join(seq)
+    elif args.traffic_kernel:
+        base = args.traffic_kernel.split("<")[0]
+
+        def is_kernel(k):
+            return k == base or k.startswith(base + "<")
+
+        fetch = _counter_per_dispatch(fdir, "FETCH_SIZE", is_kernel)
+        write = _counter_per_dispatch(wdir, "WRITE_SIZE", is_kernel)
+        for name in sorted(set(fetch) & set(write)):
+            m = re.search(r"<(\d+)>", name)
+            groups[m.group(1) if m else name] = (name, fetch[name], write[name])
+    else:
+        raise SystemExit("--write-traffic needs --traffic-kernel or --traffic-sequence")
     variants = {}
-    for name in sorted(set(fetch) & set(write)):
-        f_kib = sum(fetch[name]) / len(fetch[name])
-        w_kib = sum(write[name]) / len(write[name])
+    for key, (name, fv, wv) in groups.items():
+        if not (fv and wv):
+            raise SystemExit(f"a counter pass holds no dispatch of {name}")
+        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
         fb, wb = f_kib * 1024 * fscale, w_kib * 1024 * wscale
-        m = re.search(r"<(\d+)>", name)
-        key = m.group(1) if m else name
-        variants[key] = {"kernel": name, "launches": len(fetch[name]),
+        variants[key] = {"kernel": name, "launches": len(fv),
                          "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
                          "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                          "bytes_per_launch": fb + wb}
-        print(f"{name}: {len(fetch[name])} launches; FETCH_SIZE {f_kib:.1f} KiB raw x {fscale:.5f}, "
+        print(f"{name}: {len(fv)} launches; FETCH_SIZE {f_kib:.1f} KiB raw x {fscale:.5f}, "
               f"WRITE_SIZE {w_kib:.1f} KiB raw x {wscale:.5f} -> {(fb + wb) / 1e9:.4f} GB per launch")
+    files = KERNEL_SOURCES[args.workload]
     rec = {"workload": args.workload, "kernel": base, "variants": variants,
-           "source_sha": kernel_source_hash(), "source_files": list(DENSE_KERNEL_SOURCES),
+           "source_sha": kernel_source_hash(files), "source_files": list(files),
            "copy_calibration": {"bytes": 1 << 30, "fetch_kib_raw": sum(cfetch) / len(cfetch),
                                 "write_kib_raw": sum(cwrite) / len(cwrite), "fetch_scale": fscale,
                                 "write_scale": wscale, "launches": len(cfetch)}}
-    with open(out, "w") as fh:
+    with open(out or traffic_file(args.workload), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
@@ -212,7 +268,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c1", "c4", "c5"])
+    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c1", "c4", "c5"])
     ap.add_argument("--latency-solves", type=int, default=20,
                     help="c1-c3: solves issued one at a time after the timed run for the p50/p99 "
                          "solve latency (0: skip)")
@@ -252,7 +308,14 @@ def main():
                     help="practical HBM ceiling: a 2 GiB device copy and a 4 GiB read-only sum "
                          "(library kernels of PyTorch), timed with events")
     ap.add_argument("--traffic-kernel", default=None,
-                    help="exact kernel name for --write-traffic, e.g. 'k_gemv_rows<2>'")
+                    help="kernel for --write-traffic: every template variant of it is recorded, "
+                         "e.g. 'k_gemv_rows'")
+    ap.add_argument("--traffic-sequence", default=None,
+                    help="for --write-traffic: ';'-separated exact short names of consecutive "
+                         "dispatches forming one product, e.g. 'k_pack_split;k_gemm_bf16<2, true, "
+                         "false>;k_fwd_reduce'")
+    ap.add_argument("--traffic-key", default=None,
+                    help="record key of --traffic-sequence (c4: forward_bf16_refined)")
     args = ap.parse_args()
     if args.write_traffic:
         return write_traffic(args)
@@ -347,15 +410,8 @@ def main():
                     "entry_frac": entries / avg_fwd_s / RING_ENTRY_PEAK,
                     "avg_launch_ms": avg_fwd_s * 1e3, "launches": int(fwd_n)}
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            var = tr.get("variants", {}).get(str(settings.get("tune_gemv_rows")))
-            if tr.get("source_sha") == kernel_source_hash() and tr.get("workload") == args.workload \
-                    and var is not None:
-                traffic = var["bytes_per_launch"]
-        except (OSError, ValueError):
-            traffic = None
+    if p.op_kind == "dense" and not args.matrix_free:
+        traffic = traffic_for(args.workload, settings.get("tune_gemv_rows"))
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; forward product avg "
           f"{avg_fwd_s * 1e3:.3f} ms, adjoint avg {adj_ms / max(adj_n, 1):.3f} ms",
           file=sys.stderr, flush=True)
@@ -482,49 +538,95 @@ def adaptive_run(args, eng, op, p, settings, g, f):
             "rule": "S4 eta=1.1, delta=noise norm, inner cap as configured; outer stop rtol=0 from k=3"}
 
 
+C4_A_BYTES_PER_VOXEL_ITER = {"bf16_refined": 1024, "bf16": 512}   # A_hi (+ A_lo) per product pair
+STENCIL_BYTES_PER_VOXEL_ITER = 75                                   # vectors, multigrid, update
+
+
+def c4_oracle_sample(probs, A, which=(0, 63), target_s=15.0):
+    """The FP64 oracle on instances of the batched family: its first outer iteration with S
+    inner iterations, S sized so that one instance takes about target_s seconds. Returns
+    (cpu_baseline record, S, {instance: f})."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import lagged, multigrid
+    from oracle.operators import Dense
+
+    p0 = probs[which[0]]
+    nx, ny, nz = p0.dims
+    shape = (nz, ny, nx)
+    op = Dense(A, shape)                       # one FP64 copy of A serves every sample (untimed)
+    sm = multigrid.Smoother(p0.smoother, p0.nu_pre, p0.nu_post, p0.omega)
+
+    def run(p, inner):
+        t0 = time.perf_counter()
+        f, _ = lagged.solve(shape, op, np.asarray(p.g, dtype=np.float64), p.reg, p.T, p.tau, p.eps,
+                            1, inner, p.levels, sm)
+        return time.perf_counter() - t0, f
+
+    t2, _ = run(p0, 2)
+    per_iter = max(t2 / 3.0, 1e-3)            # setup and initialisation cost about one step
+    S = int(min(p0.inner, max(4, round(target_s / per_iter) - 1)))
+    refs, times = {}, []
+    for i in which:
+        t, refs[i] = run(probs[i], S)
+        times.append(t)
+        print(f"[bench] oracle instance {i}: 1 x {S} in {t:.1f} s", file=sys.stderr, flush=True)
+    threads = [x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"]
+    n = nx * ny * nz
+    rec = {"value": n * S * len(which) / sum(times), "unit": "voxel-iter/s",
+           "cores": int(max(threads) if threads else 1), "kind": "oracle",
+           "sample": f"instances {', '.join(map(str, which))} one at a time, first outer iteration "
+                     f"with {S} inner iterations each (setup included), {sum(times):.1f} s, FP64 "
+                     f"NumPy/SciPy on the FP64 matrix, host cores: {len(os.sched_getaffinity(0))}"}
+    return rec, S, refs
+
+
 def bench_c4(args):
     """64 reconstructions of 64^3 sharing one 8192 x 262144 sensitivity, batched in lockstep
     with the dense products on MFMA (BF16 split products), against the same instances run
-    one at a time on the FP32 path."""
+    one at a time on the FP32 path; the FP64 oracle timed on a sample and compared with the
+    batched GPU result on the same sample."""
+    import dataclasses
     import numpy as np
     import torch
-    import gen
-    from gen.configs import c4_matrix
+    from gen.configs import c4_matrix, config_c4_batch
     from paper_1308_6634_amd import plsqr as P
     from paper_1308_6634_amd.engine import Engine, problem_struct
 
     B = 64
+    t_gen = time.perf_counter()
     A = c4_matrix(64)
-    probs = [gen.config_c4(i, A) for i in range(B)]
+    probs = config_c4_batch(A, B)
     p0 = probs[0]
     n, m = p0.n_x, A.shape[0]
+    print(f"[bench] c4 inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
     prec = P.PLSQR_PREC_BF16_REFINED if args.precision == "bf16_refined" else P.PLSQR_PREC_BF16
-    desc = (f"64 instances x 64^3, shared dense ring sensitivity {m}x{n} (8 source rings x 16, "
+    desc = (f"c4: 64 instances x 64^3, shared dense ring sensitivity {m}x{n} (8 source rings x 16, "
             f"4 detector rings x 16, mu=0.5), own ellipsoid phantom / noise / regulariser "
             f"(sTV 0.02 or PM-log 0.05), tau=20, 8 outer x 40 inner, 5-level Jacobi V(2,2); "
             f"products {args.precision} on MFMA")
-    print(f"[bench] workload c4: {desc}", file=sys.stderr, flush=True)
+    print(f"[bench] workload {desc}", file=sys.stderr, flush=True)
     eng = Engine(0)
     A_dev = torch.from_numpy(A).cuda()
-    del A
     op = eng.dense_operator(p0.dims, A_dev)
     gs = [torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32)).cuda() for p in probs]
     fs = [torch.zeros(n, device="cuda") for _ in probs]
-    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, precision=prec) for p in probs]
 
-    def run_batch():
+    def run_batch(pbs):
         ts = eng.submit_batch(op, pbs, gs, fs)
         res = [eng.wait(t) for t in ts]
         for st, _ in res:
             assert st == 0, P.plsqr_last_error(eng.handle)
         return res
 
+    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, precision=prec) for p in probs]
     for _ in range(args.warmup):
-        run_batch()
+        run_batch(pbs)
     print("[bench] warmup done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [run_batch() for _ in range(args.steps)]
+    results = [run_batch(pbs) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = B * n * p0.outer * p0.inner * args.steps / elapsed
@@ -537,6 +639,13 @@ def bench_c4(args):
     print(f"[bench] batched: {elapsed / args.steps * 1e3:.1f} ms per batch; forward product "
           f"{fwd_ms:.3f} ms, adjoint {adj_ms:.3f} ms", file=sys.stderr, flush=True)
 
+    # one more batch with every phase timed (not part of the timed steps)
+    ph = run_batch([problem_struct(p, flags=P.PLSQR_FLAG_TIME_PHASES, precision=prec)
+                    for p in probs])[0][1]
+    phases = {"setup_ms": ph.setup_ms, "forward_ms": ph.forward_ms, "adjoint_ms": ph.adjoint_ms,
+              "vcycle_ms": ph.vcycle_ms, "update_ms": ph.update_ms, "diag_ms": ph.diag_ms,
+              "device_ms": ph.device_ms, "inner_steps": int(ph.phase_launches)}
+
     # plain comparison: the same instances one at a time, FP32 products
     pl = [problem_struct(p, flags=0) for p in probs[:args.plain_sample]]
     torch.cuda.synchronize()
@@ -547,23 +656,45 @@ def bench_c4(args):
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t1) / len(pl) if pl else None
     plain_value = n * p0.outer * p0.inner / plain_s if pl else None
+    bpvi = C4_A_BYTES_PER_VOXEL_ITER[args.precision] + STENCIL_BYTES_PER_VOXEL_ITER
     out = {
         "metric": "voxel-LSQR-iters/s", "value": value, "unit": "voxel-iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"c4: {desc}", "instances": B, "n_x": n, "n_y": m,
-                   "outer": p0.outer, "inner": p0.inner, "precision": args.precision},
-        "roofline": {"bound": "hbm", "kernel": "forward product (pack + k_gemm_bf16 + reduce)",
-                     "achieved": fwd_bytes / (fwd_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": fwd_bytes / (fwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": fwd_bytes, "avg_launch_ms": fwd_ms,
-                     "mfma_tflops": fwd_flops / (fwd_ms / 1e3) / 1e12, "mfma_peak_tflops": 2500.0},
+        "config": {"workload": desc, "instances": B, "n_x": n, "n_y": m, "outer": p0.outer,
+                   "inner": p0.inner, "precision": args.precision + " products, fp32 vectors, "
+                   "fp64 scalars"},
+        "roofline": {"bound": "hbm", "kernel": "forward product (k_pack_split + k_gemm_bf16 + "
+                     "k_fwd_reduce)", "achieved": fwd_bytes / (fwd_ms / 1e3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fwd_bytes / (fwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic_for("c4", "forward_" + args.precision), "bytes_per_launch": fwd_bytes,
+                     "avg_launch_ms": fwd_ms, "adjoint_avg_launch_ms": adj_ms,
+                     "mfma_tflops": fwd_flops / (fwd_ms / 1e3) / 1e12, "mfma_peak_tflops": 2500.0,
+                     "whole_step": {"bytes_per_voxel_iter": bpvi,
+                                    "achieved_GBps": value * bpvi / 1e9,
+                                    "frac": value * bpvi / 1e9 / HBM_PEAK_GBS}},
+        "phases_ms_one_batch": phases,
         "plain_fp32_one_at_a_time": {"value": plain_value, "unit": "voxel-iter/s",
-                                     "sample": f"{len(pl)} of the {B} instances, FP32 products",
-                                     "s_per_instance": plain_s} if pl else None,
+                                     "sample": f"instances 0..{len(pl) - 1} of the {B}, FP32 "
+                                               f"products", "s_per_instance": plain_s}
+        if pl else None,
         "batched_over_plain": value / plain_value if pl else None,
     }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
+        cb, S, refs = c4_oracle_sample(probs, A)
+        out["cpu_baseline"] = cb
+        # the same sample on the GPU: the whole batch at 1 outer x S inner, same precision
+        run_batch([problem_struct(dataclasses.replace(p, outer=1, inner=S), precision=prec)
+                   for p in probs])
+        errs = {}
+        for i, f_ref in refs.items():
+            fg = fs[i].cpu().numpy().astype(np.float64).reshape(f_ref.shape)
+            errs[str(i)] = float(np.linalg.norm(fg - f_ref) / np.linalg.norm(f_ref))
+        out["parity_sample_rel_l2"] = max(errs.values())
+        out["parity_sample"] = {"instances": errs, "outer": 1, "inner": S, "bar": 5e-3}
     eng.close()
     print(json.dumps(out), flush=True)
 

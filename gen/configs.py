@@ -156,6 +156,38 @@ def config_c4(i, A, n=64, outer=8, inner=40):
                               smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8)
 
 
+def config_c4_batch(A, count=64, n=64, outer=8, inner=40, chunk=256):
+    """Instances 0..count-1 of the batched family, equal to ``config_c4(i, A)`` one by one
+    (same seeds and draw order: regulariser, phantom, then noise per instance), with the clean
+    data of all instances formed in one pass over A: each float64 row chunk of A multiplies the
+    matrix of all phantoms (the one-at-a-time recipe converts A once per instance)."""
+    rngs, meta, F = [], [], []
+    for i in range(count):
+        rng = np.random.default_rng(1000 + i)
+        if rng.uniform() < 0.5:
+            reg, T = "stv", 0.02
+        else:
+            reg, T = "pm_log", 0.05
+        f = phantoms.ellipsoids_3d(rng, n, count=5)
+        rngs.append(rng)
+        meta.append((reg, T, f))
+        F.append(f.ravel())
+    F = np.stack(F, axis=1)                                  # n^3 x count, float64
+    clean = np.empty((A.shape[0], count))
+    for r0 in range(0, A.shape[0], chunk):
+        clean[r0:r0 + chunk] = A[r0:r0 + chunk].astype(np.float64) @ F
+    ring = (*ops.ring_points(n, 8, 4), 0.5 * 64.0 / n)
+    out = []
+    for i, (rng, (reg, T, f)) in enumerate(zip(rngs, meta)):
+        g, sd, delta = ops.add_noise(rng, clean[:, i], 0.01)
+        nz, ny, nx = f.shape
+        out.append(Problem(name=f"c4_{i}", dims=(nx, ny, nz), f_true=f, g=g, op_kind="dense", A=A,
+                           noise_sd=sd, delta=delta, extra={"ring": ring}, reg=reg, T=T, tau=20.0,
+                           eps=1e-6, outer=outer, inner=inner, levels=auto_levels((n, n, n)),
+                           smoother="jacobi", nu_pre=2, nu_post=2, omega=0.8))
+    return out
+
+
 C5_SIZES = (32, 48, 64, 96, 128)
 
 

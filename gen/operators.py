@@ -105,7 +105,7 @@ def dense_sensitivity(n, mu=0.5, n_src_rings=4, n_det_rings=4, per_ring=16, thre
     return A
 
 
-def _add_noise(rng, clean, noise_frac):
+def add_noise(rng, clean, noise_frac):
     """Returns (float32 data, noise standard deviation, Euclidean norm of the drawn noise)."""
     sd = noise_frac * float(np.max(np.abs(clean)))
     e = rng.normal(0.0, sd, size=clean.shape)
@@ -120,7 +120,7 @@ def blur_data(rng, f_true, taps, noise_frac):
     for ax in range(3):
         if clean.shape[ax] > 1:
             clean = ndimage.correlate1d(clean, w, axis=ax, mode="constant", cval=0.0)
-    return _add_noise(rng, clean, noise_frac)
+    return add_noise(rng, clean, noise_frac)
 
 
 def dense_data(rng, A, f_true, noise_frac, chunk=512):
@@ -129,7 +129,7 @@ def dense_data(rng, A, f_true, noise_frac, chunk=512):
     clean = np.empty(A.shape[0])
     for r0 in range(0, A.shape[0], chunk):
         clean[r0:r0 + chunk] = A[r0:r0 + chunk].astype(np.float64) @ x
-    return _add_noise(rng, clean, noise_frac)
+    return add_noise(rng, clean, noise_frac)
 
 
 def radius_for_sigma(sigma):

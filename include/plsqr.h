@@ -81,13 +81,19 @@ enum {
                                          Section 3.4: MLSQR ends after the first step i with
                                          ||g - A f_i|| <= eta * delta; `inner` stays the cap
                                          on steps per outer iteration (Section 4.1) */
-  PLSQR_FLAG_STOP_OUTER = 1u << 3     /* outer stop of Algorithm 3 (step 5): after outer step
+  PLSQR_FLAG_STOP_OUTER = 1u << 3,    /* outer stop of Algorithm 3 (step 5): after outer step
                                          k >= outer_min, stop when
                                          R(f^k) - R(f^{k-1}) >= -outer_rtol * R(f^{k-1}),
                                          i.e. R no longer falls by more than the fraction
                                          outer_rtol (Section 4.3 uses 0.15; Section 5.3 stops
                                          once R stops decreasing, outer_rtol = 0); the result
                                          is f^k, `outer` stays the cap */
+  PLSQR_FLAG_TIME_PHASES = 1u << 4    /* time every phase of the method with HIP events on the
+                                         engine stream (implies PLSQR_FLAG_TIME_PRODUCTS): setup
+                                         (a1-a3), products, priorconditioner V-cycles, updates and
+                                         per-outer diagnostics; totals in plsqr_result. The events
+                                         add a few microseconds per phase. A serving engine
+                                         records no phase times. */
 };
 
 #define PLSQR_MAX_LEVELS 12
@@ -209,6 +215,22 @@ typedef struct {
   double adjoint_ms;                  /* same for the adjoint products (A^T u) */
   int64_t adjoint_launches;
   int64_t workspace_bytes;            /* device memory the request held */
+  /* with PLSQR_FLAG_TIME_PHASES: summed device time of each phase (events around each phase
+     on the engine stream; the launch gaps between phases are not counted, so the phases and
+     the two product totals above add up to at most device_ms):
+       setup_ms   diffusivity and penalty of the previous iterate, multigrid hierarchy and
+                  coarsest factor, MLSQR initialisation (eq. (1.12)-(1.13), Section 4.2,
+                  Algorithm 2 initialisation), once per outer step
+       vcycle_ms  the inner steps' priorconditioner solves v = B p (one V-cycle, Section 4.2)
+                  with the reduction alpha = sqrt(v.p) and the damping and Givens rotations
+       update_ms  the inner steps' updates of f and w (and the S4 residual recurrence)
+       diag_ms    the per-outer residual ||g - A f^k|| and penalty R(f^k), and the final copy
+       phase_launches  inner steps timed */
+  double setup_ms;
+  double vcycle_ms;
+  double update_ms;
+  double diag_ms;
+  int64_t phase_launches;
 } plsqr_result;
 
 /* Create an engine on HIP device `device`, with at most `hbm_budget_bytes` of

@@ -5,6 +5,7 @@ by the ROCm clang; the shared object is linked by hipcc. Usage:
 ``python -m paper_1308_6634_amd.build`` (or ``build()`` from Python).
 """
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -47,15 +48,20 @@ def build(verbose=True):
         clang = shutil.which("g++")
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", os.path.join(ROCM, "include")]
-    objs = []
+    jobs = []
     for src in KERNEL_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, "-c", *DEVICE_FLAGS, *inc, os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((obj, [hipcc, "-c", *DEVICE_FLAGS, *inc, os.path.join(CSRC, src), "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([clang, "-x", "c++", "-c", *HOST_FLAGS, *inc, os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((obj, [clang, "-x", "c++", "-c", *HOST_FLAGS, *inc, os.path.join(CSRC, src),
+                           "-o", obj]))
+    # the translation units are independent: compile them side by side
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "8"))))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        for fut in [ex.submit(_run, cmd, verbose) for _, cmd in jobs]:
+            fut.result()
+    objs = [obj for obj, _ in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lpthread"], verbose)

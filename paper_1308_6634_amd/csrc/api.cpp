@@ -230,7 +230,8 @@ void release_group(plsqr_engine *eng, Group &G) {
   if (G.ev_start) hipEventDestroy(G.ev_start);
   if (G.ev_end) hipEventDestroy(G.ev_end);
   G.ev_start = G.ev_end = nullptr;
-  for (auto *lst : {&G.fwd_events, &G.adj_events}) {
+  for (auto *lst : {&G.fwd_events, &G.adj_events, &G.setup_events, &G.vcycle_events,
+                    &G.update_events, &G.diag_events}) {
     for (auto &e : *lst) {
       hipEventDestroy(e.first);
       hipEventDestroy(e.second);
@@ -304,6 +305,12 @@ int start_group_impl(plsqr_engine *eng, Group &G) {
                          eng->stream));
   BatchView bv{G.d_descs, B, &r0.host, &r0.lay, G.timed ? &G.fwd_events : nullptr,
                G.timed ? &G.adj_events : nullptr, G.use_gemm ? &G.gemm : nullptr};
+  if (G.phases) {
+    bv.setup_events = &G.setup_events;
+    bv.vcycle_events = &G.vcycle_events;
+    bv.update_events = &G.update_events;
+    bv.diag_events = &G.diag_events;
+  }
   if (!(r0.pb.flags & PLSQR_FLAG_NO_GRAPHS)) G.graphs = std::make_unique<GraphCache>();
   enqueue_whole_solve(eng->stream, bv, r0.pb.outer, r0.pb.inner, G.graphs.get());
   HIP_TRY(hipGetLastError());
@@ -385,6 +392,13 @@ void reap(plsqr_engine *eng, Group &G) {
     res.adjoint_ms = adj;
     res.adjoint_launches = (int64_t)G.adj_events.size();
     res.workspace_bytes = (int64_t)r.lay.total;
+    if (G.phases) {
+      res.setup_ms = total_ms(G.setup_events);
+      res.vcycle_ms = total_ms(G.vcycle_events);
+      res.update_ms = total_ms(G.update_events);
+      res.diag_ms = total_ms(G.diag_events);
+      res.phase_launches = (int64_t)G.vcycle_events.size();
+    }
     r.t_done = now;
     res.submit_to_done_ms = r.t_done - r.t_submit;
     r.status = res.status;
@@ -449,7 +463,8 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
   G->id = eng->next_group++;
   G->op_id = op_id;
   G->precision = prec;
-  G->timed = (probs[0].flags & PLSQR_FLAG_TIME_PRODUCTS) != 0;
+  G->phases = (probs[0].flags & PLSQR_FLAG_TIME_PHASES) != 0;
+  G->timed = G->phases || (probs[0].flags & PLSQR_FLAG_TIME_PRODUCTS) != 0;
   const double t = now_ms();
   for (int b = 0; b < count; ++b) {
     auto r = std::make_unique<Request>();

@@ -529,46 +529,99 @@ static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
   quiet.prod_events = nullptr;
   quiet.adj_events = nullptr;
   const bool timed = bv.prod_events != nullptr;
-  hipGraphExec_t ex;
-  if (timed) {
-    ex = capture_graph(gc.cap, [&](hipStream_t s) {
-      const int np = enqueue_vcycle(s, quiet);
-      launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
-      launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
-      enqueue_s4(s, quiet);
-      if (H.n_tau > 0) launch_basis_store(s, quiet.d_descs, quiet.B, H.n);
-    });
+  auto vcycle_part = [&](hipStream_t s) {
+    const int np = enqueue_vcycle(s, quiet);
+    launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
+  };
+  auto update_part = [&](hipStream_t s) {
+    launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
+    enqueue_s4(s, quiet);
+    if (H.n_tau > 0) launch_basis_store(s, quiet.d_descs, quiet.B, H.n);
+  };
+  std::vector<hipGraphExec_t> ex;
+  if (bv.vcycle_events) {
+    // phases timed: the V-cycle part and the update part replay as two graphs
+    ex.push_back(capture_graph(gc.cap, vcycle_part));
+    ex.push_back(capture_graph(gc.cap, update_part));
+  } else if (timed) {
+    ex.push_back(capture_graph(gc.cap, [&](hipStream_t s) {
+      vcycle_part(s);
+      update_part(s);
+    }));
   } else {
-    ex = capture_graph(gc.cap, [&](hipStream_t s) { enqueue_inner(s, quiet); });
+    ex.push_back(capture_graph(gc.cap, [&](hipStream_t s) { enqueue_inner(s, quiet); }));
   }
-  if (!ex) return false;
-  gc.execs.push_back(ex);
+  for (hipGraphExec_t e : ex)
+    if (!e) {
+      for (hipGraphExec_t f : ex)
+        if (f) hipGraphExecDestroy(f);
+      return false;
+    }
+  gc.execs = ex;
   return true;
+}
+
+// Events around one phase when its list is given.
+template <class F>
+static void timed_phase(hipStream_t st, EventList *ev, F body) {
+  hipEvent_t a = nullptr;
+  time_begin(st, ev, &a);
+  body();
+  time_end(st, ev, a);
 }
 
 void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inner,
                          GraphCache *graphs) {
   const bool use_graphs = graphs && prepare_inner_graphs(bv, *graphs);
   const bool timed = bv.prod_events != nullptr;
-  enqueue_request_begin(st, bv);
+  const bool phases = bv.vcycle_events != nullptr;
+  timed_phase(st, bv.setup_events, [&] { enqueue_request_begin(st, bv); });
   for (int k = 1; k <= outer; ++k) {
-    enqueue_outer_setup(st, bv);
-    enqueue_mlsqr_init(st, bv);
+    timed_phase(st, bv.setup_events, [&] {
+      enqueue_outer_setup(st, bv);
+      enqueue_mlsqr_init(st, bv);
+    });
     for (int i = 0; i < inner; ++i) {
-      if (!use_graphs) {
-        enqueue_inner(st, bv);
-      } else if (!timed) {
+      if (!timed) {
+        if (use_graphs) hipGraphLaunch(graphs->execs[0], st);
+        else enqueue_inner(st, bv);
+        continue;
+      }
+      const int np = enqueue_forward(st, bv, V_V, EPI_FWD);
+      launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
+      enqueue_adjoint(st, bv, EPI_ADJ);
+      const InstDesc &H = *bv.h;
+      if (phases) {
+        timed_phase(st, bv.vcycle_events, [&] {
+          if (use_graphs) {
+            hipGraphLaunch(graphs->execs[0], st);
+          } else {
+            const int nq = enqueue_vcycle(st, bv);
+            launch_finalize(st, bv.d_descs, bv.B, nq, FIN_ALPHA);
+          }
+        });
+        timed_phase(st, bv.update_events, [&] {
+          if (use_graphs) {
+            hipGraphLaunch(graphs->execs[1], st);
+          } else {
+            launch_update_fw(st, bv.d_descs, bv.B, H.n);
+            enqueue_s4(st, bv);
+            if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
+          }
+        });
+      } else if (use_graphs) {
         hipGraphLaunch(graphs->execs[0], st);
       } else {
-        const int np = enqueue_forward(st, bv, V_V, EPI_FWD);
-        launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
-        enqueue_adjoint(st, bv, EPI_ADJ);
-        hipGraphLaunch(graphs->execs[0], st);
+        const int nq = enqueue_vcycle(st, bv);
+        launch_finalize(st, bv.d_descs, bv.B, nq, FIN_ALPHA);
+        launch_update_fw(st, bv.d_descs, bv.B, H.n);
+        enqueue_s4(st, bv);
+        if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
       }
     }
-    enqueue_outer_end(st, bv);
+    timed_phase(st, bv.diag_events, [&] { enqueue_outer_end(st, bv); });
   }
-  enqueue_request_end(st, bv);
+  timed_phase(st, bv.diag_events, [&] { enqueue_request_end(st, bv); });
 }
 
 }  // namespace plsqr

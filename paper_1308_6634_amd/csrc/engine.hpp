@@ -119,7 +119,10 @@ struct Group {
   bool use_gemm = false;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   EventList fwd_events, adj_events;
+  // phase timing (PLSQR_FLAG_TIME_PHASES): setup, V-cycle, update and diagnostics phases
+  EventList setup_events, vcycle_events, update_events, diag_events;
   bool timed = false;
+  bool phases = false;
   std::unique_ptr<GraphCache> graphs;      // captured inner iteration (null: eager launches)
 };
 
@@ -132,6 +135,12 @@ struct BatchView {
   EventList *prod_events;     // optional timing (forward products)
   EventList *adj_events;      // optional timing (adjoint products)
   const GemmArgs *gemm;       // batched MFMA products, or null
+  // optional phase timing: events around the setup (a1-a3), inner V-cycle (with the alpha
+  // reduction and rotations), inner update and per-outer diagnostics phases
+  EventList *setup_events = nullptr;
+  EventList *vcycle_events = nullptr;
+  EventList *update_events = nullptr;
+  EventList *diag_events = nullptr;
 };
 
 // Solve driver (same sequence for one instance or a lockstep batch).

@@ -39,6 +39,7 @@ PLSQR_FLAG_TIME_PRODUCTS = 1
 PLSQR_FLAG_NO_GRAPHS = 2
 PLSQR_FLAG_STOP_S4 = 4
 PLSQR_FLAG_STOP_OUTER = 8
+PLSQR_FLAG_TIME_PHASES = 16
 PLSQR_MAX_LEVELS = 12
 PLSQR_MAX_OUTER = 64
 PLSQR_MAX_RADIUS = 16
@@ -88,7 +89,10 @@ class plsqr_result(ctypes.Structure):
                 ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("forward_ms", ctypes.c_double), ("forward_launches", ctypes.c_int64),
                 ("adjoint_ms", ctypes.c_double), ("adjoint_launches", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64),
+                ("setup_ms", ctypes.c_double), ("vcycle_ms", ctypes.c_double),
+                ("update_ms", ctypes.c_double), ("diag_ms", ctypes.c_double),
+                ("phase_launches", ctypes.c_int64)]
 
 
 class PlsqrError(RuntimeError):

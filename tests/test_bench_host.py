@@ -41,7 +41,8 @@ def test_write_traffic_scales_by_copy(tmp_path):
     _csv(tmp_path / "cf", [(1, cp, "FETCH_SIZE", 524288.0), (2, cp, "FETCH_SIZE", 524288.0)])
     _csv(tmp_path / "cw", [(1, cp, "WRITE_SIZE", 1048576.0)])
     args = argparse.Namespace(write_traffic=[str(tmp_path / d) for d in ("f", "w", "cf", "cw")],
-                              traffic_kernel="k_gemv_rows", workload="c2")
+                              traffic_kernel="k_gemv_rows", traffic_sequence=None,
+                              traffic_key=None, workload="c2")
     out = tmp_path / "traffic.json"
     bench.write_traffic(args, out=str(out))
     rec = json.load(open(out))
@@ -53,7 +54,32 @@ def test_write_traffic_scales_by_copy(tmp_path):
     assert v2["fetch_bytes_per_launch"] == pytest.approx(1100.0 * 1024 * 2.0)
     assert v2["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
     assert v4["bytes_per_launch"] == pytest.approx(3000.0 * 1024 * 2.0 + 8.0 * 1024)
-    assert rec["source_sha"] == bench.kernel_source_hash()
+    assert rec["source_sha"] == bench.kernel_source_hash(bench.KERNEL_SOURCES["c2"])
+
+
+def test_write_traffic_sums_a_dispatch_sequence(tmp_path):
+    """The c4 forward product is three consecutive dispatches (pack, GEMM, reduce); the adjoint
+    reuses the pack kernel before another GEMM variant, which must not be counted."""
+    pk = "void plsqr::k_pack_split(plsqr::InstDesc* const*, int, int, long long)"
+    gf = "void plsqr::k_gemm_bf16<2, true, false>(plsqr::GemmArgs)"
+    ga = "void plsqr::k_gemm_bf16<2, true, true>(plsqr::GemmArgs)"
+    rd = "void plsqr::k_fwd_reduce(plsqr::InstDesc* const*, float const*, int)"
+    seq = [(pk, 5.0), (gf, 100.0), (rd, 2.0), (pk, 7.0), (ga, 300.0)] * 2
+    _csv(tmp_path / "f", [(i + 1, k, "FETCH_SIZE", v) for i, (k, v) in enumerate(seq)])
+    _csv(tmp_path / "w", [(i + 1, k, "WRITE_SIZE", v / 10) for i, (k, v) in enumerate(seq)])
+    cp = "__amd_rocclr_copyBuffer"
+    _csv(tmp_path / "cf", [(1, cp, "FETCH_SIZE", 1048576.0)])
+    _csv(tmp_path / "cw", [(1, cp, "WRITE_SIZE", 1048576.0)])
+    args = argparse.Namespace(write_traffic=[str(tmp_path / d) for d in ("f", "w", "cf", "cw")],
+                              traffic_kernel=None,
+                              traffic_sequence="k_pack_split;k_gemm_bf16<2, true, false>;k_fwd_reduce",
+                              traffic_key="forward_bf16_refined", workload="c4")
+    out = tmp_path / "traffic_c4.json"
+    bench.write_traffic(args, out=str(out))
+    v = json.load(open(out))["variants"]["forward_bf16_refined"]
+    assert v["launches"] == 2
+    assert v["fetch_bytes_per_launch"] == pytest.approx(107.0 * 1024)
+    assert v["write_bytes_per_launch"] == pytest.approx(10.7 * 1024)
 
 
 def test_dominant_bytes():

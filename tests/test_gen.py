@@ -75,3 +75,18 @@ def test_c5_requests_and_arrivals():
     r = gen.configs.c5_request(3, sizes=(32,))
     assert r.dims == (32, 32, 32) and r.levels == 4
     assert r.radius == math.ceil(3 * r.extra["sigma"]) and 1.5 <= r.extra["sigma"] <= 3.5
+
+
+def test_c4_batch_generator_equals_one_at_a_time():
+    """The batched family's generator that forms every instance's clean data in one pass over A
+    gives the same instances as the one-at-a-time recipe (same seeds and draw order)."""
+    from gen import operators as ops
+    from gen.configs import config_c4, config_c4_batch
+    A = ops.dense_sensitivity(8, mu=4.0, n_src_rings=8, n_det_rings=4)
+    one = [config_c4(i, A, n=8) for i in range(6)]
+    many = config_c4_batch(A, 6, n=8)
+    for a, b in zip(one, many):
+        assert (a.reg, a.T, a.tau, a.levels) == (b.reg, b.T, b.tau, b.levels)
+        np.testing.assert_array_equal(a.f_true, b.f_true)
+        np.testing.assert_array_equal(a.g, b.g)
+        assert a.delta == pytest.approx(b.delta, rel=1e-12)

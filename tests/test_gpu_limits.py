@@ -27,6 +27,7 @@ import pytest
 
 import gen
 from oracle import lagged, multigrid
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +59,8 @@ def _check(p, engine, matrix_free=False):
     _say(f"[limits] {p.name} dims={p.dims} levels={p.levels} outer={p.outer} inner={p.inner}")
     f, res = solve(p, engine=engine, matrix_free=matrix_free)
     f_ref, rec = lagged.solve_problem(p)
-    err = _rel(f, f_ref)
+    err = assert_parity(f, f_ref, TOL, p.name)
     _say(f"[limits] {p.name}: rel L2 vs oracle {err:.3e}")
-    assert err <= TOL
     assert res.outer_done == p.outer
     for k, r in enumerate(rec):
         assert abs(res.resid[k] - r["resid"]) <= TOL * r["resid"]
@@ -137,6 +137,5 @@ def test_most_dampings(engine):
     refs, _ = lagged.solve_taus(shape, op_ref, np.asarray(p.g, dtype=np.float64), p.reg, p.T,
                                 p.tau, p.eps, p.outer, p.inner, p.levels, sm, taus)
     ftn = ft.cpu().numpy()
-    errs = [_rel(ftn[t], refs[t]) for t in range(64)]
+    errs = [assert_parity(ftn[t], refs[t], TOL, f"tau {t}") for t in range(64)]
     _say(f"[limits] 64 dampings: max rel L2 vs oracle {max(errs):.3e}")
-    assert max(errs) <= TOL

@@ -23,6 +23,7 @@ import pytest
 
 import gen
 from oracle import lagged
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -86,8 +87,7 @@ def _compare(p, f_gpu, res, f_ref, rec, tol=TOL):
          f"(oracle {[r['inner_done'] for r in rec]}), rel L2 = {err:.3e}")
     assert res.outer_done == len(rec)
     assert counts == [r["inner_done"] for r in rec]
-    assert np.all(np.isfinite(f_gpu))
-    assert err <= tol, err
+    assert_parity(f_gpu, f_ref, tol, p.name)
     for k, r in enumerate(rec):
         assert abs(res.resid[k] - r["resid"]) <= tol * r["resid"]
         assert abs(res.penalty[k] - r["penalty"]) <= tol * max(abs(r["penalty"]), 1e-30)

@@ -269,3 +269,45 @@ def test_method_reduces_error_and_penalty_on_small_tv_problem():
         errs.append(np.linalg.norm(f - p.f_true) / np.linalg.norm(p.f_true))
     assert errs[1] < errs[0]
     assert rec[-1]["penalty"] < rec[1]["penalty"]
+
+
+@pytest.mark.parametrize("reg,T,tau,outer", [("stv", 0.05, 0.2, 60), ("pm_log", 0.3, 0.1, 120)])
+def test_lagged_diffusivity_fixed_point_is_stationary(reg, T, tau, outer):
+    """Section 4.1: the outer loop is the lagged-diffusivity fixed-point iteration for the
+    stationarity condition (4.1)/(4.2) of the MAP functional. With an exact prior solve (one
+    multigrid level: the Cholesky solve of M) and converged inner solves, each outer step
+    returns argmin ||g - A f||^2 + tau f^T M_{f^{k-1}} f, so a fixed point f* satisfies
+    A^T (A f* - g) + tau (G^T diag(kappa(|grad f*|)) G + eps I) f* = 0, which is the gradient of
+        J(f) = 1/2 ||g - A f||^2 + tau R(f) + 1/2 tau eps ||f||^2
+    (dR/df = G^T diag(r'(t)/t) G f). The gradient is taken here by central differences of J
+    (no diffusivity formula enters), so a kappa formed from the wrong iterate or the wrong
+    formula leaves a non-zero gradient at the limit. The first iterate (kappa from f^0 = 0) is
+    far from stationary, which shows the check has teeth."""
+    p = gen.small_blur_case(3, (7, 6, 1), sigma=1.2, radius=2, reg=reg, T=T, tau=tau, levels=1,
+                            eps=1e-3)
+    shape = (1, 6, 7)
+    op = Blur(p.taps, shape)
+    g = p.g.astype(float).reshape(shape)
+    sm = multigrid.Smoother("jacobi", 2, 2, 0.8)
+    f, _ = lagged.solve(shape, op, g, reg, T, tau, p.eps, outer, 150, 1, sm)
+    f_next, _ = lagged.solve(shape, op, g, reg, T, tau, p.eps, outer + 1, 150, 1, sm)
+    assert np.linalg.norm(f_next - f) <= 1e-8 * np.linalg.norm(f)      # the iteration has settled
+
+    def J(x):
+        x = x.reshape(shape)
+        return (0.5 * np.sum((g - op.apply(x)) ** 2) + tau * grid.penalty(x, reg, T)
+                + 0.5 * tau * p.eps * np.sum(x * x))
+
+    def grad_J(x, h=1e-6):
+        x = x.ravel()
+        out = np.zeros(x.size)
+        for j in range(x.size):
+            e = np.zeros(x.size)
+            e[j] = h
+            out[j] = (J(x + e) - J(x - e)) / (2.0 * h)
+        return out
+
+    scale = np.linalg.norm(op.apply_T(g))
+    assert np.linalg.norm(grad_J(f_next)) <= 1e-7 * scale
+    f1, _ = lagged.solve(shape, op, g, reg, T, tau, p.eps, 1, 150, 1, sm)
+    assert np.linalg.norm(grad_J(f1)) >= 1e-3 * scale
