@@ -100,6 +100,7 @@ enum {
 #define PLSQR_MAX_OUTER 64
 #define PLSQR_MAX_RADIUS 16
 #define PLSQR_MAX_COARSE 512     /* largest coarsest-grid size solved by dense Cholesky */
+#define PLSQR_STATIC_SCRATCH_BYTES (64u << 20)   /* device scratch of plsqr_solve_static */
 
 typedef struct plsqr_engine plsqr_engine;   /* opaque; owns all internal device state */
 
@@ -274,6 +275,30 @@ int plsqr_solve_taus(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob
  * ticket of request i; every ticket completes when the whole batch does. */
 int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const plsqr_problem *probs,
                       const float *const *g_devs, float *const *f_devs, uint64_t *tickets);
+
+/* For callers that cannot allocate memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. One reconstruction as plsqr_solve runs it
+ * (FP32, fixed or adaptive counts), with every internal buffer of the request (descriptor,
+ * FP64 scalars and per-outer records, Krylov vectors, multigrid levels, reduction partials)
+ * taken from a static device array of PLSQR_STATIC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on each GPU until the process ends. The call makes no device or pinned allocation,
+ * no event and no graph: its kernels are launched eagerly on the engine's stream, the
+ * descriptor travels as a kernel argument, and the records are cleared by a kernel.
+ *  - A problem whose workspace (plsqr_workspace_bytes) exceeds the array fails with
+ *    PLSQR_E_BUDGET and nothing is enqueued; so do timing flags (PLSQR_FLAG_TIME_*), a
+ *    precision other than PLSQR_PREC_FP32 (PLSQR_E_INVALID) and a serving engine.
+ *  - out == NULL: returns PLSQR_OK once the work is enqueued (usable under stream capture);
+ *    f_dev is written when the stream reaches the end, unless the request fails.
+ *    out != NULL: waits for the engine's stream, fills *out (status, counts, per-outer
+ *    ||g - A f^k|| and R(f^k), workspace_bytes; no timings) and returns the request's
+ *    status.
+ *  - Every call on a GPU shares that GPU's array, which keeps the last call's contents:
+ *    calls that overlap on one GPU (other engines or streams, other host threads) race and
+ *    corrupt each other; calls in one stream order are safe. Requests submitted through the
+ *    other entry points use their own memory and do not touch the array.
+ *  g_dev, f_dev are device pointers as for plsqr_solve. */
+int plsqr_solve_static(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob,
+                       const float *g_dev, float *f_dev, plsqr_result *out);
 
 /* Non-blocking completion check: PLSQR_PENDING while the request runs; otherwise the
  * request's status (PLSQR_OK or an error), with *out filled (out may be NULL). A

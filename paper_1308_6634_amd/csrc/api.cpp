@@ -857,6 +857,13 @@ int plsqr_create(plsqr_engine **out, int device, uint64_t hbm_budget_bytes, void
     return set_error(PLSQR_E_HIP, "no HIP device available");
   if (device < 0 || device >= ndev) return set_error(PLSQR_E_INVALID, "device index out of range");
   if (flags & ~(uint32_t)PLSQR_ENGINE_SERVE) return set_error(PLSQR_E_INVALID, "unknown engine flags");
+  {
+    // the no-allocation entry point's scratch on this device: its address is looked up once
+    DeviceGuard dg(device);
+    std::string why;
+    const int rc = resolve_scratch(device, &why);
+    if (rc != PLSQR_OK) return set_error(rc, why);
+  }
   auto *e = new plsqr_engine();
   e->device = device;
   e->stream = static_cast<hipStream_t>(hip_stream);
@@ -986,6 +993,60 @@ int plsqr_solve_batch(plsqr_engine *eng, int32_t op_id, int32_t count, const pls
   std::lock_guard<std::mutex> lk(eng->mu);
   DeviceGuard dg(eng->device);
   return submit_group(eng, op_id, count, probs, g_devs, f_devs, tickets);
+}
+
+int plsqr_solve_static(plsqr_engine *eng, int32_t op_id, const plsqr_problem *prob,
+                       const float *g_dev, float *f_dev, plsqr_result *out) {
+  if (!eng || !prob) return set_error(PLSQR_E_INVALID, "null argument");
+  if (!g_dev || !f_dev) return set_error(PLSQR_E_INVALID, "g_dev and f_dev must be device pointers");
+  if (eng->flags & PLSQR_ENGINE_SERVE)
+    return set_error(PLSQR_E_INVALID, "plsqr_solve_static runs on a plain engine, not a serving one");
+  if (prob->precision != PLSQR_PREC_FP32)
+    return set_error(PLSQR_E_INVALID, "plsqr_solve_static runs in PLSQR_PREC_FP32");
+  if (prob->flags & (PLSQR_FLAG_TIME_PRODUCTS | PLSQR_FLAG_TIME_PHASES))
+    return set_error(PLSQR_E_INVALID, "plsqr_solve_static records no timings (they need events)");
+  std::lock_guard<std::mutex> lk(eng->mu);
+  DeviceGuard dg(eng->device);
+  const Operator *op = (op_id >= 0 && op_id < (int)eng->ops.size()) ? &eng->ops[op_id] : nullptr;
+  int levels = 0;
+  std::string why;
+  const int rc = validate(*prob, op, &levels, &why);
+  if (rc != PLSQR_OK) return set_error(rc, why);
+  Request r;
+  r.pb = *prob;
+  r.g = g_dev;
+  r.f_out = f_dev;
+  r.lay = make_layout(*prob, op->op.n_y, levels, op->op.kind);
+  if (r.lay.total > (size_t)PLSQR_STATIC_SCRATCH_BYTES)
+    return set_error(PLSQR_E_BUDGET, "the request needs " + std::to_string(r.lay.total) +
+                                         " bytes of workspace, more than the " +
+                                         std::to_string((size_t)PLSQR_STATIC_SCRATCH_BYTES) +
+                                         "-byte static scratch of plsqr_solve_static");
+  r.ws = static_cast<char *>(scratch_ptr(eng->device));
+  if (!r.ws) return set_error(PLSQR_E_HIP, "the static scratch of this device was not resolved");
+  fill_desc(eng, r, *op);
+  InstDesc *d_desc = reinterpret_cast<InstDesc *>(r.ws + r.lay.desc);
+  InstDesc **d_ptrs = reinterpret_cast<InstDesc **>(r.ws + r.lay.descptr);
+  const int n_rec = (prob->outer + 1) * DG_COUNT;
+  launch_static_setup(eng->stream, r.host, d_desc, d_ptrs, reinterpret_cast<double *>(r.ws + r.lay.diag),
+                      n_rec);
+  BatchView bv{d_ptrs, 1, &r.host, &r.lay, nullptr, nullptr, nullptr};
+  enqueue_whole_solve(eng->stream, bv, prob->outer, prob->inner, nullptr);
+  HIP_TRY(hipGetLastError());
+  if (!out) return PLSQR_OK;
+  HIP_TRY(hipStreamSynchronize(eng->stream));
+  double sc[SC_COUNT];
+  double dg_rec[(PLSQR_MAX_OUTER + 1) * DG_COUNT];
+  HIP_TRY(hipMemcpy(sc, r.ws + r.lay.sc, sizeof(sc), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(dg_rec, r.ws + r.lay.diag, (size_t)n_rec * sizeof(double), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  fill_records(r, sc, dg_rec, *out);
+  out->workspace_bytes = (int64_t)r.lay.total;
+  if (out->status != PLSQR_OK)
+    return set_error(out->status, out->status == PLSQR_E_NOT_SPD ? "preconditioner not positive definite"
+                                  : out->status == PLSQR_E_NONFINITE ? "non-finite value in the Krylov scalars"
+                                                                     : "request failed");
+  return PLSQR_OK;
 }
 
 int plsqr_poll(plsqr_engine *eng, uint64_t ticket, plsqr_result *out) {

@@ -155,6 +155,15 @@ void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inn
 
 double now_ms();
 
+// Static scratch of the no-allocation entry point (static_scratch.hip): resolve_scratch looks
+// up the array's device address on `device` (which must be current) once per device;
+// scratch_ptr returns it (null before). launch_static_setup writes a request's descriptor and
+// pointer array into it and clears the per-outer records.
+int resolve_scratch(int device, std::string *why);
+void *scratch_ptr(int device);
+void launch_static_setup(hipStream_t st, const InstDesc &desc, InstDesc *d_desc, InstDesc **d_ptrs,
+                         double *records, int n_records);
+
 }  // namespace plsqr
 
 struct plsqr_engine {

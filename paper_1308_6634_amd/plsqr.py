@@ -39,6 +39,7 @@ PLSQR_FLAG_TIME_PRODUCTS = 1
 PLSQR_FLAG_NO_GRAPHS = 2
 PLSQR_FLAG_STOP_S4 = 4
 PLSQR_FLAG_STOP_OUTER = 8
+PLSQR_STATIC_SCRATCH_BYTES = 64 << 20
 PLSQR_FLAG_TIME_PHASES = 16
 PLSQR_MAX_LEVELS = 12
 PLSQR_MAX_OUTER = 64
@@ -50,7 +51,7 @@ REG_CODES = {"tikhonov": PLSQR_REG_TIKHONOV, "stv": PLSQR_REG_STV, "pm_log": PLS
 SMOOTHER_CODES = {"jacobi": PLSQR_SMOOTH_JACOBI, "chebyshev": PLSQR_SMOOTH_CHEBYSHEV}
 
 EXPORTED = ("plsqr_create", "plsqr_set_operator", "plsqr_solve", "plsqr_solve_batch", "plsqr_poll",
-            "plsqr_solve_taus",
+            "plsqr_solve_taus", "plsqr_solve_static",
             "plsqr_wait_all",
             "plsqr_destroy", "plsqr_last_error", "plsqr_auto_levels", "plsqr_workspace_bytes")
 
@@ -118,6 +119,8 @@ def _load():
     lib.plsqr_solve_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                       P(plsqr_problem), P(ctypes.c_void_p), P(ctypes.c_void_p),
                                       P(ctypes.c_uint64)]
+    lib.plsqr_solve_static.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(plsqr_problem),
+                                       ctypes.c_void_p, ctypes.c_void_p, P(plsqr_result)]
     lib.plsqr_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(plsqr_result)]
     lib.plsqr_wait_all.argtypes = [ctypes.c_void_p]
     lib.plsqr_destroy.argtypes = [ctypes.c_void_p]
@@ -175,6 +178,18 @@ def plsqr_solve_batch(eng, op_id, probs, g_devs, f_devs):
     tickets = (ctypes.c_uint64 * n)()
     _check(_lib.plsqr_solve_batch(eng, op_id, n, arr, gs, fs, tickets), eng)
     return list(tickets)
+
+
+def plsqr_solve_static(eng, op_id, prob, g_dev, f_dev, want_result=True):
+    """The no-allocation entry point. With want_result, waits and returns (status, result);
+    otherwise returns (PLSQR_OK, None) once the work is enqueued. Argument errors raise; a
+    request that fails on the device returns its status."""
+    res = plsqr_result() if want_result else None
+    rc = _lib.plsqr_solve_static(eng, op_id, ctypes.byref(prob), g_dev, f_dev,
+                                 ctypes.byref(res) if want_result else None)
+    if rc < 0 and (res is None or res.status != rc):
+        _check(rc, eng)
+    return rc, res
 
 
 def plsqr_poll(eng, ticket):
