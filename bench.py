@@ -296,6 +296,9 @@ def main():
                     help="c2: apply the ring sensitivity through its geometry (entries recomputed "
                          "in every product) instead of the stored 4096 x 262144 matrix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a tiling knob of the problem struct (tune_*), after any autotuning; "
+                         "repeatable")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) autotuning of tiling knobs before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -317,6 +320,12 @@ def main():
     ap.add_argument("--traffic-key", default=None,
                     help="record key of --traffic-sequence (c4: forward_bf16_refined)")
     args = ap.parse_args()
+    args.knobs = {}
+    for kv in args.knob:
+        name, _, val = kv.partition("=")
+        if not name.startswith("tune_") or not val:
+            raise SystemExit(f"--knob takes tune_NAME=VALUE, got {kv!r}")
+        args.knobs[name] = int(val)
     if args.write_traffic:
         return write_traffic(args)
     if args.copy_calibration:
@@ -360,6 +369,7 @@ def main():
         settings, tune_report = autotune.tune(p, eng)
         p = autotune.apply(p, settings)
         print(f"[bench] autotuned: {settings}", file=sys.stderr, flush=True)
+    settings.update(args.knobs)
     if p.op_kind == "dense" and args.matrix_free:
         op = eng.ring_operator(p.dims, *p.extra["ring"])
     elif p.op_kind == "dense":
@@ -368,8 +378,10 @@ def main():
         op = eng.blur_operator(p.dims, p.taps)
     g = torch.from_numpy(np.ascontiguousarray(p.g, dtype=np.float32).ravel()).cuda()
     f = torch.zeros(n, dtype=torch.float32, device="cuda")
-    pb = problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS |
-                        (P.PLSQR_FLAG_NO_GRAPHS if args.no_graphs else 0), knobs=settings)
+    # the timed steps carry no timing events (every inner iteration replays as one graph); the
+    # products are timed with events in one more solve afterwards, for the roofline figure
+    graphs_flag = P.PLSQR_FLAG_NO_GRAPHS if args.no_graphs else 0
+    pb = problem_struct(p, flags=graphs_flag, knobs=settings)
 
     for _ in range(args.warmup):
         st, _ = eng.wait(eng.submit(op, pb, g, f))
@@ -386,10 +398,12 @@ def main():
         assert st == 0
     iters = n * p.outer * p.inner * args.steps
     value = iters / elapsed
-    fwd_ms = sum(r.forward_ms for _, r in results)
-    fwd_n = sum(r.forward_launches for _, r in results)
-    adj_ms = sum(r.adjoint_ms for _, r in results)
-    adj_n = sum(r.adjoint_launches for _, r in results)
+    st, timed = eng.wait(eng.submit(op, problem_struct(p, flags=graphs_flag |
+                                                       P.PLSQR_FLAG_TIME_PRODUCTS,
+                                                       knobs=settings), g, f))
+    assert st == 0
+    fwd_ms, fwd_n = timed.forward_ms, timed.forward_launches
+    adj_ms, adj_n = timed.adjoint_ms, timed.adjoint_launches
     avg_fwd_s = fwd_ms / max(fwd_n, 1) / 1e3
     nbytes, kname, pass_bytes = dominant_bytes(p)
     achieved = nbytes / avg_fwd_s / 1e9 if avg_fwd_s > 0 else None
@@ -413,8 +427,8 @@ def main():
     if p.op_kind == "dense" and not args.matrix_free:
         traffic = traffic_for(args.workload, settings.get("tune_gemv_rows"))
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; forward product avg "
-          f"{avg_fwd_s * 1e3:.3f} ms, adjoint avg {adj_ms / max(adj_n, 1):.3f} ms",
-          file=sys.stderr, flush=True)
+          f"{avg_fwd_s * 1e3:.3f} ms, adjoint avg {adj_ms / max(adj_n, 1):.3f} ms (one more "
+          f"solve with product timing)", file=sys.stderr, flush=True)
 
     out = {
         "metric": "voxel-LSQR-iters/s",
@@ -620,7 +634,20 @@ def bench_c4(args):
             assert st == 0, P.plsqr_last_error(eng.handle)
         return res
 
-    pbs = [problem_struct(p, flags=P.PLSQR_FLAG_TIME_PRODUCTS, precision=prec) for p in probs]
+    settings = {}
+    if not args.no_tune:
+        # V-cycle launch schedule for this batch, by the V-cycle phase time of a short batch
+        from paper_1308_6634_amd import autotune
+        short = [dataclasses.replace(p, outer=1, inner=2) for p in probs]
+
+        def vcycle_ms(vs):
+            res = run_batch([problem_struct(p, flags=P.PLSQR_FLAG_TIME_PHASES, precision=prec,
+                                            knobs=vs) for p in short])
+            return res[0][1].vcycle_ms
+        settings, _ = autotune.tune_vcycle(vcycle_ms, repeats=1)
+        print(f"[bench] autotuned V-cycle: {settings}", file=sys.stderr, flush=True)
+    settings.update(args.knobs)
+    pbs = [problem_struct(p, precision=prec, knobs=settings) for p in probs]
     for _ in range(args.warmup):
         run_batch(pbs)
     print("[bench] warmup done", file=sys.stderr, flush=True)
@@ -630,18 +657,19 @@ def bench_c4(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = B * n * p0.outer * p0.inner * args.steps / elapsed
-    r0 = [res[0][1] for res in results]
-    fwd_ms = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1)
-    adj_ms = sum(r.adjoint_ms for r in r0) / max(sum(r.adjoint_launches for r in r0), 1)
+    # one more batch with every phase timed (not part of the timed steps): the product launch
+    # times of the roofline and the phase split
+    ph = run_batch([problem_struct(p, flags=P.PLSQR_FLAG_TIME_PHASES, precision=prec,
+                                   knobs=settings)
+                    for p in probs])[0][1]
+    fwd_ms = ph.forward_ms / max(ph.forward_launches, 1)
+    adj_ms = ph.adjoint_ms / max(ph.adjoint_launches, 1)
     lo = 2 if prec == P.PLSQR_PREC_BF16_REFINED else 1
     fwd_bytes = lo * 2 * m * n + 2 * 2 * 64 * n
     fwd_flops = 2.0 * m * n * 64 * (lo + 1)
     print(f"[bench] batched: {elapsed / args.steps * 1e3:.1f} ms per batch; forward product "
           f"{fwd_ms:.3f} ms, adjoint {adj_ms:.3f} ms", file=sys.stderr, flush=True)
 
-    # one more batch with every phase timed (not part of the timed steps)
-    ph = run_batch([problem_struct(p, flags=P.PLSQR_FLAG_TIME_PHASES, precision=prec)
-                    for p in probs])[0][1]
     phases = {"setup_ms": ph.setup_ms, "forward_ms": ph.forward_ms, "adjoint_ms": ph.adjoint_ms,
               "vcycle_ms": ph.vcycle_ms, "update_ms": ph.update_ms, "diag_ms": ph.diag_ms,
               "device_ms": ph.device_ms, "inner_steps": int(ph.phase_launches)}
@@ -664,7 +692,7 @@ def bench_c4(args):
         "data": "synthetic",
         "config": {"workload": desc, "instances": B, "n_x": n, "n_y": m, "outer": p0.outer,
                    "inner": p0.inner, "precision": args.precision + " products, fp32 vectors, "
-                   "fp64 scalars"},
+                   "fp64 scalars", "autotuned": settings},
         "roofline": {"bound": "hbm", "kernel": "forward product (k_pack_split + k_gemm_bf16 + "
                      "k_fwd_reduce)", "achieved": fwd_bytes / (fwd_ms / 1e3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -687,7 +715,8 @@ def bench_c4(args):
         cb, S, refs = c4_oracle_sample(probs, A)
         out["cpu_baseline"] = cb
         # the same sample on the GPU: the whole batch at 1 outer x S inner, same precision
-        run_batch([problem_struct(dataclasses.replace(p, outer=1, inner=S), precision=prec)
+        run_batch([problem_struct(dataclasses.replace(p, outer=1, inner=S), precision=prec,
+                                  knobs=settings)
                    for p in probs])
         errs = {}
         for i, f_ref in refs.items():

@@ -54,6 +54,8 @@ enum { PLSQR_OP_BLUR = 1, PLSQR_OP_DENSE = 2, PLSQR_OP_RING = 3 };
 /* r(t) of eq. (1.3) (Tikhonov), (1.4) smoothed TV, (1.5) Perona-Malik log / exp forms */
 enum { PLSQR_REG_TIKHONOV = 0, PLSQR_REG_STV = 1, PLSQR_REG_PM_LOG = 2, PLSQR_REG_PM_EXP = 3 };
 enum { PLSQR_SMOOTH_JACOBI = 0, PLSQR_SMOOTH_CHEBYSHEV = 1 };
+/* V-cycle launch schedule (plsqr_problem.tune_vcycle) */
+enum { PLSQR_VCYCLE_FUSED = 0, PLSQR_VCYCLE_PER_SWEEP = 1 };
 /* FP32: float32 vectors and products, float64 Krylov scalars and coarsest solve.
  * BF16_REFINED / BF16 (batches on a dense operator only): the dense products of the
  * batch run as BF16 MFMA GEMMs with FP32 accumulation. Every FP32 operand v is split
@@ -186,7 +188,19 @@ typedef struct {
    *  tune_gemv_rows   rows of A per block of the dense forward product (1, 2, 4 or 8)
    *  tune_col_chunks  row chunks of the dense adjoint product (1..64)
    *  tune_blur_window outputs per thread of the y/z blur passes (4, 8, 16 or 32; default 8)
-   *  tune_blur_xgroups 4-output groups per thread of the x blur pass (1, 2 or 4; default 2) */
+   *  tune_blur_xgroups 4-output groups per thread of the x blur pass (1, 2 or 4; default 2)
+   *  tune_vcycle      PLSQR_VCYCLE_FUSED (default): every level above the one-workgroup tail
+   *                   runs its pre-smoothing with the residual restriction as one launch and its
+   *                   prolongation with the post-smoothing as another (Jacobi with nu <= 4,
+   *                   Chebyshev with nu = 1 and degree <= 4, levels with nx % 4 == 0);
+   *                   PLSQR_VCYCLE_PER_SWEEP: one launch per sweep and a separate restriction.
+   *                   Both compute the same values.
+   *  tune_zm_ty, tune_zm_zc  output rows and planes per block of the fused level kernels
+   *                   (even, ty in [2, 64], zc in [2, 64]; 0: chosen from the grid)
+   *  tune_zm_v        voxels per thread of the fused level kernels, 1 or 4 (0: 4 on levels of
+   *                   at least 2^20 cells, 1 below)
+   *  tune_tail_cells  largest level (in cells) that joins the one-workgroup V-cycle tail
+   *                   (0: 4096; at most 2^20) */
   int32_t tune_gemv_rows;
   int32_t tune_col_chunks;
   /* adaptive stopping (PLSQR_FLAG_STOP_S4, PLSQR_FLAG_STOP_OUTER) */
@@ -195,6 +209,12 @@ typedef struct {
   int32_t outer_min;
   int32_t tune_blur_window;
   int32_t tune_blur_xgroups;
+  int32_t tune_vcycle;
+  int32_t tune_zm_ty;
+  int32_t tune_zm_zc;
+  int32_t tune_zm_v;
+  int32_t tune_tail_cells;
+  int32_t reserved1;
 } plsqr_problem;
 
 /* Completion record of one request (filled by plsqr_poll). */

@@ -95,6 +95,11 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.gemv_rows = pb.tune_gemv_rows ? pb.tune_gemv_rows : 4;
   D.blur_window = pb.tune_blur_window;
   D.blur_xgroups = pb.tune_blur_xgroups;
+  D.vcycle_mode = pb.tune_vcycle;
+  D.zm_ty = pb.tune_zm_ty;
+  D.zm_zc = pb.tune_zm_zc;
+  D.zm_v = pb.tune_zm_v;
+  D.tail_cells = pb.tune_tail_cells;
   D.out_f = r.f_out;
   D.sc = reinterpret_cast<double *>(ws + Ly.sc);
   D.part = reinterpret_cast<double *>(ws + Ly.part);
@@ -447,7 +452,10 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
         c.smoother != a.smoother || c.nu_pre != a.nu_pre || c.cheb_degree != a.cheb_degree ||
         c.precision != a.precision || c.flags != a.flags ||
         c.tune_gemv_rows != a.tune_gemv_rows || c.tune_col_chunks != a.tune_col_chunks ||
-        c.tune_blur_window != a.tune_blur_window || c.tune_blur_xgroups != a.tune_blur_xgroups)
+        c.tune_blur_window != a.tune_blur_window || c.tune_blur_xgroups != a.tune_blur_xgroups ||
+        c.tune_vcycle != a.tune_vcycle || c.tune_zm_ty != a.tune_zm_ty ||
+        c.tune_zm_zc != a.tune_zm_zc || c.tune_zm_v != a.tune_zm_v ||
+        c.tune_tail_cells != a.tune_tail_cells)
       return set_error(PLSQR_E_INVALID,
                        "a batch must share counts, levels, smoother schedule, precision and flags");
   }
@@ -509,11 +517,13 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
 // dense or ring operator the operator itself (its row count sizes grids, column chunks and
 // the ring adjoint's LDS). Blur requests of one grid share launches whatever their taps.
 struct ClassKey {
-  int nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win, xg;
+  int nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win, xg, vc, zty,
+      zzc, zv, tail;
   bool operator<(const ClassKey &o) const {
     return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win,
-                    xg) < std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind,
-                                   o.type, o.stop, o.op, o.gemv, o.cols, o.win, o.xg);
+                    xg, vc, zty, zzc, zv, tail) <
+           std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type, o.stop,
+                    o.op, o.gemv, o.cols, o.win, o.xg, o.vc, o.zty, o.zzc, o.zv, o.tail);
   }
 };
 
@@ -622,7 +632,8 @@ void serve_tick(plsqr_engine *eng) {
     ClassKey key{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
                  r.host.op_kind, step_type(pb, r.step),
                  (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)), op_key,
-                 pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window, pb.tune_blur_xgroups};
+                 pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window, pb.tune_blur_xgroups,
+                 pb.tune_vcycle, pb.tune_zm_ty, pb.tune_zm_zc, pb.tune_zm_v, pb.tune_tail_cells};
     groups[key].push_back(&r);
   }
   plsqr_engine::TickSlot &slot = eng->ring[eng->ring_next];

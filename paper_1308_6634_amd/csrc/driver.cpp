@@ -58,6 +58,16 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   if (pb.tune_blur_xgroups && pb.tune_blur_xgroups != 1 && pb.tune_blur_xgroups != 2 &&
       pb.tune_blur_xgroups != 4)
     return bad("tune_blur_xgroups must be 0, 1, 2 or 4");
+  if (pb.tune_vcycle != PLSQR_VCYCLE_FUSED && pb.tune_vcycle != PLSQR_VCYCLE_PER_SWEEP)
+    return bad("tune_vcycle must be PLSQR_VCYCLE_FUSED or PLSQR_VCYCLE_PER_SWEEP");
+  if (pb.tune_zm_ty && (pb.tune_zm_ty < 2 || pb.tune_zm_ty > 64 || (pb.tune_zm_ty & 1)))
+    return bad("tune_zm_ty must be 0 or even in [2, 64]");
+  if (pb.tune_zm_zc && (pb.tune_zm_zc < 2 || pb.tune_zm_zc > 64 || (pb.tune_zm_zc & 1)))
+    return bad("tune_zm_zc must be 0 or even in [2, 64]");
+  if (pb.tune_zm_v != 0 && pb.tune_zm_v != 1 && pb.tune_zm_v != 4)
+    return bad("tune_zm_v must be 0, 1 or 4");
+  if (pb.tune_tail_cells < 0 || pb.tune_tail_cells > (1 << 20))
+    return bad("tune_tail_cells must be in [0, 2^20]");
   int levels = pb.mg_levels;
   if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
   if (levels < 1 || levels > kMaxLevels) return bad("mg_levels out of range");
@@ -324,15 +334,25 @@ struct LevelLaunch {
 }  // namespace
 
 // First level of the V-cycle tail (one workgroup per instance, see k_vcycle_tail): the first
-// level l >= 1 with at most kTailCells cells such that every level l .. L-2 has nx % 4 == 0;
-// L - 1 (only the coarsest solve) when there is none.
-static int tail_start(const Layout &Ly, int L) {
+// level l >= 1 with at most `cells` cells (kTailCells unless tuned) such that every level
+// l .. L-2 has nx % 4 == 0; L - 1 (only the coarsest solve) when there is none.
+static int tail_start(const Layout &Ly, int L, int cells) {
+  const long long limit = cells > 0 ? cells : kTailCells;
   int t = L - 1;
   for (int l = L - 2; l >= 1; --l) {
-    if (Ly.ln[l] > kTailCells || Ly.lnx[l] % 4 != 0) break;
+    if (Ly.ln[l] > limit || Ly.lnx[l] % 4 != 0) break;
     t = l;
   }
   return t;
+}
+
+// Depth of the fused level kernels for this smoother schedule (Jacobi: nu sweeps; Chebyshev:
+// the degree, with one polynomial per side), 0 when there is no fused form or the per-sweep
+// kernels are asked for.
+static int zm_depth(const InstDesc &H) {
+  if (H.vcycle_mode == PLSQR_VCYCLE_PER_SWEEP) return 0;
+  if (H.smoother == PLSQR_SMOOTH_JACOBI) return (H.nu_pre >= 1 && H.nu_pre <= 4) ? H.nu_pre : 0;
+  return (H.nu_pre == 1 && H.cheb_degree >= 1 && H.cheb_degree <= 4) ? H.cheb_degree : 0;
 }
 
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
@@ -348,7 +368,20 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   }
   int np = 0;
   const int nu = H.nu_pre;
-  const int t = tail_start(Ly, L);
+  const int t = tail_start(Ly, L, H.tail_cells);
+  // levels above the tail whose pre- and post-smoothing each run as one fused launch
+  const int hz = zm_depth(H);
+  ZmShape shp[kMaxLevels];
+  bool fz[kMaxLevels] = {};
+  for (int l = 0; l < t; ++l) {
+    shp[l] = zm_shape(Ly.lnx[l], Ly.lny[l], Ly.lnz[l], hz > 0 ? hz : 1, H.zm_ty, H.zm_zc, H.zm_v);
+    fz[l] = hz > 0 && zm_fits(Ly.lnx[l], hz, shp[l]);
+  }
+  // level 0's up kernel writes one alpha partial per block into the instance's partials
+  if (fz[0] && zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], shp[0]) > Ly.nparts) fz[0] = false;
+  auto zm = [&](int kind, int l, int want) {
+    return launch_zm(st, d, B, kind, hz, l, Ly.lnx[l], Ly.lny[l], Ly.lnz[l], shp[l], want);
+  };
   if (H.smoother == PLSQR_SMOOTH_JACOBI) {
     // the first two pre-sweeps run as one kernel; the prolongation runs inside the first
     // post-sweep; every sweep writes the other of the (x, t) pair, ending in x
@@ -356,6 +389,10 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
     const int first_dst = ((pre_writes + nu) % 2) ? LB_X : LB_T;
     int cur_l[kMaxLevels];
     for (int l = 0; l < t; ++l) {
+      if (fz[l]) {
+        zm(ZM_JAC_DOWN, l, 0);
+        continue;
+      }
       int cur;
       if (nu >= 2) {
         K.jacobi_first2(l, first_dst, 0);
@@ -373,6 +410,11 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
     }
     launch_vcycle_tail(st, d, B, t);
     for (int l = t - 1; l >= 0; --l) {
+      if (fz[l]) {
+        const int r = zm(ZM_JAC_UP, l, l == 0 ? 1 : 0);
+        if (l == 0) np = r;
+        continue;
+      }
       int cur = cur_l[l];
       const bool last0 = (nu == 1);
       int r = K.jacobi_prolong(l, cur, other(cur), (l == 0 && last0) ? 1 : 0);
@@ -388,6 +430,10 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   } else {
     const int m = H.cheb_degree;
     for (int l = 0; l < t; ++l) {
+      if (fz[l]) {
+        zm(ZM_CHEB_DOWN, l, 0);
+        continue;
+      }
       for (int a = 0; a < nu; ++a) {
         int dcur = LB_T;
         int k0 = 0;
@@ -411,6 +457,11 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
     }
     launch_vcycle_tail(st, d, B, t);
     for (int l = t - 1; l >= 0; --l) {
+      if (fz[l]) {
+        const int r = zm(ZM_CHEB_UP, l, l == 0 ? 1 : 0);
+        if (l == 0) np = r;
+        continue;
+      }
       for (int a = 0; a < nu; ++a) {
         if (a == 0)
           K.cheb_start_prolong(l, LB_T);

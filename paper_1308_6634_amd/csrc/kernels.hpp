@@ -62,6 +62,24 @@ void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
 // levels t .. coarsest of a V-cycle in one workgroup per instance (t >= 1; levels t .. L-2 with
 // nx % 4 == 0)
 void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
+// Fused level kernels (zmarch.hip): one launch per level and V-cycle half. ZM_*_DOWN runs the
+// whole pre-smoothing of level l from x = 0 on b_l, writes the pre-smoothed iterate to the
+// level's t buffer and the restricted residual to b_{l+1}; ZM_*_UP adds the coarse correction
+// x_{l+1} to that iterate, runs the whole post-smoothing and writes x_l (v on level 0; with
+// want_dot the partials of v.p, one per block). H: Jacobi sweeps, or the Chebyshev degree
+// (one polynomial per side); the level's nx must be a multiple of 4.
+enum ZmKind : int { ZM_JAC_DOWN = 0, ZM_JAC_UP, ZM_CHEB_DOWN, ZM_CHEB_UP };
+struct ZmShape {
+  int tx, ty, zc;   // output tile: tx x-columns (a multiple of v), ty rows, zc planes
+  int v;            // voxels per thread: 4 (x-consecutive) or 1
+};
+// Default tile for a level of nx x ny x nz (knobs > 0 override ty, zc and v).
+ZmShape zm_shape(int nx, int ny, int nz, int H, int ty_knob, int zc_knob, int v_knob);
+bool zm_fits(int nx, int H, const ZmShape &s);
+long long zm_tiles(int nx, int ny, int nz, const ZmShape &s);   // blocks per instance
+size_t zm_lds_bytes(int H, const ZmShape &s, bool down);
+int launch_zm(hipStream_t st, InstDesc *const *d, int B, int kind, int H, int l, int nx, int ny,
+              int nz, const ZmShape &s, int want_dot);
 // separable blur passes (blur.hip); the x pass takes 16-byte windows when nx % 4 == 0
 // groups: 4-output groups per thread when nx % 4 == 0 (1, 2 or 4; 0: default)
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,

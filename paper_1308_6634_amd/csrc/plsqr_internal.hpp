@@ -78,6 +78,10 @@ struct InstDesc {
   int gemv_rows;                     // rows of A per block of the dense forward product
   int blur_window;                   // outputs per thread of the y/z blur passes (0: default)
   int blur_xgroups;                  // 4-output groups per thread of the x pass (0: default)
+  int vcycle_mode;                   // PLSQR_VCYCLE_FUSED or PLSQR_VCYCLE_PER_SWEEP
+  int zm_ty, zm_zc, zm_v;            // fused level kernels: rows / planes per block, voxels per
+                                     // thread (0: chosen per level)
+  int tail_cells;                    // largest level of the one-workgroup tail (0: default)
   int stop_flags;                    // PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER bits
   int outer_min;                     // first outer step checked by the outer stop
   double s4_level;                   // eta * delta

@@ -1,0 +1,702 @@
+// Fused multigrid level kernels: one launch runs a level's whole pre-smoothing together with
+// the residual restriction ("down"), or the prolongation together with the whole
+// post-smoothing ("up"), of the V-cycle that applies the priorconditioner (section 4.2).
+//
+// Temporal blocking by marching along z. A block owns an output tile of tx x ty columns
+// (x fastest) and a chunk of zc planes. Its threads cover the tile widened by the halo the
+// smoother needs (H = the number of stencil applications, at most 4: H rows on each y side,
+// and on each x side H voxels, or one group of four when a thread owns four x-consecutive
+// voxels). The block marches through the planes: in iteration t, stage 0 forms the first
+// stencil input at plane t, and stage s (1..H) applies the level stencil at plane t - s, so
+// each stage runs one plane behind the previous one. A stage takes its z-neighbours from the
+// thread's own registers (the values the previous stage produced at the planes on either side)
+// and its x/y-neighbours from the LDS copy of the previous stage's plane written in the
+// preceding iteration; one barrier per iteration orders the LDS. Columns near the widened
+// tile's edge compute values that are never used (their neighbours are missing), and the loss
+// shrinks the valid region by one column per stage, which the halo absorbs.
+//
+// A thread owns V = 4 x-consecutive voxels (16-byte loads; for levels that keep the chip busy,
+// where the instruction count per voxel decides) or V = 1 voxel (four times as many threads
+// and a quarter of the instructions per iteration, for the small levels, where one block's
+// march along z decides).
+//
+// The inputs of a plane (right-hand side, face weights) are loaded once, one iteration before
+// their first use, and handed down the stages in registers with the plane's 1/diag, formed
+// once when the plane enters.
+//
+// Every voxel's arithmetic is that of the one-pass kernels (smooth_vec.hip): the same formulas
+// with the terms in the same order, so the fused and the per-sweep V-cycles give the same
+// values up to the sign of a zero sum; only the alpha partial sums are grouped differently.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace plsqr {
+
+namespace {
+
+// threads per block: a four-voxel thread carries about four times the registers
+constexpr int kZmMaxThreads = 1024;
+__host__ __device__ constexpr int zm_max_threads(int V) { return V == 4 ? 512 : 1024; }
+
+template <int V>
+struct Vec {
+  float v[V];
+};
+
+template <int V>
+__device__ __forceinline__ Vec<V> ldv(const float *p) {
+  Vec<V> r;
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    r.v[0] = t.x;
+    r.v[1] = t.y;
+    r.v[2] = t.z;
+    r.v[3] = t.w;
+  } else {
+    r.v[0] = *p;
+  }
+  return r;
+}
+template <int V>
+__device__ __forceinline__ void stv(float *p, const Vec<V> &a) {
+  if constexpr (V == 4) *reinterpret_cast<float4 *>(p) = make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+  else *p = a.v[0];
+}
+// LDS cell of one thread: a float4 for V = 4, a float for V = 1
+template <int V>
+using LdsCell = typename std::conditional<V == 4, float4, float>::type;
+template <int V>
+__device__ __forceinline__ LdsCell<V> to_cell(const Vec<V> &a) {
+  if constexpr (V == 4) return make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+  else return a.v[0];
+}
+template <int V>
+__device__ __forceinline__ Vec<V> from_cell(const LdsCell<V> &c) {
+  Vec<V> r;
+  if constexpr (V == 4) {
+    r.v[0] = c.x;
+    r.v[1] = c.y;
+    r.v[2] = c.z;
+    r.v[3] = c.w;
+  } else {
+    r.v[0] = c;
+  }
+  return r;
+}
+template <int V>
+__device__ __forceinline__ float first_of(const LdsCell<V> &c) {
+  if constexpr (V == 4) return c.x;
+  else return c;
+}
+template <int V>
+__device__ __forceinline__ float last_of(const LdsCell<V> &c) {
+  if constexpr (V == 4) return c.w;
+  else return c;
+}
+
+// One thread's inputs at one plane, loaded once (one iteration ahead of their first use) and
+// handed down the stages in registers: the right-hand side, the face weights to the +x/+y/+z
+// neighbours (level 0: all three are kappa of the cell), the weight from the -x neighbour of
+// the first voxel and the weights from the -y neighbours (zero where the face leaves the grid),
+// and the 1/diag formed when the plane enters. The weights from the -z neighbours are the +z
+// weights of the plane below, the next entry of the same register line.
+template <bool L0, int V>
+struct PlaneData {
+  Vec<V> b, wx, wy, wz, wym, dinv;
+  float wxl;
+};
+template <int V>
+struct PlaneData<true, V> {
+  Vec<V> b, k, wym, dinv;
+  float wxl;
+};
+
+struct ZmCtx {
+  LevelDesc L;
+  int nx, ny, nz;
+  long long sy, sz;
+  int gx, gy;          // this thread's first voxel (global x) and row
+  float eps;
+};
+
+// Loads of plane p (clamped into the grid, and for threads outside the grid from index 0, so
+// that every address is valid and no load waits on a branch); values of planes outside the
+// grid are never used.
+template <bool L0, int V>
+__device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const float *__restrict__ kap,
+                                                       bool in, long long col, int p) {
+  const int pc = min(max(p, 0), c.nz - 1);
+  const long long j = in ? col + c.sz * pc : 0;
+  const bool hl = in && c.gx > 0, hy = in && c.gy > 0;
+  const long long jl = hl ? j - 1 : j;
+  const long long jy = hy ? j - c.sy : j;
+  PlaneData<L0, V> d;
+  d.dinv = Vec<V>{};
+  d.b = ldv<V>(c.L.b + j);
+  const float *wxs = L0 ? kap : c.L.wx;
+  const float *wys = L0 ? kap : c.L.wy;
+  const float xl = wxs[jl];
+  const Vec<V> ym = ldv<V>(wys + jy);
+  d.wxl = hl ? xl : 0.f;
+#pragma unroll
+  for (int e = 0; e < V; ++e) d.wym.v[e] = hy ? ym.v[e] : 0.f;
+  if constexpr (L0) {
+    d.k = ldv<V>(kap + j);
+  } else {
+    d.wx = ldv<V>(c.L.wx + j);
+    d.wy = ldv<V>(c.L.wy + j);
+    if (c.nz > 1) d.wz = ldv<V>(c.L.wz + j);
+    else d.wz = Vec<V>{};
+  }
+  return d;
+}
+
+// 1/diag at plane p (below: the plane under it). Level 0 assembles it from kappa in the order
+// of the stencil and of the stored level-0 diagonal; coarser levels in the order of the stored
+// diagonal (eps, then each axis's pair of faces).
+template <bool L0, int V>
+__device__ __forceinline__ Vec<V> plane_dinv(const ZmCtx &c, const PlaneData<L0, V> &d,
+                                             const PlaneData<L0, V> &below, int p) {
+  Vec<V> dv;
+  const bool hyp = c.gy + 1 < c.ny, hym = c.gy > 0, hzp = p + 1 < c.nz, hzm = p > 0;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    float dg = c.eps;
+    if constexpr (L0) {
+      const float wm = (e > 0) ? d.k.v[e > 0 ? e - 1 : 0] : d.wxl;
+      if (c.gx + e + 1 < c.nx) dg += d.k.v[e];
+      if (c.gx + e > 0) dg += wm;
+      if (hyp) dg += d.k.v[e];
+      if (hym) dg += d.wym.v[e];
+      if (hzp) dg += d.k.v[e];
+      if (hzm) dg += below.k.v[e];
+    } else {
+      const float wm = (e > 0) ? d.wx.v[e > 0 ? e - 1 : 0] : d.wxl;
+      dg += d.wx.v[e] + (c.gx + e > 0 ? wm : 0.f);
+      dg += d.wy.v[e] + (hym ? d.wym.v[e] : 0.f);
+      if (c.nz > 1) dg += d.wz.v[e] + (hzm ? below.wz.v[e] : 0.f);
+    }
+    dv.v[e] = 1.0f / dg;
+  }
+  return dv;
+}
+
+// (A_l x) at plane p, with the neighbour values given: xl/xr the x-neighbours of the first and
+// last voxel, yp/ym/zp/zm the neighbouring rows and planes. The faces are added in the order of
+// stencil4. Faces that leave the grid are skipped; where a weight loaded for such a face is
+// already zero (the -x face of the grid's first voxel, the -y faces) the term is added anyway,
+// which changes nothing but the sign of a zero sum. The z faces depend only on the plane, so
+// they are tested once (a uniform branch).
+template <bool L0, int V>
+__device__ __forceinline__ Vec<V> apply_stencil(const ZmCtx &c, const PlaneData<L0, V> &d,
+                                                const PlaneData<L0, V> &below, int p,
+                                                const Vec<V> &xc, float xl, float xr,
+                                                const Vec<V> &yp, const Vec<V> &ym,
+                                                const Vec<V> &zp, const Vec<V> &zm) {
+  const bool hyp = c.gy + 1 < c.ny, hzp = p + 1 < c.nz, hzm = p > 0;
+  const bool hxr = c.gx + V < c.nx;            // +x face of the last voxel
+  Vec<V> acc;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const float xj = xc.v[e];
+    float a = c.eps * xj;
+    const float xnext = (e < V - 1) ? xc.v[e < V - 1 ? e + 1 : 0] : xr;
+    const float xprev = (e > 0) ? xc.v[e > 0 ? e - 1 : 0] : xl;
+    float wxp, wm, wyp;
+    if constexpr (L0) {
+      wxp = wyp = d.k.v[e];
+      wm = (e > 0) ? d.k.v[e > 0 ? e - 1 : 0] : d.wxl;
+    } else {
+      wxp = d.wx.v[e];
+      wyp = d.wy.v[e];
+      wm = (e > 0) ? d.wx.v[e > 0 ? e - 1 : 0] : d.wxl;
+    }
+    if (e < V - 1 || hxr) a += wxp * (xj - xnext);
+    a += wm * (xj - xprev);                     // zero weight at the grid's -x edge
+    if (hyp) a += wyp * (xj - yp.v[e]);
+    a += d.wym.v[e] * (xj - ym.v[e]);           // zero weight at the grid's -y edge
+    acc.v[e] = a;
+  }
+  if (L0 || c.nz > 1) {
+    if (hzp) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        float w;
+        if constexpr (L0) w = d.k.v[e];
+        else w = d.wz.v[e];
+        acc.v[e] += w * (xc.v[e] - zp.v[e]);
+      }
+    }
+    if (hzm) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        float w;
+        if constexpr (L0) w = below.k.v[e];
+        else w = below.wz.v[e];
+        acc.v[e] += w * (xc.v[e] - zm.v[e]);
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double block_sum_any(double v) {
+  __shared__ double red[kZmMaxThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += red[i];
+  return r;
+}
+
+// threads of x halo on each side: one group of four, or H single voxels
+__host__ __device__ constexpr int halo_units(int V, int H) { return V == 4 ? 1 : H; }
+
+}  // namespace
+
+// KIND: ZM_JAC_DOWN, ZM_JAC_UP (damped Jacobi, H = nu sweeps), ZM_CHEB_DOWN, ZM_CHEB_UP
+// (one Chebyshev polynomial of degree H per side); L0: level 0 (face weights are kappa);
+// V: voxels per thread. Down: b = level l's right-hand side -> pre-smoothed iterate into L.t,
+// restricted residual into b of level l + 1. Up: L.t and the coarse correction x of level
+// l + 1 -> post-smoothed iterate into L.x (on level 0 that is v, and with want_dot the block's
+// part of v.p).
+template <int KIND, int H, bool L0, int V>
+__global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs, int l, int tx,
+                                                     int ty, int zc, int want_dot) {
+  constexpr bool DOWN = (KIND == ZM_JAC_DOWN || KIND == ZM_CHEB_DOWN);
+  constexpr bool CHEB = (KIND == ZM_CHEB_DOWN || KIND == ZM_CHEB_UP);
+  constexpr int HX = halo_units(V, H);
+  using Cell = LdsCell<V>;
+  extern __shared__ float4 zsm4[];
+  Cell *zsm = reinterpret_cast<Cell *>(zsm4);
+  const InstDesc &D = inst(descs);
+  if (stopped_inner(D)) return;
+  ZmCtx c;
+  c.L = level_of(D, l);
+  const LevelDesc Cl = level_of(D, l + 1);
+  c.nx = c.L.nx;
+  c.ny = c.L.ny;
+  c.nz = c.L.nz;
+  c.sy = c.nx;
+  c.sz = (long long)c.nx * c.ny;
+  c.eps = (float)c.L.eps;
+  const float *__restrict__ kap = L0 ? sld(D.kappa) : nullptr;
+  const int ntx = (c.nx + tx - 1) / tx, nty = (c.ny + ty - 1) / ty, ntz = (c.nz + zc - 1) / zc;
+  const long long b = xcd_tile();
+  if (b >= (long long)ntx * nty * ntz) {   // past this instance's tiles (a larger batch member)
+    if (want_dot && threadIdx.x == 0) sld(D.part)[blockIdx.x] = 0.0;
+    return;
+  }
+  const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((long long)ntx * nty));
+  const int x0 = bx * tx, y0 = by * ty, z0 = bz * zc;
+  const int exq = tx / V + 2 * HX, ey = ty + 2 * H;
+  const int plane = exq * ey;               // LDS cells per plane
+  const int q = (int)threadIdx.x % exq, row = (int)threadIdx.x / exq;
+  c.gx = x0 - HX * V + V * q;
+  c.gy = y0 - H + row;
+  const bool live = row < ey;
+  const bool in = live && c.gx >= 0 && c.gx < c.nx && c.gy >= 0 && c.gy < c.ny;
+  const bool out = in && q >= HX && q < HX + tx / V && row >= H && row < H + ty;
+  const int qm = q > 0 ? q - 1 : 0, qp = q + 1 < exq ? q + 1 : exq - 1;
+  const int rm = row > 0 ? row - 1 : 0, rp = row + 1 < ey ? row + 1 : ey - 1;
+  const int lrow = live ? row : 0;
+  const long long col = (long long)c.gx + c.sy * c.gy;   // global index at plane 0
+  auto zb = [&](int par, int s) { return zsm + (par * H + s) * plane; };
+  auto rbuf = [&](int par) { return zsm + (2 * H + par) * plane; };
+
+  const float om = sld(D.omega);
+  const float ith = CHEB ? (float)(1.0 / sld(D.cheb_theta)) : 0.f;
+  float cdd[H], cdr[H];   // Chebyshev step coefficients (the recurrence of the one-pass kernels)
+  if (CHEB) {
+    const double sigma = sld(D.cheb_sigma), delta = sld(D.cheb_delta);
+    double rho = 1.0 / sigma;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      cdd[k] = (float)(rn * rho);
+      cdr[k] = (float)(2.0 * rn / delta);
+      rho = rn;
+    }
+  }
+  const float *__restrict__ xpre = c.L.t;    // up: the pre-smoothed iterate
+  const float *__restrict__ ecrs = Cl.x;     // up: coarse correction
+  const int czf = (c.nz > 1) ? 2 : 1;        // fine planes per coarse plane
+  const int zend = min(c.nz, z0 + zc);      // output planes [z0, zend)
+  const int t0 = max(0, z0 - H);
+  const int t1 = zend - 1 + H + (DOWN ? 1 : 0);
+  const int phi0 = min(c.nz - 1, zend - 1 + H);   // last plane stage 0 works on
+
+  // pd[s]: inputs of the plane stage s works on in this iteration (t - s); pd[H + 1] is the
+  // plane below stage H's. pf: the next iteration's plane, loaded one iteration ahead.
+  using PD = PlaneData<L0, V>;
+  PD pd[H + 2];
+  Vec<V> cur_x = {};                   // up: pre-smoothed iterate of the current plane
+  float cur_e0 = 0.f, cur_e1 = 0.f;
+  auto up_loads = [&](int p, Vec<V> &xq, float &e0, float &e1) {
+    const int pc = min(max(p, 0), c.nz - 1);
+    const long long j = in ? col + c.sz * pc : 0;
+    const long long pj = in ? (long long)(c.gx >> 1) +
+                                  (long long)Cl.nx * ((c.gy >> 1) + (long long)Cl.ny * (pc / czf))
+                            : 0;
+    xq = ldv<V>(xpre + j);
+    e0 = ecrs[pj];
+    if (V == 4) e1 = ecrs[pj + 1];
+  };
+  // PF planes are in flight: one-voxel threads have little work per plane, so they keep two
+  // planes of loads ahead (the loop runs two iterations per trip, each with its own slot, so a
+  // slot is read two iterations after its loads were issued); four-voxel threads keep one.
+  constexpr int PF = (V == 1) ? 2 : 1;
+  struct UpSlot {
+    Vec<V> x;
+    float e0, e1;
+  };
+  PD pfA = load_plane<L0, V>(c, kap, in, col, t0), pfB = pfA;
+  UpSlot upA = {}, upB = {};
+  if (!DOWN) up_loads(t0, upA.x, upA.e0, upA.e1);
+  if (PF == 2) {
+    pfB = load_plane<L0, V>(c, kap, in, col, min(t0 + 1, phi0));
+    if (!DOWN) up_loads(min(t0 + 1, phi0), upB.x, upB.e0, upB.e1);
+  }
+  {
+    // the plane below the first one (its weights are the -z weights of stage 0's diagonal);
+    // clamped to plane 0, and then unused, when t0 == 0
+    const PD below = load_plane<L0, V>(c, kap, in, col, t0 - 1);
+#pragma unroll
+    for (int s = 0; s < H + 2; ++s) pd[s] = below;
+  }
+
+  // z-lines of the stencil inputs: zcv[s], zmv[s] = stage-s input at the plane stage s works on
+  // and the one below; znv[s] = what stage s-1 produced in this iteration (the plane above)
+  Vec<V> zcv[H + 1], zmv[H + 1], znv[H + 1];
+  Vec<V> sx[H + 1], sr[H + 1];      // pointwise state passed from stage s-1 to stage s
+  Vec<V> nsx[H + 1], nsr[H + 1];
+#pragma unroll
+  for (int s = 0; s <= H; ++s) {
+    zcv[s] = Vec<V>{};
+    zmv[s] = Vec<V>{};
+    znv[s] = Vec<V>{};
+    sx[s] = Vec<V>{};
+    sr[s] = Vec<V>{};
+    nsx[s] = Vec<V>{};
+    nsr[s] = Vec<V>{};
+  }
+  Vec<V> rlast = {};          // down: the residual of the plane stage H finished last iteration
+  float racc0 = 0.f, racc1 = 0.f;
+  double dot = 0.0;
+
+  auto iteration = [&](const int t, PD &pf, UpSlot &up) {
+    const int cur = t & 1, prev = cur ^ 1;
+    // this iteration's planes, with the entering plane's 1/diag; then the loads of the plane
+    // PF ahead into the slot just emptied (unconditional, the plane is clamped, so that no
+    // branch join makes them complete early)
+#pragma unroll
+    for (int s = H + 1; s > 0; --s) pd[s] = pd[s - 1];
+    pd[0] = pf;
+    pd[0].dinv = plane_dinv<L0, V>(c, pd[0], pd[1], t);
+    if (!DOWN) {
+      cur_x = up.x;
+      cur_e0 = up.e0;
+      cur_e1 = up.e1;
+    }
+    pf = load_plane<L0, V>(c, kap, in, col, min(t + PF, phi0));
+    if (!DOWN) up_loads(min(t + PF, phi0), up.x, up.e0, up.e1);
+    // ---- down: restriction of the residual finished in the previous iteration ------------
+    // (the children of a coarse cell, summed in the order of the one-pass restriction: for
+    // each of its fine planes, the row pair in y, each row's pair in x)
+    if (DOWN) {
+      const int pr = t - 1 - H;
+      const bool even_x = (V == 4) || ((c.gx & 1) == 0);
+      if (pr >= z0 && pr < zend && out && ((row - H) & 1) == 0 && even_x) {
+        const Cell *rb = rbuf(prev);
+        if constexpr (V == 4) {
+          const float4 nb = rb[rp * exq + q];
+          racc0 += rlast.v[0];
+          racc0 += rlast.v[1];
+          racc1 += rlast.v[2];
+          racc1 += rlast.v[3];
+          racc0 += nb.x;
+          racc0 += nb.y;
+          racc1 += nb.z;
+          racc1 += nb.w;
+        } else {
+          racc0 += rlast.v[0];
+          racc0 += rb[lrow * exq + qp];
+          racc0 += rb[rp * exq + q];
+          racc0 += rb[rp * exq + qp];
+        }
+        if (czf == 1 || (pr & 1)) {
+          const long long J = (long long)(c.gx >> 1) +
+                              (long long)Cl.nx * ((c.gy >> 1) + (long long)Cl.ny * (pr / czf));
+          if constexpr (V == 4) *reinterpret_cast<float2 *>(Cl.b + J) = make_float2(racc0, racc1);
+          else Cl.b[J] = racc0;
+          racc0 = 0.f;
+          racc1 = 0.f;
+        }
+      }
+    }
+    // ---- stage 0 at plane t: the first stencil input ------------------------------------
+    {
+      Vec<V> z1 = {};
+      const int p = t;
+      if (in && p <= phi0) {
+        if (DOWN) {
+          const Vec<V> &dv = pd[0].dinv;
+#pragma unroll
+          for (int e = 0; e < V; ++e) z1.v[e] = (CHEB ? ith : om) * dv.v[e] * pd[0].b.v[e];
+        } else {
+          // x' = x + P e: voxel pairs along x share one coarse parent
+          z1 = cur_x;
+#pragma unroll
+          for (int e = 0; e < V; ++e) z1.v[e] += (e < 2) ? cur_e0 : cur_e1;
+        }
+        nsx[1] = z1;                                 // x after the first sweep / step, or x'
+      }
+      znv[1] = z1;
+      if (live) zb(cur, 0)[lrow * exq + q] = to_cell<V>(z1);
+    }
+    // ---- stages 1..H at planes t-1 .. t-H ---------------------------------------------------
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+      const int p = t - s;
+      const int plo = max(0, z0 - (H - s)), phi = min(c.nz - 1, zend - 1 + (H - s));
+      const bool act = in && p >= plo && p <= phi;
+      Vec<V> znext = {};
+      if (act) {
+        const long long j = col + c.sz * p;
+        const Cell *zp_ = zb(prev, s - 1);
+        const Vec<V> ym = from_cell<V>(zp_[rm * exq + q]), yp = from_cell<V>(zp_[rp * exq + q]);
+        const float xl = last_of<V>(zp_[lrow * exq + qm]), xr = first_of<V>(zp_[lrow * exq + qp]);
+        const PD &d = pd[s];
+        const Vec<V> xc = zcv[s];
+        const Vec<V> ax = apply_stencil<L0, V>(c, d, pd[s + 1], p, xc, xl, xr, yp, ym, znv[s], zmv[s]);
+        const Vec<V> &dv = d.dinv;
+        const Vec<V> &bb = d.b;
+        if (KIND == ZM_JAC_DOWN || KIND == ZM_JAC_UP) {
+          const bool last = (s == H);
+          if (DOWN && last) {
+            // residual of the pre-smoothed iterate (xc): restricted next iteration
+            Vec<V> r;
+#pragma unroll
+            for (int e = 0; e < V; ++e) r.v[e] = bb.v[e] - ax.v[e];
+            rlast = r;
+            rbuf(cur)[lrow * exq + q] = to_cell<V>(r);
+            if (out) stv<V>(c.L.t + j, xc);
+          } else {
+            Vec<V> xn;
+#pragma unroll
+            for (int e = 0; e < V; ++e) xn.v[e] = xc.v[e] + om * dv.v[e] * (bb.v[e] - ax.v[e]);
+            if (last) {   // up: the post-smoothed iterate
+              if (out) {
+                stv<V>(c.L.x + j, xn);
+                if (want_dot) {
+                  double dq = 0.0;
+#pragma unroll
+                  for (int e = 0; e < V; ++e) dq += (double)xn.v[e] * (double)bb.v[e];
+                  dot += dq;
+                }
+              }
+            } else {
+              znext = xn;
+            }
+          }
+        } else if (KIND == ZM_CHEB_DOWN) {
+          // stage s applies the stencil to d_{s-1}; x already holds d_0 + .. + d_{s-2}
+          Vec<V> r, xn;
+          if (s == 1) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r.v[e] = bb.v[e] - ax.v[e];
+            xn = sx[1];                              // x = d_0
+          } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              xn.v[e] = sx[s].v[e] + xc.v[e];
+              r.v[e] = sr[s].v[e] - ax.v[e];
+            }
+          }
+          if (s < H) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) znext.v[e] = cdd[s - 1] * xc.v[e] + cdr[s - 1] * dv.v[e] * r.v[e];
+            nsx[s + 1] = xn;
+            nsr[s + 1] = r;
+          } else {
+            rlast = r;
+            rbuf(cur)[lrow * exq + q] = to_cell<V>(r);
+            if (out) stv<V>(c.L.t + j, xn);
+          }
+        } else {   // ZM_CHEB_UP
+          // stage 1: r = b - A x', d_0 = D^{-1} r / theta; stage s >= 2: x += d_{s-2},
+          // r -= A d_{s-2}, d_{s-1}; after the last stage x += d_{H-1} is the result
+          Vec<V> r, xn, dn;
+          if (s == 1) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              r.v[e] = bb.v[e] - ax.v[e];
+              dn.v[e] = ith * dv.v[e] * r.v[e];
+            }
+            xn = sx[1];                              // x' (the first step adds d_0 to it)
+          } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              xn.v[e] = sx[s].v[e] + xc.v[e];
+              r.v[e] = sr[s].v[e] - ax.v[e];
+              dn.v[e] = cdd[s - 2] * xc.v[e] + cdr[s - 2] * dv.v[e] * r.v[e];
+            }
+          }
+          if (s < H) {
+            znext = dn;
+            nsx[s + 1] = xn;
+            nsr[s + 1] = r;
+          } else {
+            Vec<V> xf;
+#pragma unroll
+            for (int e = 0; e < V; ++e) xf.v[e] = xn.v[e] + dn.v[e];
+            if (out) {
+              stv<V>(c.L.x + j, xf);
+              if (want_dot) {
+                double dq = 0.0;
+#pragma unroll
+                for (int e = 0; e < V; ++e) dq += (double)xf.v[e] * (double)bb.v[e];
+                dot += dq;
+              }
+            }
+          }
+        }
+      }
+      if (s < H) {
+        znv[s + 1] = znext;
+        if (live) zb(cur, s)[lrow * exq + q] = to_cell<V>(znext);
+      }
+    }
+    // ---- shift the z-lines and the passed state by one plane --------------------------------
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+      zmv[s] = zcv[s];
+      zcv[s] = znv[s];
+      sx[s] = nsx[s];
+      sr[s] = nsr[s];
+    }
+    __syncthreads();
+  };
+  if constexpr (PF == 1) {
+    for (int t = t0; t <= t1; ++t) iteration(t, pfA, upA);
+  } else {
+    for (int t = t0; t <= t1; t += 2) {
+      iteration(t, pfA, upA);
+      if (t + 1 <= t1) iteration(t + 1, pfB, upB);
+    }
+  }
+  if (!DOWN && want_dot) {
+    const double s = block_sum_any(dot);
+    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// launcher
+// ------------------------------------------------------------------------------------
+namespace {
+template <int KIND, bool L0, int V>
+void zm_dispatch(int H, dim3 g, dim3 blk, size_t smem, hipStream_t st, InstDesc *const *d, int l,
+                 int tx, int ty, int zc, int want_dot) {
+  switch (H) {
+    case 1: hipLaunchKernelGGL((k_zm<KIND, 1, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
+    case 2: hipLaunchKernelGGL((k_zm<KIND, 2, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
+    case 3: hipLaunchKernelGGL((k_zm<KIND, 3, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
+    default: hipLaunchKernelGGL((k_zm<KIND, 4, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
+  }
+}
+template <int KIND>
+void zm_dispatch_level(int H, int V, dim3 g, dim3 blk, size_t smem, hipStream_t st,
+                       InstDesc *const *d, int l, int tx, int ty, int zc, int want_dot) {
+  if (V == 4) {
+    if (l == 0) zm_dispatch<KIND, true, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+    else zm_dispatch<KIND, false, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+  } else {
+    if (l == 0) zm_dispatch<KIND, true, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+    else zm_dispatch<KIND, false, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+  }
+}
+
+int zm_exq(const ZmShape &s, int H) { return s.tx / s.v + 2 * halo_units(s.v, H); }
+int zm_threads(const ZmShape &s, int H) { return zm_exq(s, H) * (s.ty + 2 * H); }
+}  // namespace
+
+size_t zm_lds_bytes(int H, const ZmShape &s, bool down) {
+  const size_t cell = s.v == 4 ? sizeof(float4) : sizeof(float);
+  return (size_t)(2 * H + (down ? 2 : 0)) * zm_exq(s, H) * (s.ty + 2 * H) * cell;
+}
+
+long long zm_tiles(int nx, int ny, int nz, const ZmShape &s) {
+  return (long long)((nx + s.tx - 1) / s.tx) * ((ny + s.ty - 1) / s.ty) * ((nz + s.zc - 1) / s.zc);
+}
+
+ZmShape zm_shape(int nx, int ny, int nz, int H, int ty_knob, int zc_knob, int v_knob) {
+  ZmShape s;
+  // four voxels per thread on levels of a million cells and more (there the instruction count
+  // per voxel decides), one voxel per thread below (there one block's march decides)
+  s.v = v_knob ? v_knob : ((long long)nx * ny * nz >= (1LL << 20) && nx % 4 == 0 ? 4 : 1);
+  if (s.v == 4) {
+    s.tx = nx < 64 ? nx : 64;
+    s.ty = ty_knob > 0 ? ty_knob : 16;
+  } else {
+    s.tx = nx < 32 ? nx : 32;
+    s.ty = ty_knob > 0 ? ty_knob : 8;
+  }
+  if (s.ty > ny) s.ty = ny;
+  s.ty &= ~1;
+  if (s.ty < 2) s.ty = 2;
+  // at most kZmMaxThreads threads and 64 KB of LDS
+  while ((zm_threads(s, H) > zm_max_threads(s.v) || zm_lds_bytes(H, s, true) > 65536) && s.ty > 2)
+    s.ty -= 2;
+  const long long xy = (long long)((nx + s.tx - 1) / s.tx) * ((ny + s.ty - 1) / s.ty);
+  if (zc_knob > 0) {
+    s.zc = zc_knob;
+  } else {
+    // planes per block: the most of 16, 8, 4 that still gives the instance 256 blocks (a block's
+    // march takes zc + 2H iterations, so small levels take short chunks), else 2. The tile
+    // depends on the instance's own grid only (never on its batch), so the partial sums of
+    // v.p, hence the result, are the same alone and in any batch.
+    s.zc = 2;
+    for (int z = 16; z >= 4; z /= 2)
+      if (xy * ((nz + z - 1) / z) >= 256) {
+        s.zc = z;
+        break;
+      }
+  }
+  if (s.zc > nz) s.zc = nz;
+  if (nz > 1) s.zc = (s.zc + 1) & ~1;   // coarse planes never straddle two blocks
+  if (s.zc < 1) s.zc = 1;
+  return s;
+}
+
+bool zm_fits(int nx, int H, const ZmShape &s) {
+  return (s.v == 1 || s.v == 4) && nx % s.v == 0 && nx % 2 == 0 && H >= 1 && H <= 4 &&
+         s.tx % s.v == 0 && s.tx % 2 == 0 && s.tx >= s.v && s.ty >= 2 && s.zc >= 1 &&
+         zm_threads(s, H) <= zm_max_threads(s.v) && zm_lds_bytes(H, s, true) <= 65536;
+}
+
+int launch_zm(hipStream_t st, InstDesc *const *d, int B, int kind, int H, int l, int nx, int ny,
+              int nz, const ZmShape &s, int want_dot) {
+  const unsigned threads = (unsigned)((zm_threads(s, H) + 63) / 64 * 64);
+  const unsigned tiles = (unsigned)zm_tiles(nx, ny, nz, s);
+  const bool down = (kind == ZM_JAC_DOWN || kind == ZM_CHEB_DOWN);
+  const size_t smem = zm_lds_bytes(H, s, down);
+  const dim3 g(tiles, B), blk(threads);
+  switch (kind) {
+    case ZM_JAC_DOWN: zm_dispatch_level<ZM_JAC_DOWN>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
+    case ZM_JAC_UP: zm_dispatch_level<ZM_JAC_UP>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
+    case ZM_CHEB_DOWN: zm_dispatch_level<ZM_CHEB_DOWN>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
+    default: zm_dispatch_level<ZM_CHEB_UP>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
+  }
+  return (int)tiles;
+}
+
+}  // namespace plsqr
