@@ -20,7 +20,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 KERNEL_SOURCES = ["kernels.hip", "smooth_vec.hip", "blur.hip", "dense.hip", "gemm_bf16.hip",
-                  "ring.hip", "static_scratch.hip", "zmarch.hip"]
+                  "ring.hip", "static_scratch.hip", "zmarch.hip",
+                  "tail_lds.hip"]
 HOST_SOURCES = ["driver.cpp", "api.cpp"]
 HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp", "device_common.hpp"]
 

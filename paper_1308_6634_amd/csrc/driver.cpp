@@ -355,6 +355,20 @@ static int zm_depth(const InstDesc &H) {
   return (H.nu_pre == 1 && H.cheb_degree >= 1 && H.cheb_degree <= 4) ? H.cheb_degree : 0;
 }
 
+// First level of the LDS-resident tail: the first level l >= 1 with at most `cells` cells
+// (kTailCells unless tuned) such that the levels l .. coarsest fit its LDS pool; L - 1 (only the
+// coarsest solve) when there is none. Any nx will do: the tail works voxel by voxel.
+static int tail_start_lds(const Layout &Ly, int L, int cells) {
+  const long long limit = cells > 0 ? cells : kTailCells;
+  int t = L - 1;
+  for (int l = L - 2; l >= 1; --l) {
+    if (Ly.ln[l] > limit) break;
+    if (tail_lds_floats(Ly.ln + l, L - l) > kTailLdsFloats) break;
+    t = l;
+  }
+  return t;
+}
+
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
   const Layout &Ly = *bv.lay;
@@ -368,7 +382,14 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   }
   int np = 0;
   const int nu = H.nu_pre;
-  const int t = tail_start(Ly, L, H.tail_cells);
+  // the fused schedule ends in the LDS-resident tail, the per-sweep one in the tail that keeps
+  // its levels in global memory
+  const bool fused_mode = H.vcycle_mode != PLSQR_VCYCLE_PER_SWEEP;
+  const int t = fused_mode ? tail_start_lds(Ly, L, H.tail_cells) : tail_start(Ly, L, H.tail_cells);
+  auto tail = [&]() {
+    if (fused_mode) launch_vcycle_tail_lds(st, d, B, t);
+    else launch_vcycle_tail(st, d, B, t);
+  };
   // levels above the tail whose pre- and post-smoothing each run as one fused launch
   const int hz = zm_depth(H);
   ZmShape shp[kMaxLevels];
@@ -408,7 +429,7 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
       cur_l[l] = cur;
       K.restrict_to(l, cur, 0);
     }
-    launch_vcycle_tail(st, d, B, t);
+    tail();
     for (int l = t - 1; l >= 0; --l) {
       if (fz[l]) {
         const int r = zm(ZM_JAC_UP, l, l == 0 ? 1 : 0);
@@ -455,7 +476,7 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
       }
       K.restrict_to(l, LB_X, 1);
     }
-    launch_vcycle_tail(st, d, B, t);
+    tail();
     for (int l = t - 1; l >= 0; --l) {
       if (fz[l]) {
         const int r = zm(ZM_CHEB_UP, l, l == 0 ? 1 : 0);

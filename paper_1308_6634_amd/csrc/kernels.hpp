@@ -14,6 +14,8 @@ enum LevelBuf : int { LB_X = 0, LB_B, LB_R, LB_T, LB_S };
 // One-workgroup V-cycle tail: threads, and the largest level it takes over.
 constexpr int kTailBlock = 1024;
 constexpr long long kTailCells = 4096;
+// LDS-resident tail: floats of its pool (eight arrays per level: 16^3 + 8^3 + 4^3 fit)
+constexpr int kTailLdsFloats = 37888;
 
 void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n);
 void launch_outer_begin(hipStream_t st, InstDesc *const *d, int B);
@@ -62,6 +64,10 @@ void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
 // levels t .. coarsest of a V-cycle in one workgroup per instance (t >= 1; levels t .. L-2 with
 // nx % 4 == 0)
 void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
+// the same with every tail level resident in LDS (tail_lds.hip); the levels t .. coarsest must
+// need at most kTailLdsFloats floats: tail_lds_floats of their cell counts
+void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t);
+long long tail_lds_floats(const long long *cells, int nlev);
 // Fused level kernels (zmarch.hip): one launch per level and V-cycle half. ZM_*_DOWN runs the
 // whole pre-smoothing of level l from x = 0 on b_l, writes the pre-smoothed iterate to the
 // level's t buffer and the restricted residual to b_{l+1}; ZM_*_UP adds the coarse correction

@@ -56,7 +56,14 @@ CASES = [
     ((48, 16, 4), 3, "chebyshev", 1, 2, 0, 0, 0),
     ((40, 16, 8), 3, "chebyshev", 1, 4, 6, 2, 4),
     ((40, 16, 8), 3, "chebyshev", 1, 4, 6, 2, 1),
+    # four levels: the LDS-resident tail holds two smoothed levels and the coarsest, so a
+    # prolongation reads a level whose iterate is in either array of its pair
+    ((32, 32, 16), 4, "jacobi", 2, 3, 0, 0, 0),
+    ((32, 32, 16), 4, "jacobi", 1, 3, 0, 0, 4),
+    ((32, 32, 16), 4, "jacobi", 3, 3, 0, 0, 1),
+    ((32, 32, 16), 4, "chebyshev", 1, 2, 0, 0, 0),
     ((64, 48, 1), 4, "jacobi", 2, 3, 0, 0, 0),
+    ((64, 48, 1), 4, "jacobi", 1, 3, 0, 0, 0),
     ((64, 48, 1), 4, "chebyshev", 1, 3, 8, 0, 4),
     ((16, 16, 2), 2, "jacobi", 2, 3, 0, 0, 0),
     ((70, 14, 4), 2, "chebyshev", 1, 3, 0, 0, 1),
