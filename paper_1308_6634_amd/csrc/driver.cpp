@@ -39,7 +39,8 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
   if (pb.smoother == PLSQR_SMOOTH_JACOBI) {
     if (!(pb.omega > 0.0 && pb.omega <= 1.0)) return bad("Jacobi omega must be in (0, 1]");
   } else if (pb.smoother == PLSQR_SMOOTH_CHEBYSHEV) {
-    if (pb.cheb_degree < 1 || pb.cheb_degree > 16) return bad("cheb_degree must be in [1, 16]");
+    if (pb.cheb_degree < 1 || pb.cheb_degree > kMaxChebDegree)
+      return bad("cheb_degree must be in [1, 16]");
     if (!(pb.cheb_lo > 0.0 && pb.cheb_hi > pb.cheb_lo && pb.cheb_hi <= 4.0))
       return bad("Chebyshev interval must satisfy 0 < lo < hi <= 4");
   } else {
@@ -356,10 +357,12 @@ static int zm_depth(const InstDesc &H) {
 }
 
 // First level of the LDS-resident tail: the first level l >= 1 with at most `cells` cells
-// (kTailCells unless tuned) such that the levels l .. coarsest fit its LDS pool; L - 1 (only the
-// coarsest solve) when there is none. Any nx will do: the tail works voxel by voxel.
+// (kTailCells unless tuned; never more than kTailMaxPer per thread) such that the levels
+// l .. coarsest fit its LDS pool; L - 1 (only the coarsest solve) when there is none. Any nx will
+// do: the tail works voxel by voxel.
 static int tail_start_lds(const Layout &Ly, int L, int cells) {
-  const long long limit = cells > 0 ? cells : kTailCells;
+  const long long limit = std::min<long long>(cells > 0 ? cells : kTailCells,
+                                              (long long)kTailMaxPer * kTailBlock);
   int t = L - 1;
   for (int l = L - 2; l >= 1; --l) {
     if (Ly.ln[l] > limit) break;

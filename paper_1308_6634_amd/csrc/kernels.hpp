@@ -16,6 +16,10 @@ constexpr int kTailBlock = 1024;
 constexpr long long kTailCells = 4096;
 // LDS-resident tail: floats of its pool (eight arrays per level: 16^3 + 8^3 + 4^3 fit)
 constexpr int kTailLdsFloats = 37888;
+// most cells per thread on a level of the LDS-resident tail (kTailBlock threads)
+constexpr int kTailMaxPer = 4;
+// highest Chebyshev smoother degree a problem may ask for
+constexpr int kMaxChebDegree = 16;
 
 void launch_request_begin(hipStream_t st, InstDesc *const *d, int B, long long n);
 void launch_outer_begin(hipStream_t st, InstDesc *const *d, int B);

@@ -38,9 +38,23 @@ namespace plsqr {
 
 namespace {
 
-// threads per block: a four-voxel thread carries about four times the registers
-constexpr int kZmMaxThreads = 1024;
-__host__ __device__ constexpr int zm_max_threads(int V) { return V == 4 ? 512 : 1024; }
+// threads per block: a four-voxel thread carries about four times the registers; a one-voxel
+// block covers at most (32 + 2H) x (8 + 2H) columns, 640 at H = 4, which leaves a one-voxel
+// thread about 168 registers for its two planes of loads in flight
+constexpr int kZmMaxThreads = 640;
+__host__ __device__ constexpr int zm_max_threads(int V) { return V == 4 ? 512 : 640; }
+
+// Planes of loads a thread keeps in flight (see k_zm), from the register counts of the variants:
+// two where the thread holds two slots without spilling (one-voxel threads but for the coarse
+// degree-4 Chebyshev pre-smoothing, and the level-0 four-voxel variants below), else one.
+__host__ __device__ constexpr int zm_prefetch(int kind, int H, bool L0, int V) {
+  return V == 1 ? ((!L0 && kind == ZM_CHEB_DOWN && H == 4) ? 1 : 2)
+         : !L0  ? 1
+         : (kind == ZM_JAC_DOWN) ? (H <= 3 ? 2 : 1)
+         : (kind == ZM_JAC_UP)   ? 2
+         : (kind == ZM_CHEB_DOWN) ? (H <= 3 ? 2 : 1)
+                                  : (H <= 2 ? 2 : 1);
+}
 
 template <int V>
 struct Vec {
@@ -98,12 +112,31 @@ __device__ __forceinline__ float last_of(const LdsCell<V> &c) {
   else return c;
 }
 
+// A register move the compiler cannot fold away. With two prefetch slots a slot is read through
+// it when its plane is used: the slot's registers are then dead, the next loads into the slot
+// can reuse them, and the loop carries the slot without copying registers whose loads are in
+// flight (such a copy waits for every outstanding load).
+__device__ __forceinline__ float vmove(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+template <int V>
+__device__ __forceinline__ Vec<V> vmove(const Vec<V> &a) {
+  Vec<V> r;
+#pragma unroll
+  for (int e = 0; e < V; ++e) r.v[e] = vmove(a.v[e]);
+  return r;
+}
+
 // One thread's inputs at one plane, loaded once (one iteration ahead of their first use) and
 // handed down the stages in registers: the right-hand side, the face weights to the +x/+y/+z
 // neighbours (level 0: all three are kappa of the cell), the weight from the -x neighbour of
-// the first voxel and the weights from the -y neighbours (zero where the face leaves the grid),
-// and the 1/diag formed when the plane enters. The weights from the -z neighbours are the +z
-// weights of the plane below, the next entry of the same register line.
+// the first voxel and the weights from the -y neighbours (as loaded: where the face leaves the
+// grid they hold an unrelated weight, which every use masks), and the 1/diag formed when the
+// plane enters. The weights from the -z neighbours are the +z weights of the plane below, the
+// next entry of the same register line. Nothing is computed from the loaded values until the
+// plane is used, so the loads stay in flight until then.
 template <bool L0, int V>
 struct PlaneData {
   Vec<V> b, wx, wy, wz, wym, dinv;
@@ -131,7 +164,7 @@ __device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const flo
                                                        bool in, long long col, int p) {
   const int pc = min(max(p, 0), c.nz - 1);
   const long long j = in ? col + c.sz * pc : 0;
-  const bool hl = in && c.gx > 0, hy = in && c.gy > 0;
+  const bool hl = in && c.gx > 0, hy = in && c.gy > 0;   // the -x / -y faces exist
   const long long jl = hl ? j - 1 : j;
   const long long jy = hy ? j - c.sy : j;
   PlaneData<L0, V> d;
@@ -139,11 +172,8 @@ __device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const flo
   d.b = ldv<V>(c.L.b + j);
   const float *wxs = L0 ? kap : c.L.wx;
   const float *wys = L0 ? kap : c.L.wy;
-  const float xl = wxs[jl];
-  const Vec<V> ym = ldv<V>(wys + jy);
-  d.wxl = hl ? xl : 0.f;
-#pragma unroll
-  for (int e = 0; e < V; ++e) d.wym.v[e] = hy ? ym.v[e] : 0.f;
+  d.wxl = wxs[jl];
+  d.wym = ldv<V>(wys + jy);
   if constexpr (L0) {
     d.k = ldv<V>(kap + j);
   } else {
@@ -153,6 +183,27 @@ __device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const flo
     else d.wz = Vec<V>{};
   }
   return d;
+}
+
+template <bool MOVE, bool L0, int V>
+__device__ __forceinline__ PlaneData<L0, V> take_plane(const PlaneData<L0, V> &p) {
+  if constexpr (!MOVE) {
+    return p;
+  } else {
+    PlaneData<L0, V> d;
+    d.b = vmove<V>(p.b);
+    if constexpr (L0) {
+      d.k = vmove<V>(p.k);
+    } else {
+      d.wx = vmove<V>(p.wx);
+      d.wy = vmove<V>(p.wy);
+      d.wz = vmove<V>(p.wz);
+    }
+    d.wym = vmove<V>(p.wym);
+    d.wxl = vmove(p.wxl);
+    d.dinv = Vec<V>{};
+    return d;
+  }
 }
 
 // 1/diag at plane p (below: the plane under it). Level 0 assembles it from kappa in the order
@@ -187,18 +238,19 @@ __device__ __forceinline__ Vec<V> plane_dinv(const ZmCtx &c, const PlaneData<L0,
 
 // (A_l x) at plane p, with the neighbour values given: xl/xr the x-neighbours of the first and
 // last voxel, yp/ym/zp/zm the neighbouring rows and planes. The faces are added in the order of
-// stencil4. Faces that leave the grid are skipped; where a weight loaded for such a face is
-// already zero (the -x face of the grid's first voxel, the -y faces) the term is added anyway,
-// which changes nothing but the sign of a zero sum. The z faces depend only on the plane, so
-// they are tested once (a uniform branch).
+// stencil4. Faces that leave the grid are skipped; for the -x face of the grid's first voxel and
+// the -y faces the term is added anyway with the weight masked to zero, which changes nothing
+// but the sign of a zero sum. The z faces depend only on the plane, so they are tested once (a
+// uniform branch).
 template <bool L0, int V>
 __device__ __forceinline__ Vec<V> apply_stencil(const ZmCtx &c, const PlaneData<L0, V> &d,
                                                 const PlaneData<L0, V> &below, int p,
                                                 const Vec<V> &xc, float xl, float xr,
                                                 const Vec<V> &yp, const Vec<V> &ym,
                                                 const Vec<V> &zp, const Vec<V> &zm) {
-  const bool hyp = c.gy + 1 < c.ny, hzp = p + 1 < c.nz, hzm = p > 0;
+  const bool hyp = c.gy + 1 < c.ny, hym = c.gy > 0, hzp = p + 1 < c.nz, hzm = p > 0;
   const bool hxr = c.gx + V < c.nx;            // +x face of the last voxel
+  const bool hxl = c.gx > 0;                   // -x face of the first voxel
   Vec<V> acc;
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -216,9 +268,9 @@ __device__ __forceinline__ Vec<V> apply_stencil(const ZmCtx &c, const PlaneData<
       wm = (e > 0) ? d.wx.v[e > 0 ? e - 1 : 0] : d.wxl;
     }
     if (e < V - 1 || hxr) a += wxp * (xj - xnext);
-    a += wm * (xj - xprev);                     // zero weight at the grid's -x edge
+    a += (e > 0 || hxl ? wm : 0.f) * (xj - xprev);   // zero weight at the grid's -x edge
     if (hyp) a += wyp * (xj - yp.v[e]);
-    a += d.wym.v[e] * (xj - ym.v[e]);           // zero weight at the grid's -y edge
+    a += (hym ? d.wym.v[e] : 0.f) * (xj - ym.v[e]);  // zero weight at the grid's -y edge
     acc.v[e] = a;
   }
   if (L0 || c.nz > 1) {
@@ -350,27 +402,29 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
     e0 = ecrs[pj];
     if (V == 4) e1 = ecrs[pj + 1];
   };
-  // PF planes are in flight: one-voxel threads have little work per plane, so they keep two
-  // planes of loads ahead (the loop runs two iterations per trip, each with its own slot, so a
-  // slot is read two iterations after its loads were issued); four-voxel threads keep one.
-  constexpr int PF = (V == 1) ? 2 : 1;
+  // PF planes are in flight (the loop runs two iterations per trip, each with its own slot, so
+  // a slot is read two iterations after its loads were issued); one where two slots would not
+  // fit the registers of a four-voxel thread without spilling (a spill reload in the loop would
+  // wait for the loads issued before it).
+  constexpr int PF = zm_prefetch(KIND, H, L0, V);
   struct UpSlot {
     Vec<V> x;
     float e0, e1;
   };
+  {
+    // the plane below the first one (its weights are the -z weights of stage 0's diagonal);
+    // clamped to plane 0, and then unused, when t0 == 0. Loaded first: the first iteration
+    // needs it and slot A, the second slot B.
+    const PD below = load_plane<L0, V>(c, kap, in, col, t0 - 1);
+#pragma unroll
+    for (int s = 0; s < H + 2; ++s) pd[s] = below;
+  }
   PD pfA = load_plane<L0, V>(c, kap, in, col, t0), pfB = pfA;
   UpSlot upA = {}, upB = {};
   if (!DOWN) up_loads(t0, upA.x, upA.e0, upA.e1);
   if (PF == 2) {
     pfB = load_plane<L0, V>(c, kap, in, col, min(t0 + 1, phi0));
     if (!DOWN) up_loads(min(t0 + 1, phi0), upB.x, upB.e0, upB.e1);
-  }
-  {
-    // the plane below the first one (its weights are the -z weights of stage 0's diagonal);
-    // clamped to plane 0, and then unused, when t0 == 0
-    const PD below = load_plane<L0, V>(c, kap, in, col, t0 - 1);
-#pragma unroll
-    for (int s = 0; s < H + 2; ++s) pd[s] = below;
   }
 
   // z-lines of the stencil inputs: zcv[s], zmv[s] = stage-s input at the plane stage s works on
@@ -399,12 +453,18 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
     // branch join makes them complete early)
 #pragma unroll
     for (int s = H + 1; s > 0; --s) pd[s] = pd[s - 1];
-    pd[0] = pf;
+    pd[0] = take_plane<PF == 2, L0, V>(pf);
     pd[0].dinv = plane_dinv<L0, V>(c, pd[0], pd[1], t);
     if (!DOWN) {
-      cur_x = up.x;
-      cur_e0 = up.e0;
-      cur_e1 = up.e1;
+      if constexpr (PF == 2) {
+        cur_x = vmove<V>(up.x);
+        cur_e0 = vmove(up.e0);
+        if (V == 4) cur_e1 = vmove(up.e1);
+      } else {
+        cur_x = up.x;
+        cur_e0 = up.e0;
+        cur_e1 = up.e1;
+      }
     }
     pf = load_plane<L0, V>(c, kap, in, col, min(t + PF, phi0));
     if (!DOWN) up_loads(min(t + PF, phi0), up.x, up.e0, up.e1);
@@ -588,10 +648,14 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   if constexpr (PF == 1) {
     for (int t = t0; t <= t1; ++t) iteration(t, pfA, upA);
   } else {
-    for (int t = t0; t <= t1; t += 2) {
+    // pairs of iterations, then an odd last one outside the loop: every path back to the loop
+    // head has issued slot B's loads after slot A's, so the head waits for slot A only
+    int t = t0;
+    for (; t + 1 <= t1; t += 2) {
       iteration(t, pfA, upA);
-      if (t + 1 <= t1) iteration(t + 1, pfB, upB);
+      iteration(t + 1, pfB, upB);
     }
+    if (t <= t1) iteration(t, pfA, upA);
   }
   if (!DOWN && want_dot) {
     const double s = block_sum_any(dot);
@@ -653,7 +717,7 @@ ZmShape zm_shape(int nx, int ny, int nz, int H, int ty_knob, int zc_knob, int v_
   if (s.ty > ny) s.ty = ny;
   s.ty &= ~1;
   if (s.ty < 2) s.ty = 2;
-  // at most kZmMaxThreads threads and 64 KB of LDS
+  // at most zm_max_threads threads and 64 KB of LDS
   while ((zm_threads(s, H) > zm_max_threads(s.v) || zm_lds_bytes(H, s, true) > 65536) && s.ty > 2)
     s.ty -= 2;
   const long long xy = (long long)((nx + s.tx - 1) / s.tx) * ((ny + s.ty - 1) / s.ty);
