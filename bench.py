@@ -273,7 +273,7 @@ def main():
                     help="c1-c3: solves issued one at a time after the timed run for the p50/p99 "
                          "solve latency (0: skip)")
     ap.add_argument("--requests", type=int, default=2000, help="c5 only: requests in the stream")
-    ap.add_argument("--templates", type=int, default=40,
+    ap.add_argument("--templates", type=int, default=200,
                     help="c5 only: distinct pre-generated reconstructions the stream cycles through")
     ap.add_argument("--plain-requests", type=int, default=300,
                     help="c5 only: prefix of the stream replayed on the plain one-at-a-time path")
@@ -637,14 +637,15 @@ def bench_c4(args):
     settings = {}
     if not args.no_tune:
         # V-cycle launch schedule for this batch, by the V-cycle phase time of a short batch
+        # (8 V-cycles per trial, the better of two runs)
         from paper_1308_6634_amd import autotune
-        short = [dataclasses.replace(p, outer=1, inner=2) for p in probs]
+        short = [dataclasses.replace(p, outer=1, inner=8) for p in probs]
 
         def vcycle_ms(vs):
             res = run_batch([problem_struct(p, flags=P.PLSQR_FLAG_TIME_PHASES, precision=prec,
                                             knobs=vs) for p in short])
             return res[0][1].vcycle_ms
-        settings, _ = autotune.tune_vcycle(vcycle_ms, repeats=1)
+        settings, _ = autotune.tune_vcycle(vcycle_ms, repeats=2)
         print(f"[bench] autotuned V-cycle: {settings}", file=sys.stderr, flush=True)
     settings.update(args.knobs)
     pbs = [problem_struct(p, precision=prec, knobs=settings) for p in probs]
@@ -827,7 +828,8 @@ def _replay(eng, arrivals, reqs, poll_sleep=0.002):
             if st != 1:
                 # latency from the scheduled arrival (a late submit counts against the path)
                 t_end = t_sub[i] + (res.submit_to_done_ms / 1e3 if res is not None else 0.0)
-                done[i] = ((t_end - (t0 + arrivals[i])) * 1e3, st, t_end)
+                mixed = res.mixed_steps if res is not None else 0
+                done[i] = ((t_end - (t0 + arrivals[i])) * 1e3, st, t_end, mixed)
                 remaining.discard(i)
         time.sleep(poll_sleep)
     th.join()
@@ -878,6 +880,9 @@ def bench_c5(args):
     assert all(d[1] == 0 for d in done)
     total = sum(work[i % NT] for i in range(N))
     served_value = total / span
+    # inner steps that ran in launches shared with requests of other grids
+    mixed_share = sum(d[3] for d in done) / sum(temps[i % NT].outer * temps[i % NT].inner
+                                                for i in range(N))
 
     plain = Engine(0, hbm_budget_bytes=200 * 10**9)
     M = min(args.plain_requests, N)
@@ -893,7 +898,8 @@ def bench_c5(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "config": {"workload": f"c5: {desc}"},
         "served": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "requests": N, "span_s": span, "voxel_iters_per_s": served_value},
+                   "requests": N, "span_s": span, "voxel_iters_per_s": served_value,
+                   "mixed_grid_step_share": mixed_share},
         "plain": {"p50_ms": float(np.percentile(plat, 50)), "p99_ms": float(np.percentile(plat, 99)),
                   "requests": M, "span_s": pspan, "voxel_iters_per_s": ptotal / pspan},
         "served_over_plain_throughput": served_value / (ptotal / pspan),

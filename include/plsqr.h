@@ -222,7 +222,8 @@ typedef struct {
   int32_t status;                     /* PLSQR_OK or the request's error code */
   int32_t outer_done;                 /* outer iterations run (< outer after an outer stop) */
   int32_t levels;                     /* multigrid levels used */
-  int32_t reserved0;
+  int32_t mixed_steps;                /* serving mode: inner steps that ran in launches shared
+                                         with requests of other grids */
   int32_t inner_done[PLSQR_MAX_OUTER];/* MLSQR steps completed per outer iteration
                                          (< inner after an S4 or exact-termination stop) */
   double resid[PLSQR_MAX_OUTER];      /* ||g - A f^k|| per outer iteration k */

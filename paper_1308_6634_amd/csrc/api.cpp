@@ -155,6 +155,7 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
     if (l > 0) eps_l *= (Ly.lnz[l - 1] > 1) ? 8.0 : 4.0;
     L.eps = eps_l;
   }
+  plan_vcycle(D, Ly);
   (void)eng;
 }
 
@@ -371,6 +372,7 @@ void fill_records(const Request &r, const double *sc, const double *dg, plsqr_re
   // SC_OUTER counts the outer steps run (it stops advancing once the outer stop fired)
   res.outer_done = std::max(0, std::min(r.pb.outer, (int)sc[SC_OUTER]));
   res.levels = r.lay.levels;
+  res.mixed_steps = r.mixed_steps;
   for (int k = 1; k <= res.outer_done; ++k) {
     res.resid[k - 1] = dg[(size_t)k * DG_COUNT + DG_RESID];
     res.penalty[k - 1] = dg[(size_t)k * DG_COUNT + DG_PENALTY];
@@ -622,22 +624,63 @@ void serve_fail_resident(plsqr_engine *eng, int rc, const std::string &msg) {
 }
 
 // Build and enqueue one tick. Caller holds the lock.
+// What every instance of one ragged launch shares: the smoother schedule (the fused kernels'
+// variant), the stop flags (epilogue masks) and the blur launch knobs (kernel variants).
+struct RagKey {
+  int smoother, nu, deg, stop, win, xg;
+  bool operator<(const RagKey &o) const {
+    return std::tie(smoother, nu, deg, stop, win, xg) <
+           std::tie(o.smoother, o.nu, o.deg, o.stop, o.win, o.xg);
+  }
+};
+
 void serve_tick(plsqr_engine *eng) {
   std::map<ClassKey, std::vector<Request *>> groups;
-  for (uint64_t t : eng->resident) {
-    Request &r = *eng->reqs[t];
+  // inner steps that can share launches across grids, by what such launches must share
+  std::map<RagKey, std::vector<Request *>> rag_groups;
+  auto class_key = [](const Request &r) {
     const plsqr_problem &pb = r.pb;
     // in serving mode `group` holds the operator id
     const int op_key = r.host.op_kind == PLSQR_OP_BLUR ? -1 : (int)r.group;
-    ClassKey key{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
-                 r.host.op_kind, step_type(pb, r.step),
-                 (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)), op_key,
-                 pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window, pb.tune_blur_xgroups,
-                 pb.tune_vcycle, pb.tune_zm_ty, pb.tune_zm_zc, pb.tune_zm_v, pb.tune_tail_cells};
-    groups[key].push_back(&r);
+    return ClassKey{pb.nx, pb.ny, pb.nz, r.lay.levels, pb.smoother, pb.nu_pre, pb.cheb_degree,
+                    r.host.op_kind, step_type(pb, r.step),
+                    (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)), op_key,
+                    pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window,
+                    pb.tune_blur_xgroups, pb.tune_vcycle, pb.tune_zm_ty, pb.tune_zm_zc,
+                    pb.tune_zm_v, pb.tune_tail_cells};
+  };
+  for (uint64_t t : eng->resident) {
+    Request &r = *eng->reqs[t];
+    const plsqr_problem &pb = r.pb;
+    if (step_type(pb, r.step) == ST_INNER && ragged_ok(r.host, r.lay)) {
+      RagKey rk{pb.smoother, pb.nu_pre, pb.cheb_degree,
+                (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)),
+                pb.tune_blur_window, pb.tune_blur_xgroups};
+      rag_groups[rk].push_back(&r);
+      continue;
+    }
+    groups[class_key(r)].push_back(&r);
+  }
+  // a ragged group of one class runs as a uniform batch; one of several classes runs in shared
+  // launches, kMaxRag instances at a time
+  std::vector<std::vector<Request *>> rag_chunks;
+  rag_chunks.reserve(eng->resident.size());
+  for (auto &kv : rag_groups) {
+    std::vector<Request *> &mem = kv.second;
+    bool one_class = true;
+    for (Request *r : mem) one_class = one_class && !(class_key(*r) < class_key(*mem[0])) &&
+                                       !(class_key(*mem[0]) < class_key(*r));
+    if (one_class) {
+      std::vector<Request *> &g = groups[class_key(*mem[0])];
+      g.insert(g.end(), mem.begin(), mem.end());
+      continue;
+    }
+    for (size_t i = 0; i < mem.size(); i += kMaxRag)
+      rag_chunks.emplace_back(mem.begin() + i, mem.begin() + std::min(mem.size(), i + kMaxRag));
   }
   plsqr_engine::TickSlot &slot = eng->ring[eng->ring_next];
-  const size_t need = eng->resident.size() * sizeof(void *) + groups.size() * 256;
+  const size_t need =
+      eng->resident.size() * sizeof(void *) + (groups.size() + rag_chunks.size()) * 256;
   if (slot.cap < need) {
     // the slot's last tick has finished: at most max_inflight_ticks (< ring size) are queued
     if (slot.pinned) hipHostFree(slot.pinned);
@@ -657,14 +700,21 @@ void serve_tick(plsqr_engine *eng) {
     slot.cap = cap;
   }
   size_t off = 0;
-  std::vector<std::pair<size_t, std::vector<Request *> *>> plan;
-  for (auto &kv : groups) {
+  struct PlanItem {
+    size_t off;
+    std::vector<Request *> *mem;
+    bool ragged;
+  };
+  std::vector<PlanItem> plan;
+  auto place = [&](std::vector<Request *> &mem, bool ragged) {
     off = (off + 255) / 256 * 256;
     InstDesc **dst = reinterpret_cast<InstDesc **>(slot.pinned + off);
-    for (size_t i = 0; i < kv.second.size(); ++i) dst[i] = kv.second[i]->d_desc;
-    plan.emplace_back(off, &kv.second);
-    off += kv.second.size() * sizeof(void *);
-  }
+    for (size_t i = 0; i < mem.size(); ++i) dst[i] = mem[i]->d_desc;
+    plan.push_back(PlanItem{off, &mem, ragged});
+    off += mem.size() * sizeof(void *);
+  };
+  for (auto &c : rag_chunks) place(c, true);
+  for (auto &kv : groups) place(kv.second, false);
   hipMemcpyAsync(slot.dev, slot.pinned, off, hipMemcpyHostToDevice, eng->stream);
   hipEventRecord(eng->ev_upload, eng->stream);
   // subgroups run concurrently on the worker streams; each waits for the upload (which is
@@ -680,19 +730,30 @@ void serve_tick(plsqr_engine *eng) {
       hipStreamWaitEvent(ls, eng->ev_upload, 0);
       used[li] = true;
     }
-    std::vector<Request *> &mem = *pl.second;
+    std::vector<Request *> &mem = *pl.mem;
     Request &r0 = *mem[0];
-    BatchView bv{reinterpret_cast<InstDesc *const *>(slot.dev + pl.first), (int)mem.size(),
-                 &r0.host, &r0.lay, nullptr, nullptr, nullptr};
-    switch (step_type(r0.pb, r0.step)) {
-      case ST_BEGIN: enqueue_request_begin(ls, bv); break;
-      case ST_OUTER_START:
-        enqueue_outer_setup(ls, bv);
-        enqueue_mlsqr_init(ls, bv);
-        break;
-      case ST_INNER: enqueue_inner(ls, bv); break;
-      case ST_OUTER_END: enqueue_outer_end(ls, bv); break;
-      default: enqueue_request_end(ls, bv); break;
+    InstDesc *const *dd = reinterpret_cast<InstDesc *const *>(slot.dev + pl.off);
+    if (pl.ragged) {
+      const InstDesc *hs[kMaxRag];
+      const Layout *ls_[kMaxRag];
+      for (size_t i = 0; i < mem.size(); ++i) {
+        hs[i] = &mem[i]->host;
+        ls_[i] = &mem[i]->lay;
+        ++mem[i]->mixed_steps;
+      }
+      enqueue_inner_ragged(ls, RagBatch{dd, (int)mem.size(), hs, ls_});
+    } else {
+      BatchView bv{dd, (int)mem.size(), &r0.host, &r0.lay, nullptr, nullptr, nullptr};
+      switch (step_type(r0.pb, r0.step)) {
+        case ST_BEGIN: enqueue_request_begin(ls, bv); break;
+        case ST_OUTER_START:
+          enqueue_outer_setup(ls, bv);
+          enqueue_mlsqr_init(ls, bv);
+          break;
+        case ST_INNER: enqueue_inner(ls, bv); break;
+        case ST_OUTER_END: enqueue_outer_end(ls, bv); break;
+        default: enqueue_request_end(ls, bv); break;
+      }
     }
     for (Request *r : mem) {
       if (++r->step == r->steps_total) {

@@ -66,10 +66,11 @@ __device__ __forceinline__ void epilogue4(const InstDesc &D, int epi, long long 
   }
 }
 
-__device__ __forceinline__ void block_partial(const InstDesc &D, int epi, double dot) {
+// The block's partial (bx: the block's index within its instance).
+__device__ __forceinline__ void block_partial(const InstDesc &D, int epi, double dot, int bx) {
   if (epi == EPI_FWD || epi == EPI_RESID) {
     dot = block_sum(dot);
-    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
+    if (threadIdx.x == 0) sld(D.part)[bx] = dot;
   }
 }
 
@@ -234,14 +235,16 @@ __device__ __forceinline__ void xg_outputs(const float *__restrict__ src, const 
 
 template <int kXG>
 __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int src_sel,
-                                                   int dst_sel, int adj, int epi) {
-  const InstDesc &D = inst(descs);
+                                                   int dst_sel, int adj, int epi, Rag rg) {
+  const Blk k = locate(rg);
+  if (k.i < 0) return;
+  const InstDesc &D = *descs[k.i];
   if (product_masked(D, epi)) return;
   const int r = sld(D.radius);
   const int nx = sld(D.nx);
   const long long n = sld(D.n);
   const int tpr = (nx + 4 * kXG - 1) / (4 * kXG);          // threads per row
-  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long t = (long long)k.bx * kBlock + threadIdx.x;
   const long long rows = n / nx;
   double dot = 0.0;
   if (t < rows * tpr) {
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int 
     for (int g = 0; g < kXG; ++g)
       if (x0 + 4 * g < nx) epilogue4(D, epi, rowbase + x0 + 4 * g, y[g], dst, dot);
   }
-  block_partial(D, epi, dot);
+  block_partial(D, epi, dot, k.bx);
 }
 
 // y or z pass with a register window (any nx): every thread owns one column element (x and the
@@ -314,8 +317,11 @@ __device__ __forceinline__ double win_outputs(const InstDesc &D, int epi,
 
 template <int kWinS>
 __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int axis,
-                                                    int src_sel, int dst_sel, int adj, int epi) {
-  const InstDesc &D = inst(descs);
+                                                    int src_sel, int dst_sel, int adj, int epi,
+                                                    Rag rg) {
+  const Blk k = locate(rg);
+  if (k.i < 0) return;
+  const InstDesc &D = *descs[k.i];
   if (product_masked(D, epi)) return;
   const int r = sld(D.radius);
   const int nx = sld(D.nx), ny = sld(D.ny), nz = sld(D.nz);
@@ -327,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int
   const long long total = (long long)nx * segs * no;
   // consecutive segments of a line share 2R halo lines: xcd_tile keeps consecutive blocks on
   // one XCD, so the halo is re-read from that XCD's L2
-  const long long t = xcd_tile() * kBlock + threadIdx.x;
+  const long long t = xcd_tile_of(k) * kBlock + threadIdx.x;
   double dot = 0.0;
   if (t < total) {
     const int x = (int)(t % nx);
@@ -343,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int
     PLSQR_RADIUS_SWITCH(r, PLSQR_WIN)
 #undef PLSQR_WIN
   }
-  block_partial(D, epi, dot);
+  block_partial(D, epi, dot, k.bx);
 }
 
 // ------------------------------------------------------------------------------------
@@ -358,38 +364,55 @@ __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int
 constexpr int kDefaultXGroups = 2;
 constexpr int kDefaultWindow = 8;
 
-int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups) {
-  if (nx % 4 == 0) {
-    const int G = groups ? groups : kDefaultXGroups;
-    const long long threads = n / nx * ((nx + 4 * G - 1) / (4 * G));
-    const unsigned g = (unsigned)((threads + kBlock - 1) / kBlock);
-    if (G == 1)
-      LAUNCH_B(k_blur_xg<1>, g, B, d, src, dst, adj, epi);
-    else if (G == 2)
-      LAUNCH_B(k_blur_xg<2>, g, B, d, src, dst, adj, epi);
-    else
-      LAUNCH_B(k_blur_xg<4>, g, B, d, src, dst, adj, epi);
-    return (int)g;
-  }
-  const unsigned g = (unsigned)((n + kXTile - 1) / kXTile);
-  LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);
-  return (int)g;
+int blur_x_blocks(long long n, int nx, int groups) {
+  if (nx % 4 != 0) return (int)((n + kXTile - 1) / kXTile);
+  const int G = groups ? groups : kDefaultXGroups;
+  const long long threads = n / nx * ((nx + 4 * G - 1) / (4 * G));
+  return (int)((threads + kBlock - 1) / kBlock);
 }
-int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                     int src, int dst, int adj, int epi, int window) {
+int blur_axis_blocks(int nx, int ny, int nz, int axis, int window) {
   const int S = window ? window : kDefaultWindow;
   const int na = (axis == 1) ? ny : nz, no = (axis == 1) ? nz : ny;
   const long long threads = (long long)nx * ((na + S - 1) / S) * no;
-  const unsigned g = (unsigned)((threads + kBlock - 1) / kBlock);
+  return (int)((threads + kBlock - 1) / kBlock);
+}
+
+// Grid of a launch: (g, B) for a uniform launch, (the ragged map's extent, 1) for a ragged one.
+static dim3 grid_of(unsigned g, int B, const Rag &rg) {
+  if (rg.n == 0) return dim3(g, B);
+  return dim3((unsigned)(rg.first[rg.n - 1] + rg.count[rg.n - 1]), 1);
+}
+
+int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
+                  int adj, int epi, int groups, const Rag &rg) {
+  const unsigned g = (unsigned)blur_x_blocks(n, nx, groups);
+  const dim3 grid = grid_of(g, B, rg);
+  if (nx % 4 == 0) {
+    const int G = groups ? groups : kDefaultXGroups;
+    if (G == 1)
+      hipLaunchKernelGGL(k_blur_xg<1>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+    else if (G == 2)
+      hipLaunchKernelGGL(k_blur_xg<2>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+    else
+      hipLaunchKernelGGL(k_blur_xg<4>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+    return (int)g;
+  }
+  LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);   // uniform launches only (see the driver)
+  return (int)g;
+}
+int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
+                     int src, int dst, int adj, int epi, int window, const Rag &rg) {
+  const int S = window ? window : kDefaultWindow;
+  const unsigned g = (unsigned)blur_axis_blocks(nx, ny, nz, axis, window);
+  const dim3 grid = grid_of(g, B, rg);
   if (S == 4)
-    LAUNCH_B(k_blur_win<4>, g, B, d, axis, src, dst, adj, epi);
+    hipLaunchKernelGGL(k_blur_win<4>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
   else if (S == 8)
-    LAUNCH_B(k_blur_win<8>, g, B, d, axis, src, dst, adj, epi);
+    hipLaunchKernelGGL(k_blur_win<8>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
   else if (S == 32)
-    LAUNCH_B(k_blur_win<32>, g, B, d, axis, src, dst, adj, epi);
+    hipLaunchKernelGGL(k_blur_win<32>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
   else
-    LAUNCH_B(k_blur_win<16>, g, B, d, axis, src, dst, adj, epi);
+    hipLaunchKernelGGL(k_blur_win<16>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
   return (int)g;
 }
 

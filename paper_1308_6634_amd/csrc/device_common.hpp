@@ -26,6 +26,27 @@ __device__ __forceinline__ long long xcd_tile() {
   return (long long)(b % 8u) * (nb / 8u) + b / 8u;
 }
 
+// This block's instance (index into the descriptor array; -1: a block between the ranges of a
+// ragged launch), its block index within the instance and the instance's block count.
+struct Blk {
+  int i, bx, gx;
+};
+__device__ __forceinline__ Blk locate(const Rag &rg) {
+  if (rg.n == 0) return Blk{(int)blockIdx.y, (int)blockIdx.x, (int)gridDim.x};
+  const int b = blockIdx.x;
+  Blk k{-1, 0, 0};
+  for (int e = 0; e < rg.n; ++e)
+    if (b >= rg.first[e] && b < rg.first[e] + rg.count[e]) k = Blk{rg.inst[e], b - rg.first[e], rg.count[e]};
+  return k;
+}
+// xcd_tile for a block of a possibly ragged launch (an instance's range starts at a multiple of
+// 8, so its block bx sits on XCD bx % 8 as in a uniform launch).
+__device__ __forceinline__ long long xcd_tile_of(const Blk &k) {
+  const unsigned b = k.bx, nb = k.gx;
+  if (nb % 8u != 0u) return b;
+  return (long long)(b % 8u) * (nb / 8u) + b / 8u;
+}
+
 // Uniform read of a descriptor field through the scalar cache. Descriptors are written by the
 // host before the kernels that read them and never by a kernel, so they can be read as
 // constant memory: one scalar load into SGPRs instead of a vector load per lane (which would

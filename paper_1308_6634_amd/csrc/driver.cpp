@@ -372,6 +372,43 @@ static int tail_start_lds(const Layout &Ly, int L, int cells) {
   return t;
 }
 
+// How a V-cycle of this instance runs (levels >= 2): the first tail level, the depth of the
+// fused level kernels, and for each level above the tail its fused tile (fz: whether it runs
+// fused).
+struct VcPlan {
+  int t, hz;
+  ZmShape shp[kMaxLevels];
+  bool fz[kMaxLevels];
+};
+static VcPlan vcycle_plan(const InstDesc &H, const Layout &Ly) {
+  VcPlan P{};
+  const int L = H.levels;
+  // the fused schedule ends in the LDS-resident tail, the per-sweep one in the tail that keeps
+  // its levels in global memory
+  const bool fused_mode = H.vcycle_mode != PLSQR_VCYCLE_PER_SWEEP;
+  P.t = fused_mode ? tail_start_lds(Ly, L, H.tail_cells) : tail_start(Ly, L, H.tail_cells);
+  // levels above the tail whose pre- and post-smoothing each run as one fused launch
+  P.hz = zm_depth(H);
+  for (int l = 0; l < P.t; ++l) {
+    P.shp[l] = zm_shape(Ly.lnx[l], Ly.lny[l], Ly.lnz[l], P.hz > 0 ? P.hz : 1, H.zm_ty, H.zm_zc,
+                        H.zm_v);
+    P.fz[l] = P.hz > 0 && zm_fits(Ly.lnx[l], P.hz, P.shp[l]);
+  }
+  // level 0's up kernel writes one alpha partial per block into the instance's partials
+  if (P.fz[0] && zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], P.shp[0]) > Ly.nparts) P.fz[0] = false;
+  return P;
+}
+
+void plan_vcycle(InstDesc &D, const Layout &Ly) {
+  for (int l = 0; l < kMaxLevels; ++l) D.zmp[l] = ZmPlan{0, 0, 0, 0};
+  D.tail_lds_t = 0;
+  if (D.levels < 2) return;
+  const VcPlan P = vcycle_plan(D, Ly);
+  D.tail_lds_t = P.t;
+  for (int l = 0; l < P.t; ++l)
+    if (P.fz[l]) D.zmp[l] = ZmPlan{P.shp[l].tx, P.shp[l].ty, P.shp[l].zc, P.shp[l].v};
+}
+
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
   const Layout &Ly = *bv.lay;
@@ -385,24 +422,15 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   }
   int np = 0;
   const int nu = H.nu_pre;
-  // the fused schedule ends in the LDS-resident tail, the per-sweep one in the tail that keeps
-  // its levels in global memory
   const bool fused_mode = H.vcycle_mode != PLSQR_VCYCLE_PER_SWEEP;
-  const int t = fused_mode ? tail_start_lds(Ly, L, H.tail_cells) : tail_start(Ly, L, H.tail_cells);
+  const VcPlan P = vcycle_plan(H, Ly);
+  const int t = P.t, hz = P.hz;
+  const ZmShape *shp = P.shp;
+  const bool *fz = P.fz;
   auto tail = [&]() {
     if (fused_mode) launch_vcycle_tail_lds(st, d, B, t);
     else launch_vcycle_tail(st, d, B, t);
   };
-  // levels above the tail whose pre- and post-smoothing each run as one fused launch
-  const int hz = zm_depth(H);
-  ZmShape shp[kMaxLevels];
-  bool fz[kMaxLevels] = {};
-  for (int l = 0; l < t; ++l) {
-    shp[l] = zm_shape(Ly.lnx[l], Ly.lny[l], Ly.lnz[l], hz > 0 ? hz : 1, H.zm_ty, H.zm_zc, H.zm_v);
-    fz[l] = hz > 0 && zm_fits(Ly.lnx[l], hz, shp[l]);
-  }
-  // level 0's up kernel writes one alpha partial per block into the instance's partials
-  if (fz[0] && zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], shp[0]) > Ly.nparts) fz[0] = false;
   auto zm = [&](int kind, int l, int want) {
     return launch_zm(st, d, B, kind, hz, l, Ly.lnx[l], Ly.lny[l], Ly.lnz[l], shp[l], want);
   };
@@ -559,6 +587,110 @@ void enqueue_inner(hipStream_t st, const BatchView &bv) {
   launch_update_fw(st, bv.d_descs, bv.B, H.n);
   enqueue_s4(st, bv);
   if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
+}
+
+// ---------------------------------------------------------------------------------
+// inner steps of instances of different grids in shared launches
+// ---------------------------------------------------------------------------------
+bool ragged_ok(const InstDesc &H, const Layout &Ly) {
+  if (H.op_kind != PLSQR_OP_BLUR || H.nz < 2 || H.ny < 2 || H.nx % 4 != 0) return false;
+  if (H.n_tau > 0 || (H.stop_flags & PLSQR_FLAG_STOP_S4) || H.levels < 2) return false;
+  if (H.vcycle_mode == PLSQR_VCYCLE_PER_SWEEP) return false;
+  const VcPlan P = vcycle_plan(H, Ly);
+  for (int l = 0; l < P.t; ++l)
+    if (!P.fz[l]) return false;
+  return true;
+}
+
+namespace {
+// A ragged map over the instances `who` (indices into the batch), count(i) blocks each, every
+// range starting at a multiple of 8.
+template <class F>
+Rag rag_over(const std::vector<int> &who, F count) {
+  Rag r{};
+  r.n = (int)who.size();
+  int off = 0;
+  for (int k = 0; k < r.n; ++k) {
+    r.inst[k] = who[k];
+    r.first[k] = off;
+    r.count[k] = count(who[k]);
+    off = (off + r.count[k] + 7) / 8 * 8;
+  }
+  return r;
+}
+}  // namespace
+
+void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
+  const int B = rb.B;
+  InstDesc *const *d = rb.d_descs;
+  const InstDesc &H0 = *rb.h[0];
+  std::vector<int> all(B);
+  for (int i = 0; i < B; ++i) all[i] = i;
+  auto h = [&](int i) -> const InstDesc & { return *rb.h[i]; };
+  // blur product: x, y, z passes, the last with the epilogue; returns the last pass's map
+  auto blur = [&](int src, int adj, int epi) {
+    const int em = with_mask(H0, epi);
+    const int e_mid = EPI_STORE | (em & (EPI_MASK_INNER | EPI_MASK_OUTER));
+    const Rag rx = rag_over(all, [&](int i) { return blur_x_blocks(h(i).n, h(i).nx, H0.blur_xgroups); });
+    launch_blur_x(st, d, B, H0.n, H0.nx, src, V_TMP1, adj, e_mid, H0.blur_xgroups, rx);
+    const Rag ry = rag_over(all, [&](int i) {
+      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 1, H0.blur_window);
+    });
+    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 1, V_TMP1, V_TMP2, adj, e_mid, H0.blur_window, ry);
+    const Rag rz = rag_over(all, [&](int i) {
+      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 2, H0.blur_window);
+    });
+    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 2, V_TMP2, V_TMP2, adj, em, H0.blur_window, rz);
+    return rz;
+  };
+  launch_finalize(st, d, B, 0, FIN_BETA, blur(V_V, 0, EPI_FWD));
+  blur(V_U, 1, EPI_ADJ);
+
+  // V-cycle by depth from the finest level: the down halves of depth 0, 1, .. (an instance takes
+  // part while the depth is above its tail), every instance's LDS-resident tail in one launch,
+  // then the up halves back to depth 0; instances of one depth with different voxels per
+  // thread take one launch each
+  std::vector<VcPlan> P(B);
+  int T = 0;
+  for (int i = 0; i < B; ++i) {
+    P[i] = vcycle_plan(h(i), *rb.lay[i]);
+    T = std::max(T, P[i].t);
+  }
+  const int H = P[0].hz;
+  const bool jac = H0.smoother == PLSQR_SMOOTH_JACOBI;
+  Rag np{};
+  auto depth = [&](int dd, bool down) {
+    for (int v : {4, 1}) {
+      std::vector<int> who;
+      for (int i = 0; i < B; ++i)
+        if (P[i].t > dd && P[i].shp[dd].v == v) who.push_back(i);
+      if (who.empty()) continue;
+      int threads = 0;
+      size_t lds = 0;
+      for (int i : who) {
+        threads = std::max(threads, zm_threads(P[i].shp[dd], H));
+        lds = std::max(lds, zm_lds_bytes(H, P[i].shp[dd], down));
+      }
+      const Rag rg = rag_over(who, [&](int i) {
+        const Layout &Ly = *rb.lay[i];
+        return (int)zm_tiles(Ly.lnx[dd], Ly.lny[dd], Ly.lnz[dd], P[i].shp[dd]);
+      });
+      const int kind = down ? (jac ? ZM_JAC_DOWN : ZM_CHEB_DOWN) : (jac ? ZM_JAC_UP : ZM_CHEB_UP);
+      const int want = (!down && dd == 0) ? 1 : 0;
+      launch_zm_ragged(st, d, kind, H, dd, v, threads, lds, rg, want);
+      if (want)
+        for (int k = 0; k < rg.n; ++k) {
+          np.inst[np.n] = rg.inst[k];
+          np.count[np.n] = rg.count[k];
+          ++np.n;
+        }
+    }
+  };
+  for (int dd = 0; dd < T; ++dd) depth(dd, true);
+  launch_vcycle_tail_lds(st, d, B, -1);
+  for (int dd = T - 1; dd >= 0; --dd) depth(dd, false);
+  launch_finalize(st, d, B, 0, FIN_ALPHA, np);
+  launch_update_fw(st, d, B, H0.n, rag_over(all, [&](int i) { return update_fw_blocks(h(i).n); }));
 }
 
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {

@@ -89,6 +89,7 @@ struct Request {
   plsqr_result result{};
   // serving mode: position in the fixed step schedule and completion event
   int step = 0, steps_total = 0;
+  int mixed_steps = 0;       // serving: inner steps run in launches shared with other grids
   hipEvent_t ev_start = nullptr, ev_done = nullptr;
 };
 
@@ -142,6 +143,23 @@ struct BatchView {
   EventList *update_events = nullptr;
   EventList *diag_events = nullptr;
 };
+
+// Instances of different grids advanced by one inner step in shared launches (serving mode).
+struct RagBatch {
+  InstDesc *const *d_descs;   // device array of B descriptor pointers
+  int B;                      // at most kMaxRag
+  const InstDesc *const *h;   // host copy of each instance
+  const Layout *const *lay;   // and its layout
+};
+// Whether an instance's inner step can share launches with instances of other grids: a 3D blur
+// operator with nx % 4 == 0, the fused V-cycle on every level above its tail, no S4 stop and a
+// single damping. Instances that share launches must also agree on the smoother schedule, the
+// blur launch knobs and the stop flags.
+bool ragged_ok(const InstDesc &H, const Layout &Ly);
+void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb);
+// The fused V-cycle schedule of an instance (per-level fused tiles, first tail level) into its
+// descriptor: what enqueue_vcycle runs for it.
+void plan_vcycle(InstDesc &D, const Layout &Ly);
 
 // Solve driver (same sequence for one instance or a lockstep batch).
 void enqueue_request_begin(hipStream_t st, const BatchView &bv);

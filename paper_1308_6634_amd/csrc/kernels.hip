@@ -507,9 +507,13 @@ __global__ void __launch_bounds__(kBlock) k_copy_g_u(InstDesc *const *descs) {
   if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = dot;
 }
 
-// Deterministic sum of the partials, then the scalar recurrences.
-__global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int nparts, int what) {
-  const InstDesc &D = inst(descs);
+// Deterministic sum of the partials, then the scalar recurrences. One block per instance;
+// np.n > 0: instance np.inst[k] (block k) has np.count[k] partials, else every instance nparts.
+__global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int nparts, int what,
+                                                    Rag np) {
+  const int bi = np.n ? np.inst[blockIdx.y] : (int)blockIdx.y;
+  if (np.n) nparts = np.count[blockIdx.y];
+  const InstDesc &D = *descs[bi];
   double s = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) s += sld(D.part)[i];
   s = block_sum(s);
@@ -636,12 +640,14 @@ __global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
 
 // f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step); 4 voxels
 // per thread when n is a multiple of 4.
-__global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs) {
-  const InstDesc &D = inst(descs);
+__global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs, Rag rg) {
+  const Blk k = locate(rg);
+  if (k.i < 0) return;
+  const InstDesc &D = *descs[k.i];
   const double *sc = sld(D.sc);
   if (sc[SC_STOP] != 0.0) return;
   const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
-  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long t = (long long)k.bx * kBlock + threadIdx.x;
   if ((sld(D.n) & 3) == 0) {
     if (t * 4 >= sld(D.n)) return;
     float4 wv = reinterpret_cast<const float4 *>(sld(D.w))[t];
@@ -893,14 +899,21 @@ int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m) {
   LAUNCH(k_copy_g_u, g, B, d);
   return (int)g;
 }
-void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what) {
-  LAUNCH(k_finalize, 1, B, d, nparts, what);
+void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what,
+                     const Rag &np) {
+  LAUNCH(k_finalize, 1, np.n ? np.n : B, d, nparts, what, np);
 }
 void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n) {
   LAUNCH(k_init_wf, blocks_for(n), B, d);
 }
-void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n) {
-  LAUNCH(k_update_fw, blocks_for((n + 3) / 4), B, d);
+int update_fw_blocks(long long n) { return (int)blocks_for((n + 3) / 4); }
+void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n, const Rag &rg) {
+  if (rg.n == 0) {
+    LAUNCH(k_update_fw, blocks_for((n + 3) / 4), B, d, rg);
+  } else {
+    const unsigned g = (unsigned)(rg.first[rg.n - 1] + rg.count[rg.n - 1]);
+    LAUNCH(k_update_fw, g, 1, d, rg);
+  }
 }
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n) {
   const unsigned g = blocks_for(n);

@@ -69,7 +69,8 @@ void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
 // nx % 4 == 0)
 void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
 // the same with every tail level resident in LDS (tail_lds.hip); the levels t .. coarsest must
-// need at most kTailLdsFloats floats: tail_lds_floats of their cell counts
+// need at most kTailLdsFloats floats: tail_lds_floats of their cell counts. t < 0: each
+// instance's own first tail level (its descriptor's tail_lds_t).
 void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t);
 long long tail_lds_floats(const long long *cells, int nlev);
 // Fused level kernels (zmarch.hip): one launch per level and V-cycle half. ZM_*_DOWN runs the
@@ -90,23 +91,36 @@ long long zm_tiles(int nx, int ny, int nz, const ZmShape &s);   // blocks per in
 size_t zm_lds_bytes(int H, const ZmShape &s, bool down);
 int launch_zm(hipStream_t st, InstDesc *const *d, int B, int kind, int H, int l, int nx, int ny,
               int nz, const ZmShape &s, int want_dot);
+// The same over a ragged map (each instance's level-l tile from its descriptor's zmp[l], all of
+// them with s.v voxels per thread); threads and LDS: the largest over the instances.
+void launch_zm_ragged(hipStream_t st, InstDesc *const *d, int kind, int H, int l, int v,
+                      int threads, size_t lds, const Rag &rg, int want_dot);
+int zm_threads(const ZmShape &s, int H);
 // separable blur passes (blur.hip); the x pass takes 16-byte windows when nx % 4 == 0
 // groups: 4-output groups per thread when nx % 4 == 0 (1, 2 or 4; 0: default)
+// rg: a ragged map (then nx % 4 == 0 for every instance), or kNoRag for B same-shaped
+// instances; returns the blocks per instance of a uniform launch
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups);
+                  int adj, int epi, int groups, const Rag &rg = kNoRag);
 // y (axis 1) or z (axis 2) pass; window: outputs per thread along the axis (4, 8, 16 or 32;
 // 0: default)
 int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                     int src, int dst, int adj, int epi, int window);
-// x and y passes in one kernel (nx % 4 == 0, ny > 1)
+                     int src, int dst, int adj, int epi, int window, const Rag &rg = kNoRag);
+// blocks per instance of the passes above
+int blur_x_blocks(long long n, int nx, int groups);
+int blur_axis_blocks(int nx, int ny, int nz, int axis, int window);
 int launch_gemv_rows(hipStream_t st, InstDesc *const *d, int B, long long m, int src, int epi,
                      int rows);
 void launch_gemv_cols(hipStream_t st, InstDesc *const *d, int B, long long n, int chunks);
 void launch_colsum(hipStream_t st, InstDesc *const *d, int B, long long n, int epi);
 int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m);
-void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what);
+// np: per-instance partial counts of a ragged producer (then one block per entry), or kNoRag
+void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what,
+                     const Rag &np = kNoRag);
 void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n);
-void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n);
+void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n,
+                      const Rag &rg = kNoRag);
+int update_fw_blocks(long long n);
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n);
 // batched dense products on MFMA (gemm_bf16.hip)
 int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,

@@ -53,6 +53,12 @@ struct LevelDesc {
   double eps;                        // eps_l = 2^{d l} eps
 };
 
+// Tile of a level's fused kernels: tx x-columns, ty rows, zc planes per block, v voxels per
+// thread; tx = 0: the level runs the per-sweep kernels.
+struct ZmPlan {
+  int tx, ty, zc, v;
+};
+
 struct InstDesc {
   int nx, ny, nz, levels;
   long long n;                       // n_X
@@ -100,8 +106,25 @@ struct InstDesc {
   float *ycoef;                      // n_tau x inner: f(tau_t) = sum_i ycoef[t][i] v_i
   float *f_taus;                     // caller's n_tau x n_X output
   double taus[kMaxTaus];
+  // the fused V-cycle as the driver runs it (what a launch serving instances of different
+  // grids reads per instance): each level's fused-kernel tile and the first level of the
+  // LDS-resident tail
+  ZmPlan zmp[kMaxLevels];
+  int tail_lds_t;
   LevelDesc lv[kMaxLevels];
 };
+
+// Map of a ragged launch: blocks [first[k], first[k] + count[k]) of a one-dimensional grid
+// serve instance inst[k] (an index into the launch's descriptor array); first[k] is a multiple
+// of 8, and blocks outside every range return at once. n = 0: a uniform launch, where blockIdx.y
+// is the instance and blockIdx.x the block within it. For k_finalize, count[k] is instance
+// inst[k]'s partial count.
+constexpr int kMaxRag = 32;
+struct Rag {
+  int n;
+  int inst[kMaxRag], first[kMaxRag], count[kMaxRag];
+};
+inline constexpr Rag kNoRag{};
 
 // Selectors for vectors inside an instance (kernels are batched, so they cannot take
 // per-instance pointers directly).

@@ -362,6 +362,7 @@ __device__ __forceinline__ bool tail_up_any(const InstDesc &D, const TailSm &m,
 __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail_lds(InstDesc *const *descs, int t) {
   const InstDesc &D = inst(descs);
   if (stopped_inner(D)) return;
+  if (t < 0) t = sld(D.tail_lds_t);   // instances of different hierarchies in one launch
   const int Lv = sld(D.levels);
   // the Chebyshev coefficients of each step, once
   if (sld(D.smoother) != PLSQR_SMOOTH_JACOBI && (int)threadIdx.x < sld(D.cheb_degree)) {

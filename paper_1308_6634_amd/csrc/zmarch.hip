@@ -322,15 +322,22 @@ __host__ __device__ constexpr int halo_units(int V, int H) { return V == 4 ? 1 :
 // part of v.p).
 template <int KIND, int H, bool L0, int V>
 __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs, int l, int tx,
-                                                     int ty, int zc, int want_dot) {
+                                                     int ty, int zc, int want_dot, Rag rg) {
   constexpr bool DOWN = (KIND == ZM_JAC_DOWN || KIND == ZM_CHEB_DOWN);
   constexpr bool CHEB = (KIND == ZM_CHEB_DOWN || KIND == ZM_CHEB_UP);
   constexpr int HX = halo_units(V, H);
   using Cell = LdsCell<V>;
   extern __shared__ float4 zsm4[];
   Cell *zsm = reinterpret_cast<Cell *>(zsm4);
-  const InstDesc &D = inst(descs);
+  const Blk blk = locate(rg);
+  if (blk.i < 0) return;
+  const InstDesc &D = *descs[blk.i];
   if (stopped_inner(D)) return;
+  if (tx == 0) {   // a ragged launch: this instance's own tile of level l
+    tx = sld(D.zmp[l].tx);
+    ty = sld(D.zmp[l].ty);
+    zc = sld(D.zmp[l].zc);
+  }
   ZmCtx c;
   c.L = level_of(D, l);
   const LevelDesc Cl = level_of(D, l + 1);
@@ -342,9 +349,9 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   c.eps = (float)c.L.eps;
   const float *__restrict__ kap = L0 ? sld(D.kappa) : nullptr;
   const int ntx = (c.nx + tx - 1) / tx, nty = (c.ny + ty - 1) / ty, ntz = (c.nz + zc - 1) / zc;
-  const long long b = xcd_tile();
+  const long long b = xcd_tile_of(blk);
   if (b >= (long long)ntx * nty * ntz) {   // past this instance's tiles (a larger batch member)
-    if (want_dot && threadIdx.x == 0) sld(D.part)[blockIdx.x] = 0.0;
+    if (want_dot && threadIdx.x == 0) sld(D.part)[blk.bx] = 0.0;
     return;
   }
   const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((long long)ntx * nty));
@@ -659,7 +666,7 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   }
   if (!DOWN && want_dot) {
     const double s = block_sum_any(dot);
-    if (threadIdx.x == 0) sld(D.part)[blockIdx.x] = s;
+    if (threadIdx.x == 0) sld(D.part)[blk.bx] = s;
   }
 }
 
@@ -669,29 +676,40 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
 namespace {
 template <int KIND, bool L0, int V>
 void zm_dispatch(int H, dim3 g, dim3 blk, size_t smem, hipStream_t st, InstDesc *const *d, int l,
-                 int tx, int ty, int zc, int want_dot) {
+                 int tx, int ty, int zc, int want_dot, const Rag &rg) {
   switch (H) {
-    case 1: hipLaunchKernelGGL((k_zm<KIND, 1, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
-    case 2: hipLaunchKernelGGL((k_zm<KIND, 2, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
-    case 3: hipLaunchKernelGGL((k_zm<KIND, 3, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
-    default: hipLaunchKernelGGL((k_zm<KIND, 4, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot); break;
+    case 1: hipLaunchKernelGGL((k_zm<KIND, 1, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg); break;
+    case 2: hipLaunchKernelGGL((k_zm<KIND, 2, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg); break;
+    case 3: hipLaunchKernelGGL((k_zm<KIND, 3, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg); break;
+    default: hipLaunchKernelGGL((k_zm<KIND, 4, L0, V>), g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg); break;
   }
 }
 template <int KIND>
 void zm_dispatch_level(int H, int V, dim3 g, dim3 blk, size_t smem, hipStream_t st,
-                       InstDesc *const *d, int l, int tx, int ty, int zc, int want_dot) {
+                       InstDesc *const *d, int l, int tx, int ty, int zc, int want_dot,
+                       const Rag &rg) {
   if (V == 4) {
-    if (l == 0) zm_dispatch<KIND, true, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
-    else zm_dispatch<KIND, false, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+    if (l == 0) zm_dispatch<KIND, true, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg);
+    else zm_dispatch<KIND, false, 4>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg);
   } else {
-    if (l == 0) zm_dispatch<KIND, true, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
-    else zm_dispatch<KIND, false, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot);
+    if (l == 0) zm_dispatch<KIND, true, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg);
+    else zm_dispatch<KIND, false, 1>(H, g, blk, smem, st, d, l, tx, ty, zc, want_dot, rg);
+  }
+}
+template <class... A>
+void zm_dispatch_kind(int kind, A... a) {
+  switch (kind) {
+    case ZM_JAC_DOWN: zm_dispatch_level<ZM_JAC_DOWN>(a...); break;
+    case ZM_JAC_UP: zm_dispatch_level<ZM_JAC_UP>(a...); break;
+    case ZM_CHEB_DOWN: zm_dispatch_level<ZM_CHEB_DOWN>(a...); break;
+    default: zm_dispatch_level<ZM_CHEB_UP>(a...); break;
   }
 }
 
 int zm_exq(const ZmShape &s, int H) { return s.tx / s.v + 2 * halo_units(s.v, H); }
-int zm_threads(const ZmShape &s, int H) { return zm_exq(s, H) * (s.ty + 2 * H); }
 }  // namespace
+
+int zm_threads(const ZmShape &s, int H) { return zm_exq(s, H) * (s.ty + 2 * H); }
 
 size_t zm_lds_bytes(int H, const ZmShape &s, bool down) {
   const size_t cell = s.v == 4 ? sizeof(float4) : sizeof(float);
@@ -753,14 +771,16 @@ int launch_zm(hipStream_t st, InstDesc *const *d, int B, int kind, int H, int l,
   const unsigned tiles = (unsigned)zm_tiles(nx, ny, nz, s);
   const bool down = (kind == ZM_JAC_DOWN || kind == ZM_CHEB_DOWN);
   const size_t smem = zm_lds_bytes(H, s, down);
-  const dim3 g(tiles, B), blk(threads);
-  switch (kind) {
-    case ZM_JAC_DOWN: zm_dispatch_level<ZM_JAC_DOWN>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
-    case ZM_JAC_UP: zm_dispatch_level<ZM_JAC_UP>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
-    case ZM_CHEB_DOWN: zm_dispatch_level<ZM_CHEB_DOWN>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
-    default: zm_dispatch_level<ZM_CHEB_UP>(H, s.v, g, blk, smem, st, d, l, s.tx, s.ty, s.zc, want_dot); break;
-  }
+  zm_dispatch_kind(kind, H, s.v, dim3(tiles, B), dim3(threads), smem, st, d, l, s.tx, s.ty, s.zc,
+                   want_dot, kNoRag);
   return (int)tiles;
+}
+
+void launch_zm_ragged(hipStream_t st, InstDesc *const *d, int kind, int H, int l, int v,
+                      int threads, size_t lds, const Rag &rg, int want_dot) {
+  const unsigned blocks = (unsigned)(rg.first[rg.n - 1] + rg.count[rg.n - 1]);
+  const unsigned th = (unsigned)((threads + 63) / 64 * 64);
+  zm_dispatch_kind(kind, H, v, dim3(blocks, 1), dim3(th), lds, st, d, l, 0, 0, 0, want_dot, rg);
 }
 
 }  // namespace plsqr

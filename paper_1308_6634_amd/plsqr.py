@@ -87,7 +87,7 @@ class plsqr_problem(ctypes.Structure):
 
 class plsqr_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("outer_done", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("mixed_steps", ctypes.c_int32),
                 ("inner_done", ctypes.c_int32 * PLSQR_MAX_OUTER),
                 ("resid", ctypes.c_double * PLSQR_MAX_OUTER),
                 ("penalty", ctypes.c_double * PLSQR_MAX_OUTER),
