@@ -20,9 +20,8 @@
 // and a quarter of the instructions per iteration, for the small levels, where one block's
 // march along z decides).
 //
-// The inputs of a plane (right-hand side, face weights) are loaded once, one iteration before
-// their first use, and handed down the stages in registers with the plane's 1/diag, formed
-// once when the plane enters.
+// The inputs of a plane (right-hand side, face weights, the level's stored 1/diag) are loaded
+// once, ahead of their first use, and handed down the stages in registers.
 //
 // Every voxel's arithmetic is that of the one-pass kernels (smooth_vec.hip): the same formulas
 // with the terms in the same order, so the fused and the per-sweep V-cycles give the same
@@ -51,7 +50,7 @@ __host__ __device__ constexpr int zm_prefetch(int kind, int H, bool L0, int V) {
   return V == 1 ? ((!L0 && kind == ZM_CHEB_DOWN && H == 4) ? 1 : 2)
          : !L0  ? 1
          : (kind == ZM_JAC_DOWN) ? (H <= 3 ? 2 : 1)
-         : (kind == ZM_JAC_UP)   ? 2
+         : (kind == ZM_JAC_UP)   ? (H <= 3 ? 2 : 1)
          : (kind == ZM_CHEB_DOWN) ? (H <= 3 ? 2 : 1)
                                   : (H <= 2 ? 2 : 1);
 }
@@ -129,14 +128,15 @@ __device__ __forceinline__ Vec<V> vmove(const Vec<V> &a) {
   return r;
 }
 
-// One thread's inputs at one plane, loaded once (one iteration ahead of their first use) and
+// One thread's inputs at one plane, loaded once (two iterations ahead of their first use) and
 // handed down the stages in registers: the right-hand side, the face weights to the +x/+y/+z
 // neighbours (level 0: all three are kappa of the cell), the weight from the -x neighbour of
-// the first voxel and the weights from the -y neighbours (as loaded: where the face leaves the
-// grid they hold an unrelated weight, which every use masks), and the 1/diag formed when the
-// plane enters. The weights from the -z neighbours are the +z weights of the plane below, the
-// next entry of the same register line. Nothing is computed from the loaded values until the
-// plane is used, so the loads stay in flight until then.
+// the first voxel and the weights from the -y neighbours (as loaded, where a face leaves the
+// grid, an unrelated weight: masked to zero when the plane enters), and 1/diag (the level's
+// stored diagonal, formed once per outer step in the same order as the stencil's terms). The
+// weights from the -z neighbours are the +z weights of the plane below, the next entry of the
+// same register line. Nothing is computed from the loaded values until the plane enters, so
+// the loads stay in flight until then.
 template <bool L0, int V>
 struct PlaneData {
   Vec<V> b, wx, wy, wz, wym, dinv;
@@ -168,7 +168,7 @@ __device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const flo
   const long long jl = hl ? j - 1 : j;
   const long long jy = hy ? j - c.sy : j;
   PlaneData<L0, V> d;
-  d.dinv = Vec<V>{};
+  d.dinv = ldv<V>(c.L.dinv + j);
   d.b = ldv<V>(c.L.b + j);
   const float *wxs = L0 ? kap : c.L.wx;
   const float *wys = L0 ? kap : c.L.wy;
@@ -201,56 +201,36 @@ __device__ __forceinline__ PlaneData<L0, V> take_plane(const PlaneData<L0, V> &p
     }
     d.wym = vmove<V>(p.wym);
     d.wxl = vmove(p.wxl);
-    d.dinv = Vec<V>{};
+    d.dinv = vmove<V>(p.dinv);
     return d;
   }
 }
 
-// 1/diag at plane p (below: the plane under it). Level 0 assembles it from kappa in the order
-// of the stencil and of the stored level-0 diagonal; coarser levels in the order of the stored
-// diagonal (eps, then each axis's pair of faces).
+// A plane entering the ring: the weights from the -x neighbour of the first voxel and from the
+// -y neighbours masked to zero where those faces leave the grid (the stencil adds their terms
+// unconditionally).
 template <bool L0, int V>
-__device__ __forceinline__ Vec<V> plane_dinv(const ZmCtx &c, const PlaneData<L0, V> &d,
-                                             const PlaneData<L0, V> &below, int p) {
-  Vec<V> dv;
-  const bool hyp = c.gy + 1 < c.ny, hym = c.gy > 0, hzp = p + 1 < c.nz, hzm = p > 0;
+__device__ __forceinline__ void mask_plane(const ZmCtx &c, PlaneData<L0, V> &d) {
+  const bool hxl = c.gx > 0, hym = c.gy > 0;
+  d.wxl = hxl ? d.wxl : 0.f;
 #pragma unroll
-  for (int e = 0; e < V; ++e) {
-    float dg = c.eps;
-    if constexpr (L0) {
-      const float wm = (e > 0) ? d.k.v[e > 0 ? e - 1 : 0] : d.wxl;
-      if (c.gx + e + 1 < c.nx) dg += d.k.v[e];
-      if (c.gx + e > 0) dg += wm;
-      if (hyp) dg += d.k.v[e];
-      if (hym) dg += d.wym.v[e];
-      if (hzp) dg += d.k.v[e];
-      if (hzm) dg += below.k.v[e];
-    } else {
-      const float wm = (e > 0) ? d.wx.v[e > 0 ? e - 1 : 0] : d.wxl;
-      dg += d.wx.v[e] + (c.gx + e > 0 ? wm : 0.f);
-      dg += d.wy.v[e] + (hym ? d.wym.v[e] : 0.f);
-      if (c.nz > 1) dg += d.wz.v[e] + (hzm ? below.wz.v[e] : 0.f);
-    }
-    dv.v[e] = 1.0f / dg;
-  }
-  return dv;
+  for (int e = 0; e < V; ++e) d.wym.v[e] = hym ? d.wym.v[e] : 0.f;
 }
 
 // (A_l x) at plane p, with the neighbour values given: xl/xr the x-neighbours of the first and
 // last voxel, yp/ym/zp/zm the neighbouring rows and planes. The faces are added in the order of
 // stencil4. Faces that leave the grid are skipped; for the -x face of the grid's first voxel and
-// the -y faces the term is added anyway with the weight masked to zero, which changes nothing
-// but the sign of a zero sum. The z faces depend only on the plane, so they are tested once (a
-// uniform branch).
+// the -y faces the term is added anyway with the weight masked to zero (mask_plane), which
+// changes nothing but the sign of a zero sum. The z faces depend only on the plane, so they are
+// tested once (a uniform branch).
 template <bool L0, int V>
 __device__ __forceinline__ Vec<V> apply_stencil(const ZmCtx &c, const PlaneData<L0, V> &d,
                                                 const PlaneData<L0, V> &below, int p,
                                                 const Vec<V> &xc, float xl, float xr,
                                                 const Vec<V> &yp, const Vec<V> &ym,
                                                 const Vec<V> &zp, const Vec<V> &zm) {
-  const bool hyp = c.gy + 1 < c.ny, hym = c.gy > 0, hzp = p + 1 < c.nz, hzm = p > 0;
+  const bool hyp = c.gy + 1 < c.ny, hzp = p + 1 < c.nz, hzm = p > 0;
   const bool hxr = c.gx + V < c.nx;            // +x face of the last voxel
-  const bool hxl = c.gx > 0;                   // -x face of the first voxel
   Vec<V> acc;
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -268,9 +248,9 @@ __device__ __forceinline__ Vec<V> apply_stencil(const ZmCtx &c, const PlaneData<
       wm = (e > 0) ? d.wx.v[e > 0 ? e - 1 : 0] : d.wxl;
     }
     if (e < V - 1 || hxr) a += wxp * (xj - xnext);
-    a += (e > 0 || hxl ? wm : 0.f) * (xj - xprev);   // zero weight at the grid's -x edge
+    a += wm * (xj - xprev);                     // zero weight at the grid's -x edge
     if (hyp) a += wyp * (xj - yp.v[e]);
-    a += (hym ? d.wym.v[e] : 0.f) * (xj - ym.v[e]);  // zero weight at the grid's -y edge
+    a += d.wym.v[e] * (xj - ym.v[e]);           // zero weight at the grid's -y edge
     acc.v[e] = a;
   }
   if (L0 || c.nz > 1) {
@@ -394,7 +374,7 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   const int phi0 = min(c.nz - 1, zend - 1 + H);   // last plane stage 0 works on
 
   // pd[s]: inputs of the plane stage s works on in this iteration (t - s); pd[H + 1] is the
-  // plane below stage H's. pf: the next iteration's plane, loaded one iteration ahead.
+  // plane below stage H's. The slots (pfA, pfB): planes whose loads are in flight.
   using PD = PlaneData<L0, V>;
   PD pd[H + 2];
   Vec<V> cur_x = {};                   // up: pre-smoothed iterate of the current plane
@@ -419,9 +399,9 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
     float e0, e1;
   };
   {
-    // the plane below the first one (its weights are the -z weights of stage 0's diagonal);
-    // clamped to plane 0, and then unused, when t0 == 0. Loaded first: the first iteration
-    // needs it and slot A, the second slot B.
+    // the plane below the first one (its weights are the -z weights of the stencil at the
+    // first plane); clamped to plane 0, and then unused, when t0 == 0. Loaded first, then slot
+    // A (the first iteration's plane), then slot B.
     const PD below = load_plane<L0, V>(c, kap, in, col, t0 - 1);
 #pragma unroll
     for (int s = 0; s < H + 2; ++s) pd[s] = below;
@@ -455,13 +435,13 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
 
   auto iteration = [&](const int t, PD &pf, UpSlot &up) {
     const int cur = t & 1, prev = cur ^ 1;
-    // this iteration's planes, with the entering plane's 1/diag; then the loads of the plane
-    // PF ahead into the slot just emptied (unconditional, the plane is clamped, so that no
-    // branch join makes them complete early)
+    // this iteration's planes (the entering one masked); then the loads of the plane PF ahead
+    // into the slot just emptied (unconditional, the plane is clamped, so that no branch join
+    // makes them complete early)
 #pragma unroll
     for (int s = H + 1; s > 0; --s) pd[s] = pd[s - 1];
     pd[0] = take_plane<PF == 2, L0, V>(pf);
-    pd[0].dinv = plane_dinv<L0, V>(c, pd[0], pd[1], t);
+    mask_plane<L0, V>(c, pd[0]);
     if (!DOWN) {
       if constexpr (PF == 2) {
         cur_x = vmove<V>(up.x);
