@@ -595,6 +595,38 @@ def c4_oracle_sample(probs, A, which=(0, 63), target_s=15.0):
     return rec, S, refs
 
 
+def c5_oracle_sample(temps, sizes=(32, 32, 48)):
+    """The FP64 oracle on whole requests of the served family (their full outer x inner counts):
+    the first templates of the given grid sizes, one at a time. Returns (cpu_baseline record,
+    {template index: f})."""
+    from threadpoolctl import threadpool_info
+    from oracle import lagged
+
+    picks, want = [], list(sizes)
+    for k, p in enumerate(temps):
+        if p.dims[0] in want:
+            picks.append(k)
+            want.remove(p.dims[0])
+    refs, work, t_all = {}, 0, 0.0
+    for k in picks:
+        p = temps[k]
+        t0 = time.perf_counter()
+        refs[k], _ = lagged.solve_problem(p)
+        t = time.perf_counter() - t0
+        t_all += t
+        work += p.n_x * p.outer * p.inner
+        print(f"[bench] oracle request template {k} ({p.dims[0]}^3, {p.outer} x {p.inner}): "
+              f"{t:.1f} s", file=sys.stderr, flush=True)
+    threads = [x.get("num_threads", 1) for x in threadpool_info() if x.get("user_api") == "blas"]
+    rec = {"value": work / t_all, "unit": "voxel-iter/s",
+           "cores": int(max(threads) if threads else 1), "kind": "oracle",
+           "sample": f"requests of {', '.join(f'{temps[k].dims[0]}^3' for k in picks)} one at a "
+                     f"time at their full counts ({temps[picks[0]].outer} x "
+                     f"{temps[picks[0]].inner}, setup included), {t_all:.1f} s, FP64 NumPy/SciPy, "
+                     f"host cores: {len(os.sched_getaffinity(0))}"}
+    return rec, refs
+
+
 def bench_c4(args):
     """64 reconstructions of 64^3 sharing one 8192 x 262144 sensitivity, batched in lockstep
     with the dense products on MFMA (BF16 split products), against the same instances run
@@ -904,6 +936,20 @@ def bench_c5(args):
                   "requests": M, "span_s": pspan, "voxel_iters_per_s": ptotal / pspan},
         "served_over_plain_throughput": served_value / (ptotal / pspan),
     }
+    if not args.no_cpu_baseline:
+        # the oracle on a few whole requests of the stream, timed, and compared with what the
+        # served path returned for the same requests (request k of the stream is template k)
+        print("[bench] c5: timing the FP64 oracle on whole requests", file=sys.stderr, flush=True)
+        cb, refs = c5_oracle_sample(temps)
+        out["cpu_baseline"] = cb
+        errs = {}
+        for k, f_ref in refs.items():
+            got = reqs[k][3].cpu().numpy().astype(np.float64).reshape(f_ref.shape)
+            errs[f"template {k} ({temps[k].dims[0]}^3)"] = float(
+                np.linalg.norm(got - f_ref) / np.linalg.norm(f_ref))
+        out["parity_sample_rel_l2"] = max(errs.values())
+        out["parity_sample"] = {"requests": errs, "outer": temps[0].outer, "inner": temps[0].inner,
+                                "bar": 1e-3, "path": "served"}
     print(json.dumps(out), flush=True)
 
 
