@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -45,9 +46,9 @@ __host__ __device__ constexpr int zm_max_threads(int V) { return V == 4 ? 512 : 
 
 // Planes of loads a thread keeps in flight (see k_zm), from the register counts of the variants:
 // two where the thread holds two slots without spilling (one-voxel threads but for the coarse
-// degree-4 Chebyshev pre-smoothing, and the level-0 four-voxel variants below), else one.
+// degree-4 Chebyshev smoothing, and the level-0 four-voxel variants below), else one.
 __host__ __device__ constexpr int zm_prefetch(int kind, int H, bool L0, int V) {
-  return V == 1 ? ((!L0 && kind == ZM_CHEB_DOWN && H == 4) ? 1 : 2)
+  return V == 1 ? ((!L0 && (kind == ZM_CHEB_DOWN || kind == ZM_CHEB_UP) && H == 4) ? 1 : 2)
          : !L0  ? 1
          : (kind == ZM_JAC_DOWN) ? (H <= 3 ? 2 : 1)
          : (kind == ZM_JAC_UP)   ? (H <= 3 ? 2 : 1)
@@ -111,21 +112,14 @@ __device__ __forceinline__ float last_of(const LdsCell<V> &c) {
   else return c;
 }
 
-// A register move the compiler cannot fold away. With two prefetch slots a slot is read through
-// it when its plane is used: the slot's registers are then dead, the next loads into the slot
-// can reuse them, and the loop carries the slot without copying registers whose loads are in
-// flight (such a copy waits for every outstanding load).
-__device__ __forceinline__ float vmove(float x) {
-  float y;
-  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
-  return y;
+// f(std::integral_constant<int, I>{}) for I = 0 .. N - 1, unrolled.
+template <int... I, class F>
+__device__ __forceinline__ void static_for_seq(std::integer_sequence<int, I...>, F &&f) {
+  (f(std::integral_constant<int, I>{}), ...);
 }
-template <int V>
-__device__ __forceinline__ Vec<V> vmove(const Vec<V> &a) {
-  Vec<V> r;
-#pragma unroll
-  for (int e = 0; e < V; ++e) r.v[e] = vmove(a.v[e]);
-  return r;
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_seq(std::make_integer_sequence<int, N>{}, f);
 }
 
 // One thread's inputs at one plane, loaded once (two iterations ahead of their first use) and
@@ -185,28 +179,40 @@ __device__ __forceinline__ PlaneData<L0, V> load_plane(const ZmCtx &c, const flo
   return d;
 }
 
-template <bool MOVE, bool L0, int V>
+// A register move the compiler cannot fold away. In the paired form (below) a prefetch slot is
+// read through it when its plane is used: the slot's registers are then dead, the next loads
+// into the slot can reuse them, and the loop carries the slot without copying registers whose
+// loads are in flight (such a copy waits for every outstanding load).
+__device__ __forceinline__ float vmove(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+template <int V>
+__device__ __forceinline__ Vec<V> vmove(const Vec<V> &a) {
+  Vec<V> r;
+#pragma unroll
+  for (int e = 0; e < V; ++e) r.v[e] = vmove(a.v[e]);
+  return r;
+}
+template <bool L0, int V>
 __device__ __forceinline__ PlaneData<L0, V> take_plane(const PlaneData<L0, V> &p) {
-  if constexpr (!MOVE) {
-    return p;
+  PlaneData<L0, V> d;
+  d.b = vmove<V>(p.b);
+  if constexpr (L0) {
+    d.k = vmove<V>(p.k);
   } else {
-    PlaneData<L0, V> d;
-    d.b = vmove<V>(p.b);
-    if constexpr (L0) {
-      d.k = vmove<V>(p.k);
-    } else {
-      d.wx = vmove<V>(p.wx);
-      d.wy = vmove<V>(p.wy);
-      d.wz = vmove<V>(p.wz);
-    }
-    d.wym = vmove<V>(p.wym);
-    d.wxl = vmove(p.wxl);
-    d.dinv = vmove<V>(p.dinv);
-    return d;
+    d.wx = vmove<V>(p.wx);
+    d.wy = vmove<V>(p.wy);
+    d.wz = vmove<V>(p.wz);
   }
+  d.wym = vmove<V>(p.wym);
+  d.wxl = vmove(p.wxl);
+  d.dinv = vmove<V>(p.dinv);
+  return d;
 }
 
-// A plane entering the ring: the weights from the -x neighbour of the first voxel and from the
+// A plane entering the stages: the weights from the -x neighbour of the first voxel and from the
 // -y neighbours masked to zero where those faces leave the grid (the stencil adds their terms
 // unconditionally).
 template <bool L0, int V>
@@ -373,45 +379,68 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   const int t1 = zend - 1 + H + (DOWN ? 1 : 0);
   const int phi0 = min(c.nz - 1, zend - 1 + H);   // last plane stage 0 works on
 
-  // pd[s]: inputs of the plane stage s works on in this iteration (t - s); pd[H + 1] is the
-  // plane below stage H's. The slots (pfA, pfB): planes whose loads are in flight.
+  // The inputs of the planes the stages read (t .. t - H - 1: stage s works on plane t - s and
+  // takes its -z weights from the plane below) and of the PF planes whose loads are in flight
+  // (PF = 2, or one where two would not fit the registers of a four-voxel thread without
+  // spilling: a spill reload in the loop would wait for the loads issued before it). Three forms:
+  // * ring (four voxels per thread, PF = 2): R slots, plane t0 + i in slot i mod R, the plane
+  //   below the first in slot R - 1, and the march unrolled R times (the iteration's offset
+  //   U = (t - t0) mod R is a compile-time constant), so a plane keeps its registers from its
+  //   loads to its last use and nothing rotates;
+  // * pair (one voxel per thread, PF = 2; their marches are short, where the ring's longer code
+  //   cost more than it saved): the planes shift down a register line (pd) each iteration, two
+  //   prefetch slots taken alternately by iterations run in pairs;
+  // * single (PF = 1): the same line behind one prefetch slot.
   using PD = PlaneData<L0, V>;
-  PD pd[H + 2];
+  constexpr int PF = zm_prefetch(KIND, H, L0, V);
+  constexpr int FORM = (PF == 2) ? (V == 4 ? 0 : 1) : 2;   // ring, pair, single
+  constexpr int R = (FORM == 0) ? H + 2 + PF : 1;
+  struct UpData {     // up: the pre-smoothed iterate and the coarse correction of a plane
+    Vec<V> x;
+    float e0, e1;
+  };
+  PD ring[R];
+  UpData upr[R];
+  PD pd[H + 2];       // pair and single forms: the planes t .. t - H - 1
+  PD pfs[2];          // their prefetch slots
+  UpData ups[2];
   Vec<V> cur_x = {};                   // up: pre-smoothed iterate of the current plane
   float cur_e0 = 0.f, cur_e1 = 0.f;
-  auto up_loads = [&](int p, Vec<V> &xq, float &e0, float &e1) {
+  auto up_loads = [&](int p, UpData &u) {
     const int pc = min(max(p, 0), c.nz - 1);
     const long long j = in ? col + c.sz * pc : 0;
     const long long pj = in ? (long long)(c.gx >> 1) +
                                   (long long)Cl.nx * ((c.gy >> 1) + (long long)Cl.ny * (pc / czf))
                             : 0;
-    xq = ldv<V>(xpre + j);
-    e0 = ecrs[pj];
-    if (V == 4) e1 = ecrs[pj + 1];
-  };
-  // PF planes are in flight (the loop runs two iterations per trip, each with its own slot, so
-  // a slot is read two iterations after its loads were issued); one where two slots would not
-  // fit the registers of a four-voxel thread without spilling (a spill reload in the loop would
-  // wait for the loads issued before it).
-  constexpr int PF = zm_prefetch(KIND, H, L0, V);
-  struct UpSlot {
-    Vec<V> x;
-    float e0, e1;
+    u.x = ldv<V>(xpre + j);
+    u.e0 = ecrs[pj];
+    u.e1 = (V == 4) ? ecrs[pj + 1] : 0.f;
   };
   {
     // the plane below the first one (its weights are the -z weights of the stencil at the
-    // first plane); clamped to plane 0, and then unused, when t0 == 0. Loaded first, then slot
-    // A (the first iteration's plane), then slot B.
+    // first plane); clamped to plane 0, and then unused, when t0 == 0. Loaded first, then the
+    // first PF planes. The other slots are written before any stage reads them.
     const PD below = load_plane<L0, V>(c, kap, in, col, t0 - 1);
 #pragma unroll
-    for (int s = 0; s < H + 2; ++s) pd[s] = below;
+    for (int k = 0; k < R; ++k) {
+      ring[k] = below;
+      upr[k] = UpData{};
+    }
+#pragma unroll
+    for (int k = 0; k < H + 2; ++k) pd[k] = below;
   }
-  PD pfA = load_plane<L0, V>(c, kap, in, col, t0), pfB = pfA;
-  UpSlot upA = {}, upB = {};
-  if (!DOWN) up_loads(t0, upA.x, upA.e0, upA.e1);
-  if (PF == 2) {
-    pfB = load_plane<L0, V>(c, kap, in, col, min(t0 + 1, phi0));
-    if (!DOWN) up_loads(min(t0 + 1, phi0), upB.x, upB.e0, upB.e1);
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const PD pl = load_plane<L0, V>(c, kap, in, col, min(t0 + k, phi0));
+    UpData ul{};
+    if (!DOWN) up_loads(min(t0 + k, phi0), ul);
+    if constexpr (FORM == 0) {
+      ring[k] = pl;
+      upr[k] = ul;
+    } else {
+      pfs[k] = pl;
+      ups[k] = ul;
+    }
   }
 
   // z-lines of the stencil inputs: zcv[s], zmv[s] = stage-s input at the plane stage s works on
@@ -433,28 +462,49 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   float racc0 = 0.f, racc1 = 0.f;
   double dot = 0.0;
 
-  auto iteration = [&](const int t, PD &pf, UpSlot &up) {
+  // offset: U (the ring form) or the prefetch slot (the others), as a compile-time constant
+  auto iteration = [&](auto offset, const int t) __attribute__((always_inline)) {
+    constexpr int U = decltype(offset)::value;
+    // the inputs of plane t - s
+    auto plane = [&](int s) -> PD & {
+      if constexpr (FORM == 0) return ring[(U + R - s) % R];
+      else return pd[s];
+    };
     const int cur = t & 1, prev = cur ^ 1;
-    // this iteration's planes (the entering one masked); then the loads of the plane PF ahead
-    // into the slot just emptied (unconditional, the plane is clamped, so that no branch join
-    // makes them complete early)
-#pragma unroll
-    for (int s = H + 1; s > 0; --s) pd[s] = pd[s - 1];
-    pd[0] = take_plane<PF == 2, L0, V>(pf);
-    mask_plane<L0, V>(c, pd[0]);
-    if (!DOWN) {
-      if constexpr (PF == 2) {
-        cur_x = vmove<V>(up.x);
-        cur_e0 = vmove(up.e0);
-        if (V == 4) cur_e1 = vmove(up.e1);
-      } else {
-        cur_x = up.x;
-        cur_e0 = up.e0;
-        cur_e1 = up.e1;
+    // the entering plane, masked; then the loads of the plane PF ahead (unconditional, the plane
+    // is clamped, so that no branch join makes them complete early)
+    const int pnext = min(t + PF, phi0);
+    if constexpr (FORM == 0) {
+      mask_plane<L0, V>(c, ring[U]);
+      if (!DOWN) {
+        cur_x = upr[U].x;
+        cur_e0 = upr[U].e0;
+        cur_e1 = upr[U].e1;
       }
+      ring[(U + PF) % R] = load_plane<L0, V>(c, kap, in, col, pnext);
+      if (!DOWN) up_loads(pnext, upr[(U + PF) % R]);
+    } else {
+#pragma unroll
+      for (int s = H + 1; s > 0; --s) pd[s] = pd[s - 1];
+      if constexpr (FORM == 1) {
+        pd[0] = take_plane<L0, V>(pfs[U]);
+        if (!DOWN) {
+          cur_x = vmove<V>(ups[U].x);
+          cur_e0 = vmove(ups[U].e0);
+          if (V == 4) cur_e1 = vmove(ups[U].e1);
+        }
+      } else {
+        pd[0] = pfs[U];
+        if (!DOWN) {
+          cur_x = ups[U].x;
+          cur_e0 = ups[U].e0;
+          cur_e1 = ups[U].e1;
+        }
+      }
+      mask_plane<L0, V>(c, pd[0]);
+      pfs[U] = load_plane<L0, V>(c, kap, in, col, pnext);
+      if (!DOWN) up_loads(pnext, ups[U]);
     }
-    pf = load_plane<L0, V>(c, kap, in, col, min(t + PF, phi0));
-    if (!DOWN) up_loads(min(t + PF, phi0), up.x, up.e0, up.e1);
     // ---- down: restriction of the residual finished in the previous iteration ------------
     // (the children of a coarse cell, summed in the order of the one-pass restriction: for
     // each of its fine planes, the row pair in y, each row's pair in x)
@@ -495,9 +545,9 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
       const int p = t;
       if (in && p <= phi0) {
         if (DOWN) {
-          const Vec<V> &dv = pd[0].dinv;
+          const Vec<V> &dv = plane(0).dinv;
 #pragma unroll
-          for (int e = 0; e < V; ++e) z1.v[e] = (CHEB ? ith : om) * dv.v[e] * pd[0].b.v[e];
+          for (int e = 0; e < V; ++e) z1.v[e] = (CHEB ? ith : om) * dv.v[e] * plane(0).b.v[e];
         } else {
           // x' = x + P e: voxel pairs along x share one coarse parent
           z1 = cur_x;
@@ -521,9 +571,10 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
         const Cell *zp_ = zb(prev, s - 1);
         const Vec<V> ym = from_cell<V>(zp_[rm * exq + q]), yp = from_cell<V>(zp_[rp * exq + q]);
         const float xl = last_of<V>(zp_[lrow * exq + qm]), xr = first_of<V>(zp_[lrow * exq + qp]);
-        const PD &d = pd[s];
+        const PD &d = plane(s);
         const Vec<V> xc = zcv[s];
-        const Vec<V> ax = apply_stencil<L0, V>(c, d, pd[s + 1], p, xc, xl, xr, yp, ym, znv[s], zmv[s]);
+        const Vec<V> ax = apply_stencil<L0, V>(c, d, plane(s + 1), p, xc, xl, xr, yp, ym, znv[s],
+                                               zmv[s]);
         const Vec<V> &dv = d.dinv;
         const Vec<V> &bb = d.b;
         if (KIND == ZM_JAC_DOWN || KIND == ZM_JAC_UP) {
@@ -632,17 +683,29 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
     }
     __syncthreads();
   };
-  if constexpr (PF == 1) {
-    for (int t = t0; t <= t1; ++t) iteration(t, pfA, upA);
-  } else {
-    // pairs of iterations, then an odd last one outside the loop: every path back to the loop
-    // head has issued slot B's loads after slot A's, so the head waits for slot A only
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  if constexpr (FORM == 0) {
+    // whole trips of R iterations, then the remaining ones after the loop: every path back to
+    // the loop head has issued the loads of all R iterations in order, so the head waits only
+    // for the slot it takes
+    int t = t0;
+    for (; t + R - 1 <= t1; t += R)
+      static_for<R>([&](auto k) { iteration(k, t + decltype(k)::value); });
+    static_for<R - 1>([&](auto k) {
+      if (t + decltype(k)::value <= t1) iteration(k, t + decltype(k)::value);
+    });
+  } else if constexpr (FORM == 1) {
+    // pairs of iterations (slot 0, then slot 1), then an odd last one after the loop: every
+    // path back to the loop head has issued slot 1's loads after slot 0's
     int t = t0;
     for (; t + 1 <= t1; t += 2) {
-      iteration(t, pfA, upA);
-      iteration(t + 1, pfB, upB);
+      iteration(I0{}, t);
+      iteration(I1{}, t + 1);
     }
-    if (t <= t1) iteration(t, pfA, upA);
+    if (t <= t1) iteration(I0{}, t);
+  } else {
+    for (int t = t0; t <= t1; ++t) iteration(I0{}, t);
   }
   if (!DOWN && want_dot) {
     const double s = block_sum_any(dot);
