@@ -16,6 +16,7 @@ bounded sample of the same workload.
 """
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -296,6 +297,10 @@ def main():
                     help="c2: apply the ring sensitivity through its geometry (entries recomputed "
                          "in every product) instead of the stored 4096 x 262144 matrix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counts", default=None, metavar="OUTER,INNER",
+                    help="c1-c3: override the workload's outer x inner iteration counts (for "
+                         "profiler runs, which slow every launch; the record's workload text "
+                         "states the override)")
     ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
                     help="set a tiling knob of the problem struct (tune_*), after any autotuning; "
                          "repeatable")
@@ -359,6 +364,10 @@ def main():
             raise SystemExit("--batch applies to the c3 workload only")
         return bench_c3_batch(args)
     p, desc = workload(args.workload)
+    if args.counts:
+        k_out, k_in = (int(x) for x in args.counts.split(","))
+        p = dataclasses.replace(p, outer=k_out, inner=k_in)
+        desc += f" [counts overridden: {k_out} outer x {k_in} inner]"
     nx, ny, nz = p.dims
     n = nx * ny * nz
     print(f"[bench] workload {args.workload}: {desc}", file=sys.stderr, flush=True)
@@ -465,7 +474,6 @@ def main():
         cb, K, S, f_ref = cpu_baseline(p)
         out["cpu_baseline"] = cb
         # the same sample on the GPU, for a parity figure at full size
-        import dataclasses
         q = dataclasses.replace(p, outer=K, inner=S)
         st, _ = eng.wait(eng.submit(op, problem_struct(q, knobs=settings), g, f))
         assert st == 0
@@ -520,7 +528,6 @@ def solve_latency(k, eng, op, pb, g, f):
 
 def adaptive_run(args, eng, op, p, settings, g, f):
     """The workload with the adaptive stops against its fixed-count result (already in f)."""
-    import dataclasses
     import numpy as np
     import torch
     from paper_1308_6634_amd.engine import problem_struct
@@ -632,7 +639,6 @@ def bench_c4(args):
     with the dense products on MFMA (BF16 split products), against the same instances run
     one at a time on the FP32 path; the FP64 oracle timed on a sample and compared with the
     batched GPU result on the same sample."""
-    import dataclasses
     import numpy as np
     import torch
     from gen.configs import c4_matrix, config_c4_batch
