@@ -233,9 +233,12 @@ __device__ __forceinline__ void xg_outputs(const float *__restrict__ src, const 
     for (int e = 0; e < 4 * kXG; ++e) y[e / 4].v[e % 4] += w[k] * win[kShift + e + k];
 }
 
+// upd: also apply a pending f, w update (SC_UPD: f += (phi/rho) w, w = v / alpha - (theta/rho) w,
+// the arithmetic of k_update_fw) to this thread's output voxels; the pass reads v, and f and w
+// are not touched by the product.
 template <int kXG>
 __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int src_sel,
-                                                   int dst_sel, int adj, int epi, Rag rg) {
+                                                   int dst_sel, int adj, int epi, Rag rg, int upd) {
   const Blk k = locate(rg);
   if (k.i < 0) return;
   const InstDesc &D = *descs[k.i];
@@ -261,6 +264,25 @@ __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int 
 #pragma unroll
     for (int g = 0; g < kXG; ++g)
       if (x0 + 4 * g < nx) epilogue4(D, epi, rowbase + x0 + 4 * g, y[g], dst, dot);
+    const double *sc = sld(D.sc);
+    if (upd && sc[SC_UPD] != 0.0 && sc[SC_STOP] == 0.0) {
+      const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
+      float *f = sld(D.f), *w = sld(D.w);
+#pragma unroll
+      for (int g = 0; g < kXG; ++g) {
+        const long long j = rowbase + x0 + 4 * g;
+        if (x0 + 4 * g < nx) {
+          float4 wv = *reinterpret_cast<const float4 *>(w + j);
+          float4 fv = *reinterpret_cast<const float4 *>(f + j);
+          const float4 vv = *reinterpret_cast<const float4 *>(src + j);
+          fv.x += cf * wv.x; fv.y += cf * wv.y; fv.z += cf * wv.z; fv.w += cf * wv.w;
+          wv.x = sv * vv.x - cw * wv.x; wv.y = sv * vv.y - cw * wv.y;
+          wv.z = sv * vv.z - cw * wv.z; wv.w = sv * vv.w - cw * wv.w;
+          *reinterpret_cast<float4 *>(f + j) = fv;
+          *reinterpret_cast<float4 *>(w + j) = wv;
+        }
+      }
+    }
   }
   block_partial(D, epi, dot, k.bx);
 }
@@ -384,17 +406,17 @@ static dim3 grid_of(unsigned g, int B, const Rag &rg) {
 }
 
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups, const Rag &rg) {
+                  int adj, int epi, int groups, const Rag &rg, int upd) {
   const unsigned g = (unsigned)blur_x_blocks(n, nx, groups);
   const dim3 grid = grid_of(g, B, rg);
   if (nx % 4 == 0) {
     const int G = groups ? groups : kDefaultXGroups;
     if (G == 1)
-      hipLaunchKernelGGL(k_blur_xg<1>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+      hipLaunchKernelGGL(k_blur_xg<1>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
     else if (G == 2)
-      hipLaunchKernelGGL(k_blur_xg<2>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+      hipLaunchKernelGGL(k_blur_xg<2>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
     else
-      hipLaunchKernelGGL(k_blur_xg<4>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg);
+      hipLaunchKernelGGL(k_blur_xg<4>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
     return (int)g;
   }
   LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);   // uniform launches only (see the driver)

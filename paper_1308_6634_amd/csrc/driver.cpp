@@ -210,7 +210,8 @@ static void time_end(hipStream_t st, EventList *ev, hipEvent_t a) {
   ev->emplace_back(a, b);
 }
 
-static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi) {
+// upd: the first pass applies a pending f, w update (fused_update)
+static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi, int upd = 0) {
   const InstDesc &H = *bv.h;
   int axes[3], na = 0;
   const int ext[3] = {H.nx, H.ny, H.nz};
@@ -223,7 +224,8 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
     const int e = last ? epi : (EPI_STORE | (epi & (EPI_MASK_INNER | EPI_MASK_OUTER)));
     if (axes[i] == 0)
-      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e, H.blur_xgroups);
+      np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e, H.blur_xgroups, kNoRag,
+                         i == 0 ? upd : 0);
     else
       np = launch_blur_axis(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
                             H.blur_window);
@@ -239,8 +241,19 @@ static int with_mask(const InstDesc &H, int epi) {
   return epi | (epi == EPI_RESID ? EPI_MASK_OUTER : EPI_MASK_INNER);
 }
 
-// y = A x from vector `src`, epilogue `epi`; returns the partial count.
-static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi) {
+// Whether the f, w update of an inner step is applied by the x pass of the next forward product
+// (the pass reads v; f and w are not touched by the product) instead of a launch of its own: a
+// blur operator whose x pass takes four voxels per thread, the fused V-cycle schedule, and no
+// S4 recurrence or stored basis (they run right after the update). The update of the last inner
+// step runs before the per-outer residual, which reads f.
+static bool fused_update(const InstDesc &H) {
+  return H.op_kind == PLSQR_OP_BLUR && H.nx % 4 == 0 && H.n_tau == 0 &&
+         !(H.stop_flags & PLSQR_FLAG_STOP_S4) && H.vcycle_mode != PLSQR_VCYCLE_PER_SWEEP;
+}
+
+// y = A x from vector `src`, epilogue `epi`; returns the partial count. upd: a forward product of
+// an inner step, which applies the previous step's pending update when fused_update holds.
+static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi, bool upd = false) {
   const InstDesc &H = *bv.h;
   hipEvent_t a = nullptr;
   EventList *ev = (epi == EPI_FWD) ? bv.prod_events : nullptr;
@@ -248,7 +261,7 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   int np;
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR)
-    np = blur_chain(st, bv, src, 0, em);
+    np = blur_chain(st, bv, src, 0, em, (upd && fused_update(H)) ? 1 : 0);
   else if (H.op_kind == PLSQR_OP_RING)
     np = launch_ring_forward(st, bv.d_descs, bv.B, H, src, em);
   else if (bv.gemm)
@@ -577,16 +590,22 @@ static void enqueue_s4(hipStream_t st, const BatchView &bv) {
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_S4);
 }
 
-void enqueue_inner(hipStream_t st, const BatchView &bv) {
+// The update step after the alpha reduction: f, w (unless the next forward product applies it),
+// the S4 recurrence, the stored basis.
+static void enqueue_update(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
-  int np = enqueue_forward(st, bv, V_V, EPI_FWD);
+  if (!fused_update(H)) launch_update_fw(st, bv.d_descs, bv.B, H.n);
+  enqueue_s4(st, bv);
+  if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
+}
+
+void enqueue_inner(hipStream_t st, const BatchView &bv) {
+  int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
   enqueue_adjoint(st, bv, EPI_ADJ);
   np = enqueue_vcycle(st, bv);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
-  launch_update_fw(st, bv.d_descs, bv.B, H.n);
-  enqueue_s4(st, bv);
-  if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
+  enqueue_update(st, bv);
 }
 
 // ---------------------------------------------------------------------------------
@@ -632,7 +651,10 @@ void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
     const int em = with_mask(H0, epi);
     const int e_mid = EPI_STORE | (em & (EPI_MASK_INNER | EPI_MASK_OUTER));
     const Rag rx = rag_over(all, [&](int i) { return blur_x_blocks(h(i).n, h(i).nx, H0.blur_xgroups); });
-    launch_blur_x(st, d, B, H0.n, H0.nx, src, V_TMP1, adj, e_mid, H0.blur_xgroups, rx);
+    // the forward product applies the previous step's pending update (ragged_ok implies
+    // fused_update for every instance)
+    launch_blur_x(st, d, B, H0.n, H0.nx, src, V_TMP1, adj, e_mid, H0.blur_xgroups, rx,
+                  (adj == 0 && epi == EPI_FWD) ? 1 : 0);
     const Rag ry = rag_over(all, [&](int i) {
       return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 1, H0.blur_window);
     });
@@ -690,11 +712,12 @@ void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
   launch_vcycle_tail_lds(st, d, B, -1);
   for (int dd = T - 1; dd >= 0; --dd) depth(dd, false);
   launch_finalize(st, d, B, 0, FIN_ALPHA, np);
-  launch_update_fw(st, d, B, H0.n, rag_over(all, [&](int i) { return update_fw_blocks(h(i).n); }));
 }
 
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
+  // the last inner step's update, left pending (fused_update)
+  if (fused_update(H)) launch_update_fw(st, bv.d_descs, bv.B, H.n, kNoRag, 1);
   int np = enqueue_forward(st, bv, V_F, EPI_RESID);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_RESID);
   np = launch_diffusivity(st, bv.d_descs, bv.B, H.n, 1);
@@ -731,7 +754,6 @@ static hipGraphExec_t capture_graph(hipStream_t cap, F body) {
 static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
   if (!gc.execs.empty()) return true;
   if (!gc.cap && hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking) != hipSuccess) return false;
-  const InstDesc &H = *bv.h;
   BatchView quiet = bv;
   quiet.prod_events = nullptr;
   quiet.adj_events = nullptr;
@@ -740,11 +762,7 @@ static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
     const int np = enqueue_vcycle(s, quiet);
     launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
   };
-  auto update_part = [&](hipStream_t s) {
-    launch_update_fw(s, quiet.d_descs, quiet.B, H.n);
-    enqueue_s4(s, quiet);
-    if (H.n_tau > 0) launch_basis_store(s, quiet.d_descs, quiet.B, H.n);
-  };
+  auto update_part = [&](hipStream_t s) { enqueue_update(s, quiet); };
   std::vector<hipGraphExec_t> ex;
   if (bv.vcycle_events) {
     // phases timed: the V-cycle part and the update part replay as two graphs
@@ -794,10 +812,9 @@ void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inn
         else enqueue_inner(st, bv);
         continue;
       }
-      const int np = enqueue_forward(st, bv, V_V, EPI_FWD);
+      const int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
       launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
       enqueue_adjoint(st, bv, EPI_ADJ);
-      const InstDesc &H = *bv.h;
       if (phases) {
         timed_phase(st, bv.vcycle_events, [&] {
           if (use_graphs) {
@@ -808,22 +825,15 @@ void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inn
           }
         });
         timed_phase(st, bv.update_events, [&] {
-          if (use_graphs) {
-            hipGraphLaunch(graphs->execs[1], st);
-          } else {
-            launch_update_fw(st, bv.d_descs, bv.B, H.n);
-            enqueue_s4(st, bv);
-            if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
-          }
+          if (use_graphs) hipGraphLaunch(graphs->execs[1], st);
+          else enqueue_update(st, bv);
         });
       } else if (use_graphs) {
         hipGraphLaunch(graphs->execs[0], st);
       } else {
         const int nq = enqueue_vcycle(st, bv);
         launch_finalize(st, bv.d_descs, bv.B, nq, FIN_ALPHA);
-        launch_update_fw(st, bv.d_descs, bv.B, H.n);
-        enqueue_s4(st, bv);
-        if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
+        enqueue_update(st, bv);
       }
     }
     timed_phase(st, bv.diag_events, [&] { enqueue_outer_end(st, bv); });

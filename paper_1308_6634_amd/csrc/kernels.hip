@@ -527,6 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
   };
   switch (what) {
     case FIN_BETA_INIT: {
+      sc[SC_UPD] = 0.0;
       if (sc[SC_HALT] != 0.0) break;   // the partials were not written (outer loop ended)
       const double beta = sqrt(s);
       if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
@@ -538,6 +539,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       break;
     }
     case FIN_ALPHA_INIT: {
+      sc[SC_UPD] = 0.0;
       if (sc[SC_STOP] != 0.0) break;
       if (!isfinite(s)) { fail(PLSQR_E_NONFINITE); break; }
       if (s < 0.0) { fail(PLSQR_E_NOT_SPD); break; }
@@ -550,6 +552,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       break;
     }
     case FIN_BETA: {
+      sc[SC_UPD] = 0.0;   // the forward product that precedes this applied any pending update
       if (sc[SC_STOP] != 0.0) break;
       const double beta = sqrt(s);
       if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
@@ -592,9 +595,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
       sc[SC_ALPHA] = alpha;
       sc[SC_SV] = 1.0 / alpha;
       sc[SC_DONE] += 1.0;
+      sc[SC_UPD] = 1.0;
       break;
     }
     case FIN_RESID: {
+      sc[SC_UPD] = 0.0;
       if (sc[SC_HALT] != 0.0) break;
       dg[DG_RESID] = sqrt(s);
       dg[DG_INNER] = sc[SC_DONE];
@@ -640,12 +645,15 @@ __global__ void __launch_bounds__(kBlock) k_init_wf(InstDesc *const *descs) {
 
 // f += (phi/rho) w ; w = v/alpha - (theta/rho) w  (Algorithm 2, update step); 4 voxels
 // per thread when n is a multiple of 4.
-__global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs, Rag rg) {
+// pending_only: only an update left pending by the last step (see SC_UPD).
+__global__ void __launch_bounds__(kBlock) k_update_fw(InstDesc *const *descs, int pending_only,
+                                                     Rag rg) {
   const Blk k = locate(rg);
   if (k.i < 0) return;
   const InstDesc &D = *descs[k.i];
   const double *sc = sld(D.sc);
   if (sc[SC_STOP] != 0.0) return;
+  if (pending_only && sc[SC_UPD] == 0.0) return;
   const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
   const long long t = (long long)k.bx * kBlock + threadIdx.x;
   if ((sld(D.n) & 3) == 0) {
@@ -906,13 +914,13 @@ void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int 
 void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n) {
   LAUNCH(k_init_wf, blocks_for(n), B, d);
 }
-int update_fw_blocks(long long n) { return (int)blocks_for((n + 3) / 4); }
-void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n, const Rag &rg) {
+void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n, const Rag &rg,
+                      int pending_only) {
   if (rg.n == 0) {
-    LAUNCH(k_update_fw, blocks_for((n + 3) / 4), B, d, rg);
+    LAUNCH(k_update_fw, blocks_for((n + 3) / 4), B, d, pending_only, rg);
   } else {
     const unsigned g = (unsigned)(rg.first[rg.n - 1] + rg.count[rg.n - 1]);
-    LAUNCH(k_update_fw, g, 1, d, rg);
+    LAUNCH(k_update_fw, g, 1, d, pending_only, rg);
   }
 }
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n) {

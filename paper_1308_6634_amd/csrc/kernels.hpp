@@ -100,8 +100,10 @@ int zm_threads(const ZmShape &s, int H);
 // groups: 4-output groups per thread when nx % 4 == 0 (1, 2 or 4; 0: default)
 // rg: a ragged map (then nx % 4 == 0 for every instance), or kNoRag for B same-shaped
 // instances; returns the blocks per instance of a uniform launch
+// upd: the first pass of a forward product from v also applies a pending f, w update (SC_UPD)
+// to its output voxels (nx % 4 == 0)
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups, const Rag &rg = kNoRag);
+                  int adj, int epi, int groups, const Rag &rg = kNoRag, int upd = 0);
 // y (axis 1) or z (axis 2) pass; window: outputs per thread along the axis (4, 8, 16 or 32;
 // 0: default)
 int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
@@ -118,9 +120,9 @@ int launch_copy_g_u(hipStream_t st, InstDesc *const *d, int B, long long m);
 void launch_finalize(hipStream_t st, InstDesc *const *d, int B, int nparts, int what,
                      const Rag &np = kNoRag);
 void launch_init_wf(hipStream_t st, InstDesc *const *d, int B, long long n);
+// pending_only: only where the last MLSQR step left its update pending (SC_UPD)
 void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n,
-                      const Rag &rg = kNoRag);
-int update_fw_blocks(long long n);
+                      const Rag &rg = kNoRag, int pending_only = 0);
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n);
 // batched dense products on MFMA (gemm_bf16.hip)
 int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,

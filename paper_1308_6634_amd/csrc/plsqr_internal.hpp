@@ -38,6 +38,8 @@ enum ScalarSlot : int {
   SC_LAMBDA,      // sqrt(tau)
   SC_HALT,        // 1 once the outer stop has fired: later outer steps change nothing
   SC_S4R,         // ||g - A f_i|| of the last completed step (S4 recurrence)
+  SC_UPD,         // 1 while the f, w update of the last completed step is pending: the x pass
+                  // of the next forward product applies it (see fused_update in the driver)
   SC_COUNT = 16
 };
 
