@@ -704,7 +704,11 @@ def bench_c4(args):
     fwd_ms = ph.forward_ms / max(ph.forward_launches, 1)
     adj_ms = ph.adjoint_ms / max(ph.adjoint_launches, 1)
     lo = 2 if prec == P.PLSQR_PREC_BF16_REFINED else 1
-    fwd_bytes = lo * 2 * m * n + 2 * 2 * 64 * n
+    # A (hi and lo parts) and the packed right operand, plus the previous step's f, w update that
+    # the packing applies (16 B per voxel and instance, every inner step but the first of an
+    # outer iteration)
+    fwd_bytes = (lo * 2 * m * n + 2 * 2 * 64 * n
+                 + 16 * B * n * (p0.inner - 1) / p0.inner)
     fwd_flops = 2.0 * m * n * 64 * (lo + 1)
     print(f"[bench] batched: {elapsed / args.steps * 1e3:.1f} ms per batch; forward product "
           f"{fwd_ms:.3f} ms, adjoint {adj_ms:.3f} ms", file=sys.stderr, flush=True)

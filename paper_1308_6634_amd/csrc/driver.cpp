@@ -241,14 +241,18 @@ static int with_mask(const InstDesc &H, int epi) {
   return epi | (epi == EPI_RESID ? EPI_MASK_OUTER : EPI_MASK_INNER);
 }
 
-// Whether the f, w update of an inner step is applied by the x pass of the next forward product
-// (the pass reads v; f and w are not touched by the product) instead of a launch of its own: a
-// blur operator whose x pass takes four voxels per thread, the fused V-cycle schedule, and no
-// S4 recurrence or stored basis (they run right after the update). The update of the last inner
-// step runs before the per-outer residual, which reads f.
-static bool fused_update(const InstDesc &H) {
-  return H.op_kind == PLSQR_OP_BLUR && H.nx % 4 == 0 && H.n_tau == 0 &&
-         !(H.stop_flags & PLSQR_FLAG_STOP_S4) && H.vcycle_mode != PLSQR_VCYCLE_PER_SWEEP;
+// Whether the f, w update of an inner step is applied by the first kernel of the next forward
+// product, which reads v anyway (f and w are not touched by the product), instead of a launch of
+// its own: the x pass of a blur operator with four voxels per thread or the packing of the
+// batched MFMA product, with the fused V-cycle schedule and no S4 recurrence or stored basis
+// (they run right after the update). The update of the last inner step runs before the
+// per-outer residual, which reads f.
+static bool fused_update(const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  if (H.n_tau > 0 || (H.stop_flags & PLSQR_FLAG_STOP_S4) || H.vcycle_mode == PLSQR_VCYCLE_PER_SWEEP)
+    return false;
+  // the blur x pass (four voxels per thread) or the packing of the batched MFMA product
+  return (H.op_kind == PLSQR_OP_BLUR && H.nx % 4 == 0) || (H.op_kind == PLSQR_OP_DENSE && bv.gemm);
 }
 
 // y = A x from vector `src`, epilogue `epi`; returns the partial count. upd: a forward product of
@@ -261,11 +265,12 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   int np;
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR)
-    np = blur_chain(st, bv, src, 0, em, (upd && fused_update(H)) ? 1 : 0);
+    np = blur_chain(st, bv, src, 0, em, (upd && fused_update(bv)) ? 1 : 0);
   else if (H.op_kind == PLSQR_OP_RING)
     np = launch_ring_forward(st, bv.d_descs, bv.B, H, src, em);
   else if (bv.gemm)
-    np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, em);
+    np = launch_gemm_forward(st, bv.d_descs, bv.B, *bv.gemm, H.m, H.n, src, em,
+                             (upd && fused_update(bv)) ? 1 : 0);
   else
     np = launch_gemv_rows(st, bv.d_descs, bv.B, H.m, src, em, H.gemv_rows);
   time_end(st, ev, a);
@@ -594,7 +599,7 @@ static void enqueue_s4(hipStream_t st, const BatchView &bv) {
 // the S4 recurrence, the stored basis.
 static void enqueue_update(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
-  if (!fused_update(H)) launch_update_fw(st, bv.d_descs, bv.B, H.n);
+  if (!fused_update(bv)) launch_update_fw(st, bv.d_descs, bv.B, H.n);
   enqueue_s4(st, bv);
   if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
 }
@@ -717,7 +722,7 @@ void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
   // the last inner step's update, left pending (fused_update)
-  if (fused_update(H)) launch_update_fw(st, bv.d_descs, bv.B, H.n, kNoRag, 1);
+  if (fused_update(bv)) launch_update_fw(st, bv.d_descs, bv.B, H.n, kNoRag, 1);
   int np = enqueue_forward(st, bv, V_F, EPI_RESID);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_RESID);
   np = launch_diffusivity(st, bv.d_descs, bv.B, H.n, 1);

@@ -254,14 +254,28 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(InstDesc *const *descs, c
 }
 
 // Pack the right operand: column b of (Rhi, Rlo) = split of vector `sel` of instance b
-// (length len); padding columns b >= B are zero.
+// (length len); padding columns b >= B are zero. upd (forward product from v): also apply the
+// instance's pending f, w update (SC_UPD: f += (phi/rho) w, w = v / alpha - (theta/rho) w, the
+// arithmetic of k_update_fw) to element k, which this thread reads anyway.
 __global__ void __launch_bounds__(kBlock) k_pack_split(InstDesc *const *descs, int B, int sel,
-                                                      long long len, __bf16 *Rhi, __bf16 *Rlo) {
+                                                      long long len, __bf16 *Rhi, __bf16 *Rlo,
+                                                      int upd) {
   const int b = blockIdx.y;
   const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (k >= len) return;
   float x = 0.f;
-  if (b < B) x = vec_of(*descs[b], sel)[k];
+  if (b < B) {
+    const InstDesc &D = *descs[b];
+    x = vec_of(D, sel)[k];
+    const double *sc = sld(D.sc);
+    if (upd && sc[SC_UPD] != 0.0 && sc[SC_STOP] == 0.0) {
+      const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
+      float *f = sld(D.f), *w = sld(D.w);
+      const float wk = w[k];
+      f[k] += cf * wk;
+      w[k] = sv * x - cw * wk;
+    }
+  }
   const __bf16 hi = (__bf16)x;
   const __bf16 lo = (__bf16)(x - (float)hi);
   Rhi[(long long)b * len + k] = hi;
@@ -372,10 +386,10 @@ static void gemm_dispatch(hipStream_t st, int NT, bool lo_l, const void *L, cons
 
 // Forward product of the batch: u-epilogue (or residual) per instance; returns partials.
 int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
-                        long long n, int src_sel, int epi) {
+                        long long n, int src_sel, int epi, int upd) {
   const unsigned pb = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_pack_split, dim3(pb, g.Bpad), dim3(kBlock), 0, st, d, B, src_sel, n,
-                     (__bf16 *)g.X_hi, (__bf16 *)g.X_lo);
+                     (__bf16 *)g.X_hi, (__bf16 *)g.X_lo, upd);
   gemm_dispatch<false>(st, g.Bpad / 32, g.use_A_lo != 0, g.A_t, g.X_hi, g.X_lo, m, n, g.kchunk,
                        g.ks, g.Bpad, g.Ypart, d, B, epi);
   const unsigned rb = (unsigned)((m + kBlock - 1) / kBlock);
@@ -389,7 +403,7 @@ void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmAr
                          long long n, int epi) {
   const unsigned pb = (unsigned)((m + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_pack_split, dim3(pb, g.Bpad), dim3(kBlock), 0, st, d, B, (int)V_U, m,
-                     (__bf16 *)g.U_hi, (__bf16 *)g.U_lo);
+                     (__bf16 *)g.U_hi, (__bf16 *)g.U_lo, 0);
   gemm_dispatch<true>(st, g.Bpad / 32, g.use_A_lo != 0, g.At_t, g.U_hi, g.U_lo, n, m, m, 1,
                       g.Bpad, nullptr, d, B, epi);
 }

@@ -125,8 +125,9 @@ void launch_update_fw(hipStream_t st, InstDesc *const *d, int B, long long n,
                       const Rag &rg = kNoRag, int pending_only = 0);
 int launch_dot_vp(hipStream_t st, InstDesc *const *d, int B, long long n);
 // batched dense products on MFMA (gemm_bf16.hip)
+// upd: the packing also applies a pending f, w update (SC_UPD) of the product's instances
 int launch_gemm_forward(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
-                        long long n, int src_sel, int epi);
+                        long long n, int src_sel, int epi, int upd = 0);
 void launch_gemm_adjoint(hipStream_t st, InstDesc *const *d, int B, const GemmArgs &g, long long m,
                          long long n, int epi);
 // Tiled BF16 left operands of the batched products (n_y, n_x divisible by 256), stored as
