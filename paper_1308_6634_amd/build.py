@@ -23,7 +23,7 @@ KERNEL_SOURCES = ["kernels.hip", "smooth_vec.hip", "blur.hip", "dense.hip", "gem
                   "ring.hip", "static_scratch.hip", "zmarch.hip",
                   "tail_lds.hip"]
 HOST_SOURCES = ["driver.cpp", "api.cpp"]
-HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp", "device_common.hpp"]
+HEADERS = ["plsqr_internal.hpp", "kernels.hpp", "engine.hpp", "device_common.hpp", "finalize.hpp"]
 
 # Packed-FP32 instructions are disabled for every device compile (the compiler would
 # otherwise form v_pk_* FP32 ops from ordinary float code). Kernel arguments are preloaded

@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "device_common.hpp"
+#include "finalize.hpp"
 #include "kernels.hpp"
 
 namespace plsqr {
@@ -233,15 +234,40 @@ __device__ __forceinline__ void xg_outputs(const float *__restrict__ src, const 
     for (int e = 0; e < 4 * kXG; ++e) y[e / 4].v[e % 4] += w[k] * win[kShift + e + k];
 }
 
-// upd: also apply a pending f, w update (SC_UPD: f += (phi/rho) w, w = v / alpha - (theta/rho) w,
-// the arithmetic of k_update_fw) to this thread's output voxels; the pass reads v, and f and w
-// are not touched by the product.
+// The pending f, w update at voxel j (SC_UPD: f += (phi/rho) w, w = v / alpha - (theta/rho) w,
+// the arithmetic of k_update_fw), v_j given.
+__device__ __forceinline__ void update_at(float *f, float *w, long long j, float vj, float cf,
+                                          float cw, float sv) {
+  const float wj = w[j];
+  f[j] += cf * wj;
+  w[j] = sv * vj - cw * wj;
+}
+
+// Partial count of the finaliser block's instance i: fin_np.count[e] for fin_np.inst[e] == i
+// (a ragged launch), else fin_n.
+__device__ __forceinline__ int fin_parts(int i, int fin_n, const Rag &fin_np) {
+  if (fin_np.n == 0) return fin_n;
+  int c = 0;
+  for (int e = 0; e < fin_np.n; ++e)
+    if (fin_np.inst[e] == i) c = fin_np.count[e];
+  return c;
+}
+
+// upd: also apply a pending f, w update (update_at) to this thread's output voxels; the pass
+// reads v, and f and w are not touched by the product. fin >= 0: the last block of each
+// instance is a finaliser block instead (fin_block with its fin_parts partials, from the
+// launch before): the first pass of a product reads none of the scalars a finaliser writes.
 template <int kXG>
 __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int src_sel,
-                                                   int dst_sel, int adj, int epi, Rag rg, int upd) {
+                                                   int dst_sel, int adj, int epi, Rag rg, int upd,
+                                                   int fin, int fin_n, Rag fin_np) {
   const Blk k = locate(rg);
   if (k.i < 0) return;
   const InstDesc &D = *descs[k.i];
+  if (fin >= 0 && k.bx == k.gx - 1) {
+    fin_block(D, fin_parts(k.i, fin_n, fin_np), fin);
+    return;
+  }
   if (product_masked(D, epi)) return;
   const int r = sld(D.radius);
   const int nx = sld(D.nx);
@@ -281,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_blur_xg(InstDesc *const *descs, int 
           *reinterpret_cast<float4 *>(f + j) = fv;
           *reinterpret_cast<float4 *>(w + j) = wv;
         }
-      }
+      }   // (update_at's arithmetic, four voxels at a time)
     }
   }
   block_partial(D, epi, dot, k.bx);
@@ -337,10 +363,12 @@ __device__ __forceinline__ double win_outputs(const InstDesc &D, int epi,
   return dot;
 }
 
+// upd: also apply a pending f, w update (update_at) to this thread's output voxels (the forward
+// product's second pass when the first carries a finaliser block).
 template <int kWinS>
 __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int axis,
                                                     int src_sel, int dst_sel, int adj, int epi,
-                                                    Rag rg) {
+                                                    Rag rg, int upd) {
   const Blk k = locate(rg);
   if (k.i < 0) return;
   const InstDesc &D = *descs[k.i];
@@ -370,6 +398,19 @@ __global__ void __launch_bounds__(kBlock) k_blur_win(InstDesc *const *descs, int
 #define PLSQR_WIN(RR) dot = win_outputs<kWinS, RR>(D, epi, src, dst, pre_src, T, base, sa, seg * kWinS, na)
     PLSQR_RADIUS_SWITCH(r, PLSQR_WIN)
 #undef PLSQR_WIN
+    const double *sc = sld(D.sc);
+    if (upd && sc[SC_UPD] != 0.0 && sc[SC_STOP] == 0.0) {
+      const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
+      float *f = sld(D.f), *w = sld(D.w);
+      const float *v = sld(D.v);
+      const int a0 = seg * kWinS;
+      float vq[kWinS];
+#pragma unroll
+      for (int q = 0; q < kWinS; ++q) vq[q] = (a0 + q < na) ? v[base + (long long)(a0 + q) * sa] : 0.f;
+#pragma unroll
+      for (int q = 0; q < kWinS; ++q)
+        if (a0 + q < na) update_at(f, w, base + (long long)(a0 + q) * sa, vq[q], cf, cw, sv);
+    }
   }
   block_partial(D, epi, dot, k.bx);
 }
@@ -406,35 +447,40 @@ static dim3 grid_of(unsigned g, int B, const Rag &rg) {
 }
 
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups, const Rag &rg, int upd) {
+                  int adj, int epi, int groups, const Rag &rg, int upd, int fin, int fin_n,
+                  const Rag &fin_np) {
   const unsigned g = (unsigned)blur_x_blocks(n, nx, groups);
-  const dim3 grid = grid_of(g, B, rg);
+  // a uniform launch's finaliser blocks: one more block per instance (a ragged map counts them)
+  const dim3 grid = grid_of(fin >= 0 ? g + 1 : g, B, rg);
   if (nx % 4 == 0) {
     const int G = groups ? groups : kDefaultXGroups;
     if (G == 1)
-      hipLaunchKernelGGL(k_blur_xg<1>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
+      hipLaunchKernelGGL(k_blur_xg<1>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd,
+                         fin, fin_n, fin_np);
     else if (G == 2)
-      hipLaunchKernelGGL(k_blur_xg<2>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
+      hipLaunchKernelGGL(k_blur_xg<2>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd,
+                         fin, fin_n, fin_np);
     else
-      hipLaunchKernelGGL(k_blur_xg<4>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd);
+      hipLaunchKernelGGL(k_blur_xg<4>, grid, dim3(kBlock), 0, st, d, src, dst, adj, epi, rg, upd,
+                         fin, fin_n, fin_np);
     return (int)g;
   }
   LAUNCH_B(k_blur_x, g, B, d, src, dst, adj, epi);   // uniform launches only (see the driver)
   return (int)g;
 }
 int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                     int src, int dst, int adj, int epi, int window, const Rag &rg) {
+                     int src, int dst, int adj, int epi, int window, const Rag &rg, int upd) {
   const int S = window ? window : kDefaultWindow;
   const unsigned g = (unsigned)blur_axis_blocks(nx, ny, nz, axis, window);
   const dim3 grid = grid_of(g, B, rg);
   if (S == 4)
-    hipLaunchKernelGGL(k_blur_win<4>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
+    hipLaunchKernelGGL(k_blur_win<4>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg, upd);
   else if (S == 8)
-    hipLaunchKernelGGL(k_blur_win<8>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
+    hipLaunchKernelGGL(k_blur_win<8>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg, upd);
   else if (S == 32)
-    hipLaunchKernelGGL(k_blur_win<32>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
+    hipLaunchKernelGGL(k_blur_win<32>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg, upd);
   else
-    hipLaunchKernelGGL(k_blur_win<16>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg);
+    hipLaunchKernelGGL(k_blur_win<16>, grid, dim3(kBlock), 0, st, d, axis, src, dst, adj, epi, rg, upd);
   return (int)g;
 }
 

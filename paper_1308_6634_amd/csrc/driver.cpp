@@ -210,8 +210,11 @@ static void time_end(hipStream_t st, EventList *ev, hipEvent_t a) {
   ev->emplace_back(a, b);
 }
 
-// upd: the first pass applies a pending f, w update (fused_update)
-static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi, int upd = 0) {
+// upd: the product applies a pending f, w update (fused_update): its first pass, or its second
+// when the first carries a finaliser block. fin >= 0 (fin_blocks): the first pass (the x pass)
+// also runs finaliser fin on the fin_n partials of the launch before it, in a block of its own.
+static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int epi, int upd = 0,
+                      int fin = -1, int fin_n = 0) {
   const InstDesc &H = *bv.h;
   int axes[3], na = 0;
   const int ext[3] = {H.nx, H.ny, H.nz};
@@ -223,12 +226,13 @@ static int blur_chain(hipStream_t st, const BatchView &bv, int src, int adj, int
     const bool last = (i == na - 1);
     const int dst = last ? V_TMP2 : ((i % 2 == 0) ? V_TMP1 : V_TMP2);
     const int e = last ? epi : (EPI_STORE | (epi & (EPI_MASK_INNER | EPI_MASK_OUTER)));
+    const int u = (i == (fin >= 0 ? 1 : 0)) ? upd : 0;
     if (axes[i] == 0)
       np = launch_blur_x(st, bv.d_descs, bv.B, H.n, H.nx, cur, dst, adj, e, H.blur_xgroups, kNoRag,
-                         i == 0 ? upd : 0);
+                         u, i == 0 ? fin : -1, fin_n);
     else
       np = launch_blur_axis(st, bv.d_descs, bv.B, H.nx, H.ny, H.nz, axes[i], cur, dst, adj, e,
-                            H.blur_window);
+                            H.blur_window, kNoRag, u);
     cur = dst;
   }
   return np;
@@ -257,7 +261,9 @@ static bool fused_update(const BatchView &bv) {
 
 // y = A x from vector `src`, epilogue `epi`; returns the partial count. upd: a forward product of
 // an inner step, which applies the previous step's pending update when fused_update holds.
-static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi, bool upd = false) {
+// fin, fin_n: a finaliser block in the first pass (blur operators under fin_blocks).
+static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi, bool upd = false,
+                           int fin = -1, int fin_n = 0) {
   const InstDesc &H = *bv.h;
   hipEvent_t a = nullptr;
   EventList *ev = (epi == EPI_FWD) ? bv.prod_events : nullptr;
@@ -265,7 +271,7 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   int np;
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR)
-    np = blur_chain(st, bv, src, 0, em, (upd && fused_update(bv)) ? 1 : 0);
+    np = blur_chain(st, bv, src, 0, em, (upd && fused_update(bv)) ? 1 : 0, fin, fin_n);
   else if (H.op_kind == PLSQR_OP_RING)
     np = launch_ring_forward(st, bv.d_descs, bv.B, H, src, em);
   else if (bv.gemm)
@@ -277,15 +283,17 @@ static int enqueue_forward(hipStream_t st, const BatchView &bv, int src, int epi
   return np;
 }
 
-// p <- su A^T u (- beta sv p).
-static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi) {
+// p <- su A^T u (- beta sv p). fin, fin_n: a finaliser block in the first pass (blur operators
+// under fin_blocks).
+static void enqueue_adjoint(hipStream_t st, const BatchView &bv, int epi, int fin = -1,
+                            int fin_n = 0) {
   const InstDesc &H = *bv.h;
   hipEvent_t a = nullptr;
   EventList *ev = (epi == EPI_ADJ) ? bv.adj_events : nullptr;
   time_begin(st, ev, &a);
   const int em = with_mask(H, epi);
   if (H.op_kind == PLSQR_OP_BLUR) {
-    blur_chain(st, bv, V_U, 1, em);
+    blur_chain(st, bv, V_U, 1, em, 0, fin, fin_n);
   } else if (H.op_kind == PLSQR_OP_RING) {
     launch_ring_adjoint(st, bv.d_descs, bv.B, H, em);
   } else if (bv.gemm) {
@@ -425,6 +433,29 @@ void plan_vcycle(InstDesc &D, const Layout &Ly) {
   D.tail_lds_t = P.t;
   for (int l = 0; l < P.t; ++l)
     if (P.fz[l]) D.zmp[l] = ZmPlan{P.shp[l].tx, P.shp[l].ty, P.shp[l].zc, P.shp[l].v};
+}
+
+// Whether the beta and alpha finalisers of an inner step run in finaliser blocks of the next
+// product's first pass instead of launches of their own: the first pass of a blur product reads
+// none of the scalars they write, so the beta finaliser rides in the adjoint product's x pass and
+// the alpha finaliser of the V-cycle in the next forward product's x pass (or, after the last
+// inner step, in a launch of its own before the per-outer residual); the pending f, w update then
+// moves to the forward product's second pass. Needs the fused update, a blur operator whose
+// product starts with the four-voxel x pass and has a second pass, and a V-cycle that ends in
+// level 0's fused up kernel (its partial count is known before it runs: vcycle_parts).
+static bool fin_blocks(const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  if (!fused_update(bv) || H.op_kind != PLSQR_OP_BLUR || H.nx % 4 != 0) return false;
+  if (H.ny < 2 && H.nz < 2) return false;
+  if (H.levels < 2) return false;
+  return vcycle_plan(H, *bv.lay).fz[0];
+}
+
+// Partials of the alpha reduction that a fused V-cycle leaves: one per block of level 0's up
+// kernel.
+static int vcycle_parts(const InstDesc &H, const Layout &Ly) {
+  const VcPlan P = vcycle_plan(H, Ly);
+  return (int)zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], P.shp[0]);
 }
 
 static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
@@ -604,12 +635,35 @@ static void enqueue_update(hipStream_t st, const BatchView &bv) {
   if (H.n_tau > 0) launch_basis_store(st, bv.d_descs, bv.B, H.n);
 }
 
-void enqueue_inner(hipStream_t st, const BatchView &bv) {
-  int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
+// Whether enqueue_update enqueues nothing: the update rides on the next forward product, and
+// there is no S4 recurrence or stored basis (fused_update requires both).
+static bool update_fused_whole(const BatchView &bv) { return fused_update(bv); }
+
+// The products of an inner step with the beta finaliser between them; under fin_blocks the
+// alpha finaliser of the last V-cycle (if one is pending) rides in the forward product and beta
+// in the adjoint product.
+static void enqueue_inner_products(hipStream_t st, const BatchView &bv) {
+  if (fin_blocks(bv)) {
+    const int nb = enqueue_forward(st, bv, V_V, EPI_FWD, true, FIN_ALPHA_PEND,
+                                   vcycle_parts(*bv.h, *bv.lay));
+    enqueue_adjoint(st, bv, EPI_ADJ, FIN_BETA_PEND, nb);
+    return;
+  }
+  const int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
   enqueue_adjoint(st, bv, EPI_ADJ);
-  np = enqueue_vcycle(st, bv);
-  launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
+}
+
+// The V-cycle of an inner step and the alpha finaliser (under fin_blocks its partials wait for
+// the next forward product).
+static void enqueue_inner_vcycle(hipStream_t st, const BatchView &bv) {
+  const int np = enqueue_vcycle(st, bv);
+  if (!fin_blocks(bv)) launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
+}
+
+void enqueue_inner(hipStream_t st, const BatchView &bv) {
+  enqueue_inner_products(st, bv);
+  enqueue_inner_vcycle(st, bv);
   enqueue_update(st, bv);
 }
 
@@ -651,41 +705,48 @@ void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
   std::vector<int> all(B);
   for (int i = 0; i < B; ++i) all[i] = i;
   auto h = [&](int i) -> const InstDesc & { return *rb.h[i]; };
-  // blur product: x, y, z passes, the last with the epilogue; returns the last pass's map
-  auto blur = [&](int src, int adj, int epi) {
-    const int em = with_mask(H0, epi);
-    const int e_mid = EPI_STORE | (em & (EPI_MASK_INNER | EPI_MASK_OUTER));
-    const Rag rx = rag_over(all, [&](int i) { return blur_x_blocks(h(i).n, h(i).nx, H0.blur_xgroups); });
-    // the forward product applies the previous step's pending update (ragged_ok implies
-    // fused_update for every instance)
-    launch_blur_x(st, d, B, H0.n, H0.nx, src, V_TMP1, adj, e_mid, H0.blur_xgroups, rx,
-                  (adj == 0 && epi == EPI_FWD) ? 1 : 0);
-    const Rag ry = rag_over(all, [&](int i) {
-      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 1, H0.blur_window);
-    });
-    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 1, V_TMP1, V_TMP2, adj, e_mid, H0.blur_window, ry);
-    const Rag rz = rag_over(all, [&](int i) {
-      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 2, H0.blur_window);
-    });
-    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 2, V_TMP2, V_TMP2, adj, em, H0.blur_window, rz);
-    return rz;
-  };
-  launch_finalize(st, d, B, 0, FIN_BETA, blur(V_V, 0, EPI_FWD));
-  blur(V_U, 1, EPI_ADJ);
-
-  // V-cycle by depth from the finest level: the down halves of depth 0, 1, .. (an instance takes
-  // part while the depth is above its tail), every instance's LDS-resident tail in one launch,
-  // then the up halves back to depth 0; instances of one depth with different voxels per
-  // thread take one launch each
   std::vector<VcPlan> P(B);
   int T = 0;
   for (int i = 0; i < B; ++i) {
     P[i] = vcycle_plan(h(i), *rb.lay[i]);
     T = std::max(T, P[i].t);
   }
+  // blur product: x, y, z passes, the last with the epilogue; the x pass carries a finaliser
+  // block per instance for `fin` on the partial counts fnp (ragged_ok implies fin_blocks for
+  // every instance), the forward product's y pass applies the pending update; returns the last
+  // pass's map
+  auto blur = [&](int src, int adj, int epi, int fin, const Rag &fnp) {
+    const int em = with_mask(H0, epi);
+    const int e_mid = EPI_STORE | (em & (EPI_MASK_INNER | EPI_MASK_OUTER));
+    const Rag rx = rag_over(all, [&](int i) { return blur_x_blocks(h(i).n, h(i).nx, H0.blur_xgroups) + 1; });
+    launch_blur_x(st, d, B, H0.n, H0.nx, src, V_TMP1, adj, e_mid, H0.blur_xgroups, rx, 0, fin, 0,
+                  fnp);
+    const Rag ry = rag_over(all, [&](int i) {
+      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 1, H0.blur_window);
+    });
+    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 1, V_TMP1, V_TMP2, adj, e_mid, H0.blur_window, ry,
+                     (adj == 0 && epi == EPI_FWD) ? 1 : 0);
+    const Rag rz = rag_over(all, [&](int i) {
+      return blur_axis_blocks(h(i).nx, h(i).ny, h(i).nz, 2, H0.blur_window);
+    });
+    launch_blur_axis(st, d, B, H0.nx, H0.ny, H0.nz, 2, V_TMP2, V_TMP2, adj, em, H0.blur_window, rz);
+    return rz;
+  };
+  // the pending alpha finaliser of each instance's last V-cycle: one partial per block of its
+  // level-0 up kernel
+  const Rag na = rag_over(all, [&](int i) {
+    const Layout &Ly = *rb.lay[i];
+    return (int)zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], P[i].shp[0]);
+  });
+  const Rag nb = blur(V_V, 0, EPI_FWD, FIN_ALPHA_PEND, na);
+  blur(V_U, 1, EPI_ADJ, FIN_BETA_PEND, nb);
+
+  // V-cycle by depth from the finest level: the down halves of depth 0, 1, .. (an instance takes
+  // part while the depth is above its tail), every instance's LDS-resident tail in one launch,
+  // then the up halves back to depth 0; instances of one depth with different voxels per
+  // thread take one launch each; level 0's partials of v.p wait for the next forward product
   const int H = P[0].hz;
   const bool jac = H0.smoother == PLSQR_SMOOTH_JACOBI;
-  Rag np{};
   auto depth = [&](int dd, bool down) {
     for (int v : {4, 1}) {
       std::vector<int> who;
@@ -705,23 +766,19 @@ void enqueue_inner_ragged(hipStream_t st, const RagBatch &rb) {
       const int kind = down ? (jac ? ZM_JAC_DOWN : ZM_CHEB_DOWN) : (jac ? ZM_JAC_UP : ZM_CHEB_UP);
       const int want = (!down && dd == 0) ? 1 : 0;
       launch_zm_ragged(st, d, kind, H, dd, v, threads, lds, rg, want);
-      if (want)
-        for (int k = 0; k < rg.n; ++k) {
-          np.inst[np.n] = rg.inst[k];
-          np.count[np.n] = rg.count[k];
-          ++np.n;
-        }
     }
   };
   for (int dd = 0; dd < T; ++dd) depth(dd, true);
   launch_vcycle_tail_lds(st, d, B, -1);
   for (int dd = T - 1; dd >= 0; --dd) depth(dd, false);
-  launch_finalize(st, d, B, 0, FIN_ALPHA, np);
 }
 
 void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
   const InstDesc &H = *bv.h;
-  // the last inner step's update, left pending (fused_update)
+  // the last inner step's alpha finaliser, left pending (fin_blocks), and its update, left
+  // pending (fused_update)
+  if (fin_blocks(bv))
+    launch_finalize(st, bv.d_descs, bv.B, vcycle_parts(H, *bv.lay), FIN_ALPHA_PEND);
   if (fused_update(bv)) launch_update_fw(st, bv.d_descs, bv.B, H.n, kNoRag, 1);
   int np = enqueue_forward(st, bv, V_F, EPI_RESID);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_RESID);
@@ -763,16 +820,14 @@ static bool prepare_inner_graphs(const BatchView &bv, GraphCache &gc) {
   quiet.prod_events = nullptr;
   quiet.adj_events = nullptr;
   const bool timed = bv.prod_events != nullptr;
-  auto vcycle_part = [&](hipStream_t s) {
-    const int np = enqueue_vcycle(s, quiet);
-    launch_finalize(s, quiet.d_descs, quiet.B, np, FIN_ALPHA);
-  };
+  auto vcycle_part = [&](hipStream_t s) { enqueue_inner_vcycle(s, quiet); };
   auto update_part = [&](hipStream_t s) { enqueue_update(s, quiet); };
   std::vector<hipGraphExec_t> ex;
   if (bv.vcycle_events) {
-    // phases timed: the V-cycle part and the update part replay as two graphs
+    // phases timed: the V-cycle part and the update part replay as two graphs (the update part
+    // is empty when the next forward product applies the update)
     ex.push_back(capture_graph(gc.cap, vcycle_part));
-    ex.push_back(capture_graph(gc.cap, update_part));
+    if (!update_fused_whole(bv)) ex.push_back(capture_graph(gc.cap, update_part));
   } else if (timed) {
     ex.push_back(capture_graph(gc.cap, [&](hipStream_t s) {
       vcycle_part(s);
@@ -817,27 +872,21 @@ void enqueue_whole_solve(hipStream_t st, const BatchView &bv, int outer, int inn
         else enqueue_inner(st, bv);
         continue;
       }
-      const int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
-      launch_finalize(st, bv.d_descs, bv.B, np, FIN_BETA);
-      enqueue_adjoint(st, bv, EPI_ADJ);
+      enqueue_inner_products(st, bv);
       if (phases) {
         timed_phase(st, bv.vcycle_events, [&] {
-          if (use_graphs) {
-            hipGraphLaunch(graphs->execs[0], st);
-          } else {
-            const int nq = enqueue_vcycle(st, bv);
-            launch_finalize(st, bv.d_descs, bv.B, nq, FIN_ALPHA);
-          }
+          if (use_graphs) hipGraphLaunch(graphs->execs[0], st);
+          else enqueue_inner_vcycle(st, bv);
         });
         timed_phase(st, bv.update_events, [&] {
+          if (update_fused_whole(bv)) return;
           if (use_graphs) hipGraphLaunch(graphs->execs[1], st);
           else enqueue_update(st, bv);
         });
       } else if (use_graphs) {
         hipGraphLaunch(graphs->execs[0], st);
       } else {
-        const int nq = enqueue_vcycle(st, bv);
-        launch_finalize(st, bv.d_descs, bv.B, nq, FIN_ALPHA);
+        enqueue_inner_vcycle(st, bv);
         enqueue_update(st, bv);
       }
     }

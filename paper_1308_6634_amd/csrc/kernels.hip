@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "device_common.hpp"
+#include "finalize.hpp"
 #include "kernels.hpp"
 
 namespace plsqr {
@@ -513,123 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(InstDesc *const *descs, int
                                                     Rag np) {
   const int bi = np.n ? np.inst[blockIdx.y] : (int)blockIdx.y;
   if (np.n) nparts = np.count[blockIdx.y];
-  const InstDesc &D = *descs[bi];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) s += sld(D.part)[i];
-  s = block_sum(s);
-  if (threadIdx.x != 0) return;
-  double *sc = sld(D.sc);
-  const int k = (int)sc[SC_OUTER];
-  double *dg = sld(D.diag) + (long long)k * DG_COUNT;
-  auto fail = [&](int code) {
-    if (sc[SC_STATUS] == 0.0) sc[SC_STATUS] = (double)code;
-    sc[SC_STOP] = 1.0;
-  };
-  switch (what) {
-    case FIN_BETA_INIT: {
-      sc[SC_UPD] = 0.0;
-      if (sc[SC_HALT] != 0.0) break;   // the partials were not written (outer loop ended)
-      const double beta = sqrt(s);
-      if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
-      if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
-      sc[SC_BETA] = beta;
-      sc[SC_SU] = 1.0 / beta;
-      sc[SC_PHIBAR] = beta;
-      if (double *h = sld(D.hist)) h[sld(D.inner_count) + 1] = beta;   // beta_1
-      break;
-    }
-    case FIN_ALPHA_INIT: {
-      sc[SC_UPD] = 0.0;
-      if (sc[SC_STOP] != 0.0) break;
-      if (!isfinite(s)) { fail(PLSQR_E_NONFINITE); break; }
-      if (s < 0.0) { fail(PLSQR_E_NOT_SPD); break; }
-      const double alpha = sqrt(s);
-      if (alpha <= kTiny) { sc[SC_STOP] = 1.0; break; }
-      sc[SC_ALPHA] = alpha;
-      sc[SC_SV] = 1.0 / alpha;
-      sc[SC_RHOBAR] = alpha;
-      if (double *h = sld(D.hist)) h[0] = alpha;   // alpha_1
-      break;
-    }
-    case FIN_BETA: {
-      sc[SC_UPD] = 0.0;   // the forward product that precedes this applied any pending update
-      if (sc[SC_STOP] != 0.0) break;
-      const double beta = sqrt(s);
-      if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }
-      if (beta <= kTiny) { sc[SC_STOP] = 1.0; break; }
-      sc[SC_BETA] = beta;
-      sc[SC_SU] = 1.0 / beta;
-      // beta_{i+1} of step i (SC_DONE = i - 1 steps completed so far)
-      if (double *h = sld(D.hist)) {
-        const int i = (int)sc[SC_DONE] + 1;
-        if (i <= sld(D.inner_count)) h[sld(D.inner_count) + 1 + i] = beta;
-      }
-      break;
-    }
-    case FIN_ALPHA: {
-      if (sc[SC_STOP] != 0.0) break;
-      if (!isfinite(s)) { fail(PLSQR_E_NONFINITE); break; }
-      if (s < 0.0) { fail(PLSQR_E_NOT_SPD); break; }
-      const double alpha = sqrt(s);
-      if (alpha <= kTiny) { sc[SC_STOP] = 1.0; break; }
-      const double beta = sc[SC_BETA], lam = sc[SC_LAMBDA];
-      double rhobar = sc[SC_RHOBAR], phibar = sc[SC_PHIBAR];
-      if (double *h = sld(D.hist)) {   // alpha_{i+1} of step i
-        const int i = (int)sc[SC_DONE] + 1;
-        if (i <= sld(D.inner_count)) h[i] = alpha;
-      }
-      // damping rotation (row sqrt(tau) of (3.6)), then the Givens rotation with beta
-      const double rhohat = hypot(rhobar, lam);
-      const double c1 = rhobar / rhohat;
-      phibar = c1 * phibar;
-      const double rho = hypot(rhohat, beta);
-      const double c = rhohat / rho, sn = beta / rho;
-      const double theta = sn * alpha;
-      rhobar = -c * alpha;
-      const double phi = c * phibar;
-      phibar = sn * phibar;
-      sc[SC_CF] = phi / rho;
-      sc[SC_CW] = theta / rho;
-      sc[SC_RHOBAR] = rhobar;
-      sc[SC_PHIBAR] = phibar;
-      sc[SC_ALPHA] = alpha;
-      sc[SC_SV] = 1.0 / alpha;
-      sc[SC_DONE] += 1.0;
-      sc[SC_UPD] = 1.0;
-      break;
-    }
-    case FIN_RESID: {
-      sc[SC_UPD] = 0.0;
-      if (sc[SC_HALT] != 0.0) break;
-      dg[DG_RESID] = sqrt(s);
-      dg[DG_INNER] = sc[SC_DONE];
-      dg[DG_STATUS] = sc[SC_STATUS];
-      break;
-    }
-    case FIN_PENALTY: {
-      if (sc[SC_HALT] != 0.0) break;
-      dg[DG_PENALTY] = s;
-      // outer stop (Algorithm 3, step 5): R(f^k) no longer falls by more than outer_rtol
-      if ((sld(D.stop_flags) & PLSQR_FLAG_STOP_OUTER) && k >= sld(D.outer_min)) {
-        const double prev = dg[-DG_COUNT + DG_PENALTY];
-        if (s - prev >= -sld(D.outer_rtol) * prev) {
-          sc[SC_HALT] = 1.0;
-          sc[SC_STOP] = 1.0;
-        }
-      }
-      break;
-    }
-    case FIN_S4: {
-      // discrepancy principle S4 on the iterate of the step just completed
-      if (sc[SC_STOP] != 0.0) break;
-      const double r = sqrt(s);
-      sc[SC_S4R] = r;
-      if (!isfinite(r)) { fail(PLSQR_E_NONFINITE); break; }
-      if (r <= sld(D.s4_level)) sc[SC_STOP] = 1.0;
-      break;
-    }
-    default: break;
-  }
+  fin_block(*descs[bi], nparts, what);
 }
 
 // Initialisation of the update vectors: w = v / alpha_1, f = 0.

@@ -101,13 +101,19 @@ int zm_threads(const ZmShape &s, int H);
 // rg: a ragged map (then nx % 4 == 0 for every instance), or kNoRag for B same-shaped
 // instances; returns the blocks per instance of a uniform launch
 // upd: the first pass of a forward product from v also applies a pending f, w update (SC_UPD)
-// to its output voxels (nx % 4 == 0)
+// to its output voxels (nx % 4 == 0). fin >= 0 (nx % 4 == 0): each instance also gets a
+// finaliser block that runs finaliser fin (Fin) on its fin_n partials (per instance from fin_np
+// when fin_np.n > 0) of an earlier launch; a uniform launch adds the block itself, a ragged map
+// must count it (the last block of each instance's range).
 int launch_blur_x(hipStream_t st, InstDesc *const *d, int B, long long n, int nx, int src, int dst,
-                  int adj, int epi, int groups, const Rag &rg = kNoRag, int upd = 0);
+                  int adj, int epi, int groups, const Rag &rg = kNoRag, int upd = 0, int fin = -1,
+                  int fin_n = 0, const Rag &fin_np = kNoRag);
 // y (axis 1) or z (axis 2) pass; window: outputs per thread along the axis (4, 8, 16 or 32;
-// 0: default)
+// 0: default). upd: the pass applies a pending f, w update to its output voxels (the second pass
+// of a forward product whose first pass carries a finaliser block).
 int launch_blur_axis(hipStream_t st, InstDesc *const *d, int B, int nx, int ny, int nz, int axis,
-                     int src, int dst, int adj, int epi, int window, const Rag &rg = kNoRag);
+                     int src, int dst, int adj, int epi, int window, const Rag &rg = kNoRag,
+                     int upd = 0);
 // blocks per instance of the passes above
 int blur_x_blocks(long long n, int nx, int groups);
 int blur_axis_blocks(int nx, int ny, int nz, int axis, int window);

@@ -38,9 +38,12 @@ enum ScalarSlot : int {
   SC_LAMBDA,      // sqrt(tau)
   SC_HALT,        // 1 once the outer stop has fired: later outer steps change nothing
   SC_S4R,         // ||g - A f_i|| of the last completed step (S4 recurrence)
-  SC_UPD,         // 1 while the f, w update of the last completed step is pending: the x pass
-                  // of the next forward product applies it (see fused_update in the driver)
-  SC_COUNT = 16
+  SC_UPD,         // 1 while the f, w update of the last completed step is pending: the next
+                  // forward product applies it (see fused_update in the driver)
+  SC_FINA,        // 1 while the alpha finaliser of the last V-cycle is pending: the partials of
+                  // v.p wait in `part` for the next forward product's finaliser block (see
+                  // fin_blocks in the driver)
+  SC_COUNT = 17
 };
 
 // Per-outer diagnostic record layout (doubles).
@@ -147,9 +150,12 @@ enum Epi : int {
 constexpr int EPI_MASK_INNER = 0x100;
 constexpr int EPI_MASK_OUTER = 0x200;
 
-// Reduction finalisers (one block per instance).
+// Reduction finalisers (one block per instance). FIN_BETA_PEND: FIN_BETA, then marks the alpha
+// finaliser of the V-cycle that follows as pending (SC_FINA); FIN_ALPHA_PEND: FIN_ALPHA if it is
+// pending (and clears the mark), else nothing.
 enum Fin : int {
-  FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY, FIN_S4
+  FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY, FIN_S4,
+  FIN_BETA_PEND, FIN_ALPHA_PEND
 };
 
 }  // namespace plsqr
