@@ -99,9 +99,18 @@ def workload(name):
     return p, desc
 
 
-def dominant_bytes(p):
+def blur_update_fused(p, settings):
+    """Whether the library applies the previous inner step's f, w update inside the forward blur
+    product (the fused update: a four-voxel x pass, the fused V-cycle, no S4 recurrence)."""
+    return (p.op_kind == "blur" and p.dims[0] % 4 == 0 and not getattr(p, "stop_s4", False)
+            and not (settings or {}).get("tune_vcycle", 0))
+
+
+def dominant_bytes(p, update_fused=False):
     """Algorithmic HBM bytes of one dominant-kernel launch (the forward product u <- A v - alpha u:
-    read A (dense), read v, read and write u), its name, and the bytes its kernels move."""
+    read A (dense), read v, read and write u), its name, and the bytes its kernels move.
+    update_fused: the blur product also applies the previous step's f, w update (read and write
+    f and w: 16 bytes per voxel in inner - 1 of every inner products; its pass reads v again)."""
     nx, ny, nz = p.dims
     n = nx * ny * nz
     if p.op_kind == "dense":
@@ -113,8 +122,11 @@ def dominant_bytes(p):
     # passes, against 3 vectors (v in, u in and out) for the product itself
     k = max(1, sum(1 for e in (nx, ny, nz) if e > 1))
     names = ("k_blur_xg" if nx % 4 == 0 else "k_blur_x") + (" + k_blur_win" if k > 1 else "")
-    return 12 * n, f"{names} (forward blur product, {k} pass{'es' if k > 1 else ''})", \
-        4 * n * (2 * k + 1)
+    upd = (p.inner - 1) / p.inner if update_fused else 0.0
+    return int(12 * n + 16 * n * upd), \
+        f"{names} (forward blur product, {k} pass{'es' if k > 1 else ''}" + \
+        (", with the previous step's f, w update)" if update_fused else ")"), \
+        int(4 * n * (2 * k + 1) + 20 * n * upd)
 
 
 def cpu_baseline(p, target_s=20.0):
@@ -414,7 +426,7 @@ def main():
     fwd_ms, fwd_n = timed.forward_ms, timed.forward_launches
     adj_ms, adj_n = timed.adjoint_ms, timed.adjoint_launches
     avg_fwd_s = fwd_ms / max(fwd_n, 1) / 1e3
-    nbytes, kname, pass_bytes = dominant_bytes(p)
+    nbytes, kname, pass_bytes = dominant_bytes(p, blur_update_fused(p, settings))
     achieved = nbytes / avg_fwd_s / 1e9 if avg_fwd_s > 0 else None
     roofline = None
     if args.matrix_free:
@@ -819,7 +831,7 @@ def bench_c3_batch(args):
     value = B * n * p0.outer * p0.inner * args.steps / elapsed
     r0 = [res[0][1] for res in results]
     fwd_s = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1) / 1e3
-    nbytes, kname, pass_bytes = dominant_bytes(p0)
+    nbytes, kname, pass_bytes = dominant_bytes(p0, blur_update_fused(p0, settings))
     nbytes *= B
     pass_bytes *= B
     achieved = nbytes / fwd_s / 1e9

@@ -97,6 +97,14 @@ def test_dominant_bytes():
     p.dims = (16, 1, 1)
     b, _, k = bench.dominant_bytes(p)
     assert b == 4 * 16 * 3 and k == 4 * 16 * 3            # 1 pass
+    # with the previous step's f, w update (f and w read and written, in inner - 1 of every
+    # inner products; the pass that applies it reads v again)
+    p.dims, p.inner = (8, 8, 8), 5
+    b, _, k = bench.dominant_bytes(p, update_fused=True)
+    assert b == 12 * 512 + 16 * 512 * 4 // 5 and k == 28 * 512 + 20 * 512 * 4 // 5
+    assert bench.blur_update_fused(p, {}) and not bench.blur_update_fused(p, {"tune_vcycle": 1})
+    p.dims = (6, 8, 8)
+    assert not bench.blur_update_fused(p, {})               # the x pass takes 4-voxel groups only
     import numpy as np
     p.dims, p.op_kind, p.A = (4, 4, 2), "dense", np.zeros((10, 32), np.float32)
     b, _, k = bench.dominant_bytes(p)
