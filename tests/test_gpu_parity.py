@@ -572,18 +572,20 @@ def test_served_rejects_batch_calls(engine):
             srv.submit_batch(op, [problem_struct(p)], [g], [g.clone()])
 
 
-@pytest.mark.parametrize("kind", ["blur_cheb", "dense_jacobi"])
-def test_graph_replay_equals_eager(engine, kind):
-    """The captured inner-iteration graph (replayed outer x inner times per solve, with eager
-    setup work and synchronisations between solves) gives bitwise the eager result, with and
-    without product timing."""
+@pytest.mark.parametrize("kind,inner", [("blur_cheb", 6), ("blur_cheb", 11), ("dense_jacobi", 6),
+                                        ("dense_jacobi", 19)])
+def test_graph_replay_equals_eager(engine, kind, inner):
+    """The captured inner-iteration graphs (up to eight inner steps per graph, a second graph for
+    the rest of an outer step's count, replayed every outer step, with eager setup work and
+    synchronisations between solves) give bitwise the eager result, with and without product
+    timing."""
     from paper_1308_6634_amd import plsqr as P
     from paper_1308_6634_amd.engine import solve
     if kind == "blur_cheb":
-        p = gen.small_blur_case(95, (16, 16, 8), reg="stv", T=0.05, tau=20.0, outer=2, inner=6,
-                                levels=2, smoother="chebyshev", nu_pre=1, nu_post=1)
+        p = gen.small_blur_case(95, (16, 16, 8), reg="stv", T=0.05, tau=20.0, outer=2,
+                                inner=inner, levels=2, smoother="chebyshev", nu_pre=1, nu_post=1)
     else:
-        p = gen.small_dense_case(96, 8, outer=2, inner=6, levels=2)
+        p = gen.small_dense_case(96, 8, outer=2, inner=inner, levels=2)
     eager, _ = solve(p, engine=engine, flags=P.PLSQR_FLAG_NO_GRAPHS)
     for flags in (0, 0, P.PLSQR_FLAG_TIME_PRODUCTS, P.PLSQR_FLAG_TIME_PRODUCTS):
         got, res = solve(p, engine=engine, flags=flags)
