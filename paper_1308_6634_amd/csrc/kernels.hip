@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, i
 template <class At, class Dv>
 __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const LevelDesc &L, int l,
                                                    int n, At at, Dv dv, double *Ainv, int &bad) {
-  for (long long i = threadIdx.x; i < (long long)n * n; i += kBlock) at((int)(i / n), (int)(i % n)) = 0.0;
+  double *a0 = &at(0, 0);   // row-major n x n (n <= 512: 32-bit indices, no divisions in loops)
+  for (int i = threadIdx.x; i < n * n; i += kBlock) a0[i] = 0.0;
   __syncthreads();
   for (int J = threadIdx.x; J < n; J += kBlock) {
     const Coord c = coord_of(J, L.nx, L.ny);
@@ -167,10 +168,11 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
     const double piv = at(k, k);
     for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) at(i, k) /= piv;
     __syncthreads();
-    const int rem = n - k - 1;
-    for (long long q = threadIdx.x; q < (long long)rem * rem; q += kBlock) {
-      const int i = k + 1 + (int)(q / rem), jj = k + 1 + (int)(q % rem);
-      if (jj <= i) at(i, jj) -= at(i, k) * at(jj, k);
+    // the trailing lower triangle: wave w takes rows k + 1 + w, k + 1 + w + 4, .., lane c the
+    // columns k + 1 + c, k + 1 + c + 64, .. up to the diagonal
+    for (int i = k + 1 + (int)(threadIdx.x >> 6); i < n; i += kBlock / 64) {
+      const double lik = at(i, k);
+      for (int jj = k + 1 + (int)(threadIdx.x & 63); jj <= i; jj += 64) at(i, jj) -= lik * at(jj, k);
     }
     __syncthreads();
   }
@@ -178,24 +180,34 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
     sld(D.sc)[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
     sld(D.sc)[SC_STOP] = 1.0;
   }
-  // L^{-1}[k][j] (k >= j) is dv[j] on the diagonal and at(j, k) below it
+  // L^{-1}[k][j] (k >= j) is dv[j] on the diagonal and at(j, k) below it. The sums below run
+  // in four interleaved partial sums (k = k0 + 4 m + e), so that four of their loads are in
+  // flight at once instead of one dependent load per term.
   auto li = [&](int k, int j) -> double { return k == j ? dv[j] : at(j, k); };
   for (int j = threadIdx.x; j < n; j += kBlock) {
     for (int i = j; i < n; ++i) {
-      double sacc = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) sacc -= at(i, k) * li(k, j);
-      const double v = sacc / at(i, i);
+      double s4[4] = {(i == j) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+      int k = j;
+      for (; k + 3 < i; k += 4)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s4[e] -= at(i, k + e) * li(k + e, j);
+      for (; k < i; ++k) s4[0] -= at(i, k) * li(k, j);
+      const double v = ((s4[0] + s4[1]) + (s4[2] + s4[3])) / at(i, i);
       if (i == j) dv[j] = v; else at(j, i) = v;
     }
   }
   __syncthreads();
   // A^{-1}[i][j] = sum_{k >= max(i,j)} L^{-1}[k][i] L^{-1}[k][j]
-  for (long long q = threadIdx.x; q < (long long)n * n; q += kBlock) {
-    const int i = (int)(q / n), j = (int)(q % n);
-    const int k0 = i > j ? i : j;
-    double sacc = 0.0;
-    for (int k = k0; k < n; ++k) sacc += li(k, i) * li(k, j);
-    Ainv[q] = sacc;
+  for (int i = (int)(threadIdx.x >> 6); i < n; i += kBlock / 64) {
+    for (int j = (int)(threadIdx.x & 63); j < n; j += 64) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int k = i > j ? i : j;
+      for (; k + 3 < n; k += 4)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s4[e] += li(k + e, i) * li(k + e, j);
+      for (; k < n; ++k) s4[0] += li(k, i) * li(k, j);
+      Ainv[i * n + j] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
   }
 }
 
