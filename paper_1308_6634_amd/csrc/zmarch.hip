@@ -374,6 +374,11 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   const float *__restrict__ xpre = c.L.t;    // up: the pre-smoothed iterate
   const float *__restrict__ ecrs = Cl.x;     // up: coarse correction
   const int czf = (c.nz > 1) ? 2 : 1;        // fine planes per coarse plane
+  const int czs = czf - 1;                   // its shift: coarse plane = fine plane >> czs
+  // the coarse cell of this thread's column (x, y halved) in coarse plane 0, and the coarse
+  // plane size: a coarse index is cbase + csz * plane (32-bit: levels hold < 2^31 cells)
+  const long long cbase = (long long)(c.gx >> 1) + (long long)Cl.nx * (c.gy >> 1);
+  const int csz = Cl.nx * Cl.ny;
   const int zend = min(c.nz, z0 + zc);      // output planes [z0, zend)
   const int t0 = max(0, z0 - H);
   const int t1 = zend - 1 + H + (DOWN ? 1 : 0);
@@ -409,9 +414,7 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
   auto up_loads = [&](int p, UpData &u) {
     const int pc = min(max(p, 0), c.nz - 1);
     const long long j = in ? col + c.sz * pc : 0;
-    const long long pj = in ? (long long)(c.gx >> 1) +
-                                  (long long)Cl.nx * ((c.gy >> 1) + (long long)Cl.ny * (pc / czf))
-                            : 0;
+    const long long pj = in ? cbase + csz * (pc >> czs) : 0;
     u.x = ldv<V>(xpre + j);
     u.e0 = ecrs[pj];
     u.e1 = (V == 4) ? ecrs[pj + 1] : 0.f;
@@ -530,8 +533,7 @@ __global__ void __launch_bounds__(zm_max_threads(V)) k_zm(InstDesc *const *descs
           racc0 += rb[rp * exq + qp];
         }
         if (czf == 1 || (pr & 1)) {
-          const long long J = (long long)(c.gx >> 1) +
-                              (long long)Cl.nx * ((c.gy >> 1) + (long long)Cl.ny * (pr / czf));
+          const long long J = cbase + csz * (pr >> czs);   // pr >= z0 >= 0
           if constexpr (V == 4) *reinterpret_cast<float2 *>(Cl.b + J) = make_float2(racc0, racc1);
           else Cl.b[J] = racc0;
           racc0 = 0.f;
