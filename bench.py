@@ -440,6 +440,7 @@ def main():
                     "(forward product, entries regenerated)", "achieved": alu, "peak": alu_peak,
                     "unit": "TFLOP/s", "frac": alu / alu_peak,
                     "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                    "frac_of_fp32_vector_peak": alu / FP32_VECTOR_PEAK_TFLOPS,
                     "traffic": None, "entries_per_launch": entries,
                     "entries_per_s": entries / avg_fwd_s, "entry_peak_per_s": RING_ENTRY_PEAK,
                     "entry_frac": entries / avg_fwd_s / RING_ENTRY_PEAK,
