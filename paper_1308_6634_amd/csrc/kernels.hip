@@ -122,16 +122,18 @@ __global__ void __launch_bounds__(kBlock) k_level_dinv(InstDesc *const *descs, i
   L.dinv[j] = 1.0f / d;
 }
 
-// Assemble the coarsest operator densely in FP64, factor it (lower Cholesky, right-looking,
-// in place) and form its explicit inverse A^{-1} = L^{-T} L^{-1}, so that each V-cycle's
-// coarsest solve is one parallel matrix-vector product. at(i, j) is the working matrix: its
-// lower triangle holds L, and L^{-1} (formed column by column, one thread per column) is kept
-// transposed in the strict upper triangle with its diagonal in dv. A^{-1} goes to Ainv.
-template <class At, class Dv>
-__device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const LevelDesc &L, int l,
-                                                   int n, At at, Dv dv, double *Ainv, int &bad) {
-  double *a0 = &at(0, 0);   // row-major n x n (n <= 512: 32-bit indices, no divisions in loops)
-  for (int i = threadIdx.x; i < n * n; i += kBlock) a0[i] = 0.0;
+// Coarsest grids of up to kCoarseLds cells are inverted in LDS (coarse_gj_inverse, kCoarseLdsRows
+// rows per thread), larger ones in the instance's FP64 workspace (coarse_factor_body).
+constexpr int kCoarseLds = 64;
+constexpr int kCoarseLdsRows = kCoarseLds / (kBlock / 64);
+
+// Assemble the coarsest operator densely in FP64 into at(i, j) (all n x n entries written).
+template <class At>
+__device__ __forceinline__ void coarse_assemble(const InstDesc &D, const LevelDesc &L, int l, int n,
+                                                At at) {
+  // (n <= 512: 32-bit indices; wave w takes rows w, w + 4, .., lane c columns c, c + 64, ..)
+  for (int i = (int)(threadIdx.x >> 6); i < n; i += kBlock / 64)
+    for (int j = (int)(threadIdx.x & 63); j < n; j += 64) at(i, j) = 0.0;
   __syncthreads();
   for (int J = threadIdx.x; J < n; J += kBlock) {
     const Coord c = coord_of(J, L.nx, L.ny);
@@ -156,6 +158,67 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
     }
     at(J, J) = diag;
   }
+}
+
+// The inverse of the assembled coarsest operator (n <= 64, in LDS) by in-place Gauss-Jordan
+// elimination without pivoting: step k scales row k by 1 / a_kk and eliminates column k from
+// every other row. For a symmetric positive definite matrix the pivots are those of its
+// Cholesky factorisation (the Schur complements), so a non-positive one flags the matrix as not
+// SPD (and is replaced by 1, as the factorisation path does). Each step reads row and column k
+// from snapshots (rowk, colk: n doubles of LDS each), so every entry is updated by the one
+// thread that owns it, from values no other thread writes during the step: two barriers a step.
+template <class At>
+__device__ __forceinline__ void coarse_gj_inverse(int n, At at, double *rowk, double *colk,
+                                                  double *Ainv, int &bad) {
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);   // lane: column j
+  constexpr int kWaves = kBlock / 64;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      colk[i] = at(i, k);
+      rowk[i] = at(k, i);
+    }
+    __syncthreads();
+    double piv = colk[k];
+    if (!(piv > 0.0)) {
+      if (threadIdx.x == 0) bad = 1;
+      piv = 1.0;
+    }
+    const double rp = 1.0 / piv;
+    if (lane < n) {
+      const int j = lane;
+      const double rj = ((j == k) ? 1.0 : rowk[j]) * rp;   // row k after its scaling
+      double aij[kCoarseLdsRows];
+#pragma unroll
+      for (int r = 0; r < kCoarseLdsRows; ++r) {
+        const int i = min(w + kWaves * r, n - 1);   // clamped: read, never written
+        aij[r] = at(i, j);
+      }
+#pragma unroll
+      for (int r = 0; r < kCoarseLdsRows; ++r) {
+        const int i = w + kWaves * r;
+        if (i >= n) continue;
+        if (i == k) at(i, j) = rj;
+        else at(i, j) = ((j == k) ? 0.0 : aij[r]) - colk[i] * rj;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = w; i < n; i += kWaves)
+    if (lane < n) Ainv[i * n + lane] = at(i, lane);
+}
+
+// The global-memory path (64 < n <= 512): factor the assembled operator (lower Cholesky,
+// right-looking, in place) and form its explicit inverse A^{-1} = L^{-T} L^{-1}, so that each
+// V-cycle's coarsest solve is one parallel matrix-vector product. at(i, j) is the working
+// matrix: its lower triangle holds L, and L^{-1} (formed column by column, one thread per
+// column) is kept transposed in the strict upper triangle with its diagonal in dv. A^{-1} goes
+// to Ainv.
+template <class At, class Dv>
+__device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const LevelDesc &L, int l,
+                                                   int n, At at, Dv dv, double *Ainv, int &bad) {
+  coarse_assemble(D, L, l, n, at);
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
@@ -168,11 +231,27 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
     const double piv = at(k, k);
     for (int i = k + 1 + threadIdx.x; i < n; i += kBlock) at(i, k) /= piv;
     __syncthreads();
-    // the trailing lower triangle: wave w takes rows k + 1 + w, k + 1 + w + 4, .., lane c the
-    // columns k + 1 + c, k + 1 + c + 64, .. up to the diagonal
-    for (int i = k + 1 + (int)(threadIdx.x >> 6); i < n; i += kBlock / 64) {
-      const double lik = at(i, k);
-      for (int jj = k + 1 + (int)(threadIdx.x & 63); jj <= i; jj += 64) at(i, jj) -= lik * at(jj, k);
+    // the trailing lower triangle: lane c takes the columns jj = k + 1 + c, k + 1 + c + 64, ..,
+    // wave w the rows i = k + 1 + w, k + 1 + w + 4, .. (i >= jj), eight rows at a time with all
+    // their reads issued before their updates (a row at a time waits on three dependent LDS
+    // accesses)
+    constexpr int kRows = 8, kWaves = kBlock / 64;
+    for (int jj = k + 1 + (int)(threadIdx.x & 63); jj < n; jj += 64) {
+      const double ajk = at(jj, k);
+      for (int i0 = k + 1 + (int)(threadIdx.x >> 6); i0 < n; i0 += kRows * kWaves) {
+        double lik[kRows], aij[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const int i = min(i0 + kWaves * r, n - 1);   // clamped: read, never written
+          lik[r] = at(i, k);
+          aij[r] = at(i, jj);
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const int i = i0 + kWaves * r;
+          if (i < n && jj <= i) at(i, jj) = aij[r] - lik[r] * ajk;
+        }
+      }
     }
     __syncthreads();
   }
@@ -211,9 +290,9 @@ __device__ __forceinline__ void coarse_factor_body(const InstDesc &D, const Leve
   }
 }
 
-// One block per instance. Coarsest grids of up to kCoarseLds cells are factored in LDS, larger
-// ones in the instance's FP64 workspace (cfac: working matrix, L^{-1} diagonal, A^{-1}).
-constexpr int kCoarseLds = 64;
+// One block per instance: A^{-1} of the coarsest operator, in LDS (Gauss-Jordan) up to
+// kCoarseLds cells, else in the instance's FP64 workspace (cfac: working matrix, L^{-1}
+// diagonal, A^{-1}; Cholesky).
 __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs) {
   const InstDesc &D = inst(descs);
   if (stopped_outer(D)) return;
@@ -222,12 +301,19 @@ __global__ void __launch_bounds__(kBlock) k_coarse_factor(InstDesc *const *descs
   const int n = (int)L.n;
   double *__restrict__ W = sld(D.cfac);
   double *Ainv = W + (long long)n * n * 2;
-  __shared__ double S[kCoarseLds * kCoarseLds];
-  __shared__ double sdv[kCoarseLds];
+  // rows n + 1 doubles apart: the lanes of a wave that read one column of consecutive rows hit
+  // different banks (n doubles apart, a power of two, they would all hit the same bank)
+  __shared__ double S[kCoarseLds * (kCoarseLds + 1)];
+  __shared__ double srow[kCoarseLds], scol[kCoarseLds];
   __shared__ int bad;
   if (n <= kCoarseLds) {
-    coarse_factor_body(D, L, l, n, [&](int i, int j) -> double & { return S[i * n + j]; },
-                       sdv, Ainv, bad);
+    auto at = [&](int i, int j) -> double & { return S[i * (n + 1) + j]; };
+    coarse_assemble(D, L, l, n, at);
+    coarse_gj_inverse(n, at, srow, scol, Ainv, bad);
+    if (threadIdx.x == 0 && bad) {
+      sld(D.sc)[SC_STATUS] = (double)PLSQR_E_NOT_SPD;
+      sld(D.sc)[SC_STOP] = 1.0;
+    }
   } else {
     double *gdv = W + (long long)n * n;
     coarse_factor_body(D, L, l, n,
