@@ -99,11 +99,37 @@ def workload(name):
     return p, desc
 
 
-def blur_update_fused(p, settings):
+def update_in_tail(p, settings, batch=1):
+    """Whether the library runs the previous inner step's f, w update in extra workgroups of the
+    V-cycle tail launch (tune_update_site; by default where that applies and the batch holds at
+    most 2^22 voxels): a blur operator with nx % 4 == 0 on a grid of more than one row, no S4
+    recurrence, and a fused V-cycle of two or more levels whose finest level runs as fused
+    level kernels above the tail (Jacobi with at most 4 sweeps, or Chebyshev of degree <= 4 with
+    one polynomial per side)."""
+    s = settings or {}
+    site = s.get("tune_update_site", 0)
+    nx, ny, nz = p.dims
+    n = nx * ny * nz
+    if site == 1 or p.op_kind != "blur" or nx % 4 or s.get("tune_vcycle", 0):
+        return False
+    if n <= (s.get("tune_tail_cells", 0) or 4096):   # the finest level is in the tail
+        return False
+    if getattr(p, "stop_s4", False) or (ny < 2 and nz < 2) or p.levels == 1:
+        return False
+    if p.smoother == "jacobi" and p.nu_pre > 4:
+        return False
+    if p.smoother != "jacobi" and (p.nu_pre != 1 or p.cheb_degree > 4):
+        return False
+    return site == 2 or batch * n <= 1 << 22
+
+
+def blur_update_fused(p, settings, batch=1):
     """Whether the library applies the previous inner step's f, w update inside the forward blur
-    product (the fused update: a four-voxel x pass, the fused V-cycle, no S4 recurrence)."""
+    product (the fused update: a four-voxel x pass, the fused V-cycle, no S4 recurrence), rather
+    than in the V-cycle tail launch (update_in_tail) or a launch of its own."""
     return (p.op_kind == "blur" and p.dims[0] % 4 == 0 and not getattr(p, "stop_s4", False)
-            and not (settings or {}).get("tune_vcycle", 0))
+            and not (settings or {}).get("tune_vcycle", 0)
+            and not update_in_tail(p, settings, batch))
 
 
 def dominant_bytes(p, update_fused=False):
@@ -832,7 +858,7 @@ def bench_c3_batch(args):
     value = B * n * p0.outer * p0.inner * args.steps / elapsed
     r0 = [res[0][1] for res in results]
     fwd_s = sum(r.forward_ms for r in r0) / max(sum(r.forward_launches for r in r0), 1) / 1e3
-    nbytes, kname, pass_bytes = dominant_bytes(p0, blur_update_fused(p0, settings))
+    nbytes, kname, pass_bytes = dominant_bytes(p0, blur_update_fused(p0, settings, B))
     nbytes *= B
     pass_bytes *= B
     achieved = nbytes / fwd_s / 1e9

@@ -56,6 +56,13 @@ enum { PLSQR_REG_TIKHONOV = 0, PLSQR_REG_STV = 1, PLSQR_REG_PM_LOG = 2, PLSQR_RE
 enum { PLSQR_SMOOTH_JACOBI = 0, PLSQR_SMOOTH_CHEBYSHEV = 1 };
 /* V-cycle launch schedule (plsqr_problem.tune_vcycle) */
 enum { PLSQR_VCYCLE_FUSED = 0, PLSQR_VCYCLE_PER_SWEEP = 1 };
+/* Where the f, w update of an MLSQR step runs on a blur operator (plsqr_problem.
+ * tune_update_site; Algorithm 2's update, which nothing reads before the outer step ends):
+ * AUTO picks the tail where it applies and the batch holds at most 2^22 voxels, else the
+ * product; PRODUCT: in the next forward product's first or second pass; TAIL: in extra
+ * workgroups of the next V-cycle's one-workgroup tail launch, which leaves most of the chip idle
+ * (fused V-cycle, blur operator with nx % 4 == 0; elsewhere PRODUCT). The values are the same. */
+enum { PLSQR_UPDATE_AUTO = 0, PLSQR_UPDATE_PRODUCT = 1, PLSQR_UPDATE_TAIL = 2 };
 /* FP32: float32 vectors and products, float64 Krylov scalars and coarsest solve.
  * BF16_REFINED / BF16 (batches on a dense operator only): the dense products of the
  * batch run as BF16 MFMA GEMMs with FP32 accumulation. Every FP32 operand v is split
@@ -200,7 +207,8 @@ typedef struct {
    *  tune_zm_v        voxels per thread of the fused level kernels, 1 or 4 (0: 4 on levels of
    *                   at least 2^20 cells, 1 below)
    *  tune_tail_cells  largest level (in cells) that joins the one-workgroup V-cycle tail
-   *                   (0: 4096; at most 2^20) */
+   *                   (0: 4096; at most 2^20)
+   *  tune_update_site where the f, w update runs: PLSQR_UPDATE_AUTO (0), _PRODUCT or _TAIL */
   int32_t tune_gemv_rows;
   int32_t tune_col_chunks;
   /* adaptive stopping (PLSQR_FLAG_STOP_S4, PLSQR_FLAG_STOP_OUTER) */
@@ -214,7 +222,7 @@ typedef struct {
   int32_t tune_zm_zc;
   int32_t tune_zm_v;
   int32_t tune_tail_cells;
-  int32_t reserved1;
+  int32_t tune_update_site;
 } plsqr_problem;
 
 /* Completion record of one request (filled by plsqr_poll). */

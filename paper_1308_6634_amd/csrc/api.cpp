@@ -100,6 +100,7 @@ void fill_desc(plsqr_engine *eng, Request &r, const Operator &op) {
   D.zm_zc = pb.tune_zm_zc;
   D.zm_v = pb.tune_zm_v;
   D.tail_cells = pb.tune_tail_cells;
+  D.update_site = pb.tune_update_site;
   D.out_f = r.f_out;
   D.sc = reinterpret_cast<double *>(ws + Ly.sc);
   D.part = reinterpret_cast<double *>(ws + Ly.part);
@@ -457,7 +458,7 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
         c.tune_blur_window != a.tune_blur_window || c.tune_blur_xgroups != a.tune_blur_xgroups ||
         c.tune_vcycle != a.tune_vcycle || c.tune_zm_ty != a.tune_zm_ty ||
         c.tune_zm_zc != a.tune_zm_zc || c.tune_zm_v != a.tune_zm_v ||
-        c.tune_tail_cells != a.tune_tail_cells)
+        c.tune_tail_cells != a.tune_tail_cells || c.tune_update_site != a.tune_update_site)
       return set_error(PLSQR_E_INVALID,
                        "a batch must share counts, levels, smoother schedule, precision and flags");
   }
@@ -520,12 +521,12 @@ int submit_group(plsqr_engine *eng, int32_t op_id, int count, const plsqr_proble
 // the ring adjoint's LDS). Blur requests of one grid share launches whatever their taps.
 struct ClassKey {
   int nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win, xg, vc, zty,
-      zzc, zv, tail;
+      zzc, zv, tail, usite;
   bool operator<(const ClassKey &o) const {
     return std::tie(nx, ny, nz, levels, smoother, nu, deg, kind, type, stop, op, gemv, cols, win,
-                    xg, vc, zty, zzc, zv, tail) <
+                    xg, vc, zty, zzc, zv, tail, usite) <
            std::tie(o.nx, o.ny, o.nz, o.levels, o.smoother, o.nu, o.deg, o.kind, o.type, o.stop,
-                    o.op, o.gemv, o.cols, o.win, o.xg, o.vc, o.zty, o.zzc, o.zv, o.tail);
+                    o.op, o.gemv, o.cols, o.win, o.xg, o.vc, o.zty, o.zzc, o.zv, o.tail, o.usite);
   }
 };
 
@@ -647,7 +648,7 @@ void serve_tick(plsqr_engine *eng) {
                     (int)(pb.flags & (PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER)), op_key,
                     pb.tune_gemv_rows, pb.tune_col_chunks, pb.tune_blur_window,
                     pb.tune_blur_xgroups, pb.tune_vcycle, pb.tune_zm_ty, pb.tune_zm_zc,
-                    pb.tune_zm_v, pb.tune_tail_cells};
+                    pb.tune_zm_v, pb.tune_tail_cells, pb.tune_update_site};
   };
   for (uint64_t t : eng->resident) {
     Request &r = *eng->reqs[t];

@@ -69,6 +69,9 @@ int validate(const plsqr_problem &pb, const Operator *op, int *levels_out, std::
     return bad("tune_zm_v must be 0, 1 or 4");
   if (pb.tune_tail_cells < 0 || pb.tune_tail_cells > (1 << 20))
     return bad("tune_tail_cells must be in [0, 2^20]");
+  if (pb.tune_update_site != PLSQR_UPDATE_AUTO && pb.tune_update_site != PLSQR_UPDATE_PRODUCT &&
+      pb.tune_update_site != PLSQR_UPDATE_TAIL)
+    return bad("tune_update_site must be PLSQR_UPDATE_AUTO, _PRODUCT or _TAIL");
   int levels = pb.mg_levels;
   if (levels == 0) levels = plsqr_auto_levels(pb.nx, pb.ny, pb.nz);
   if (levels < 1 || levels > kMaxLevels) return bad("mg_levels out of range");
@@ -451,6 +454,23 @@ static bool fin_blocks(const BatchView &bv) {
   return vcycle_plan(H, *bv.lay).fz[0];
 }
 
+// Whether the pending f, w update of an inner step runs in extra workgroups of the next
+// V-cycle's tail launch rather than in the forward product (under fin_blocks the tail runs
+// after the alpha finaliser that makes the update pending, and before level 0's up kernel
+// overwrites v). The tail is one workgroup per instance: at most kTailUpdateVoxels voxels of
+// update traffic fit beside it (PLSQR_UPDATE_AUTO).
+constexpr long long kTailUpdateVoxels = 1LL << 22;
+constexpr int kTailUpdateCUs = 256;   // compute units: one tail-launch workgroup fits a CU
+static bool tail_update(const BatchView &bv) {
+  const InstDesc &H = *bv.h;
+  if (H.update_site == PLSQR_UPDATE_PRODUCT || !fin_blocks(bv) || H.n % 4 != 0) return false;
+  return H.update_site == PLSQR_UPDATE_TAIL || (long long)bv.B * H.n <= kTailUpdateVoxels;
+}
+// update workgroups per instance: the compute units the tails leave free
+static int tail_update_parts(const BatchView &bv) {
+  return std::max(1, (kTailUpdateCUs - bv.B) / bv.B);
+}
+
 // Partials of the alpha reduction that a fused V-cycle leaves: one per block of level 0's up
 // kernel.
 static int vcycle_parts(const InstDesc &H, const Layout &Ly) {
@@ -458,7 +478,8 @@ static int vcycle_parts(const InstDesc &H, const Layout &Ly) {
   return (int)zm_tiles(Ly.lnx[0], Ly.lny[0], Ly.lnz[0], P.shp[0]);
 }
 
-static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
+// upd_parts > 0: the tail launch also applies the pending f, w update (tail_update).
+static int enqueue_vcycle(hipStream_t st, const BatchView &bv, int upd_parts = 0) {
   const InstDesc &H = *bv.h;
   const Layout &Ly = *bv.lay;
   const int L = H.levels;
@@ -477,7 +498,7 @@ static int enqueue_vcycle(hipStream_t st, const BatchView &bv) {
   const ZmShape *shp = P.shp;
   const bool *fz = P.fz;
   auto tail = [&]() {
-    if (fused_mode) launch_vcycle_tail_lds(st, d, B, t);
+    if (fused_mode) launch_vcycle_tail_lds(st, d, B, t, upd_parts);
     else launch_vcycle_tail(st, d, B, t);
   };
   auto zm = [&](int kind, int l, int want) {
@@ -641,12 +662,14 @@ static bool update_fused_whole(const BatchView &bv) { return fused_update(bv); }
 
 // The products of an inner step with the beta finaliser between them; under fin_blocks the
 // alpha finaliser of the last V-cycle (if one is pending) rides in the forward product and beta
-// in the adjoint product.
+// in the adjoint product, and the forward product applies the pending update unless the
+// V-cycle's tail does (tail_update).
 static void enqueue_inner_products(hipStream_t st, const BatchView &bv) {
   if (fin_blocks(bv)) {
-    const int nb = enqueue_forward(st, bv, V_V, EPI_FWD, true, FIN_ALPHA_PEND,
+    const bool tu = tail_update(bv);
+    const int nb = enqueue_forward(st, bv, V_V, EPI_FWD, !tu, tu ? FIN_ALPHA_PEND_T : FIN_ALPHA_PEND,
                                    vcycle_parts(*bv.h, *bv.lay));
-    enqueue_adjoint(st, bv, EPI_ADJ, FIN_BETA_PEND, nb);
+    enqueue_adjoint(st, bv, EPI_ADJ, tu ? FIN_BETA_PEND_T : FIN_BETA_PEND, nb);
     return;
   }
   const int np = enqueue_forward(st, bv, V_V, EPI_FWD, true);
@@ -657,7 +680,7 @@ static void enqueue_inner_products(hipStream_t st, const BatchView &bv) {
 // The V-cycle of an inner step and the alpha finaliser (under fin_blocks its partials wait for
 // the next forward product).
 static void enqueue_inner_vcycle(hipStream_t st, const BatchView &bv) {
-  const int np = enqueue_vcycle(st, bv);
+  const int np = enqueue_vcycle(st, bv, tail_update(bv) ? tail_update_parts(bv) : 0);
   if (!fin_blocks(bv)) launch_finalize(st, bv.d_descs, bv.B, np, FIN_ALPHA);
 }
 
@@ -778,7 +801,8 @@ void enqueue_outer_end(hipStream_t st, const BatchView &bv) {
   // the last inner step's alpha finaliser, left pending (fin_blocks), and its update, left
   // pending (fused_update)
   if (fin_blocks(bv))
-    launch_finalize(st, bv.d_descs, bv.B, vcycle_parts(H, *bv.lay), FIN_ALPHA_PEND);
+    launch_finalize(st, bv.d_descs, bv.B, vcycle_parts(H, *bv.lay),
+                    tail_update(bv) ? FIN_ALPHA_PEND_T : FIN_ALPHA_PEND);
   if (fused_update(bv)) launch_update_fw(st, bv.d_descs, bv.B, H.n, kNoRag, 1);
   int np = enqueue_forward(st, bv, V_F, EPI_RESID);
   launch_finalize(st, bv.d_descs, bv.B, np, FIN_RESID);

@@ -45,12 +45,15 @@ __device__ __forceinline__ void fin_apply(const InstDesc &D, double s, int what)
     if (sc[SC_STATUS] == 0.0) sc[SC_STATUS] = (double)code;
     sc[SC_STOP] = 1.0;
   };
-  if (what == FIN_ALPHA_PEND) {
+  bool keep_upd = false;
+  if (what == FIN_ALPHA_PEND || what == FIN_ALPHA_PEND_T) {
+    if (what == FIN_ALPHA_PEND_T) sc[SC_UPD] = 0.0;   // the last V-cycle's tail applied it
     if (sc[SC_FINA] == 0.0) return;
     sc[SC_FINA] = 0.0;
     what = FIN_ALPHA;
-  } else if (what == FIN_BETA_PEND) {
+  } else if (what == FIN_BETA_PEND || what == FIN_BETA_PEND_T) {
     sc[SC_FINA] = 1.0;   // the V-cycle after this product leaves its partials for FIN_ALPHA_PEND
+    keep_upd = (what == FIN_BETA_PEND_T);   // the update waits for that V-cycle's tail
     what = FIN_BETA;
   }
   switch (what) {
@@ -81,7 +84,9 @@ __device__ __forceinline__ void fin_apply(const InstDesc &D, double s, int what)
       break;
     }
     case FIN_BETA: {
-      sc[SC_UPD] = 0.0;   // the forward product that precedes this applied any pending update
+      // the forward product that precedes this applied any pending update (unless it waits for
+      // the V-cycle's tail)
+      if (!keep_upd) sc[SC_UPD] = 0.0;
       if (sc[SC_STOP] != 0.0) break;
       const double beta = sqrt(s);
       if (!isfinite(beta)) { fail(PLSQR_E_NONFINITE); break; }

@@ -70,8 +70,10 @@ void launch_restrict4(hipStream_t st, InstDesc *const *d, int B, int l, long lon
 void launch_vcycle_tail(hipStream_t st, InstDesc *const *d, int B, int t);
 // the same with every tail level resident in LDS (tail_lds.hip); the levels t .. coarsest must
 // need at most kTailLdsFloats floats: tail_lds_floats of their cell counts. t < 0: each
-// instance's own first tail level (its descriptor's tail_lds_t).
-void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t);
+// instance's own first tail level (its descriptor's tail_lds_t). upd_parts > 0: the launch also
+// applies each instance's pending f, w update (SC_UPD; n % 4 == 0) in upd_parts more workgroups
+// per instance.
+void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t, int upd_parts = 0);
 long long tail_lds_floats(const long long *cells, int nlev);
 // Fused level kernels (zmarch.hip): one launch per level and V-cycle half. ZM_*_DOWN runs the
 // whole pre-smoothing of level l from x = 0 on b_l, writes the pre-smoothed iterate to the

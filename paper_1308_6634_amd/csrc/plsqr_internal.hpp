@@ -39,7 +39,8 @@ enum ScalarSlot : int {
   SC_HALT,        // 1 once the outer stop has fired: later outer steps change nothing
   SC_S4R,         // ||g - A f_i|| of the last completed step (S4 recurrence)
   SC_UPD,         // 1 while the f, w update of the last completed step is pending: the next
-                  // forward product applies it (see fused_update in the driver)
+                  // forward product applies it, or the tail of the next V-cycle (see
+                  // fused_update and tail_update in the driver)
   SC_FINA,        // 1 while the alpha finaliser of the last V-cycle is pending: the partials of
                   // v.p wait in `part` for the next forward product's finaliser block (see
                   // fin_blocks in the driver)
@@ -93,6 +94,7 @@ struct InstDesc {
   int zm_ty, zm_zc, zm_v;            // fused level kernels: rows / planes per block, voxels per
                                      // thread (0: chosen per level)
   int tail_cells;                    // largest level of the one-workgroup tail (0: default)
+  int update_site;                   // where a pending f, w update runs (PLSQR_UPDATE_*)
   int stop_flags;                    // PLSQR_FLAG_STOP_S4 | PLSQR_FLAG_STOP_OUTER bits
   int outer_min;                     // first outer step checked by the outer stop
   double s4_level;                   // eta * delta
@@ -152,10 +154,12 @@ constexpr int EPI_MASK_OUTER = 0x200;
 
 // Reduction finalisers (one block per instance). FIN_BETA_PEND: FIN_BETA, then marks the alpha
 // finaliser of the V-cycle that follows as pending (SC_FINA); FIN_ALPHA_PEND: FIN_ALPHA if it is
-// pending (and clears the mark), else nothing.
+// pending (and clears the mark), else nothing. The _T forms are for steps whose pending update
+// runs in the V-cycle tail (after the beta finaliser): FIN_BETA_PEND_T leaves the update pending
+// and FIN_ALPHA_PEND_T first retires it (that tail has run by then).
 enum Fin : int {
   FIN_BETA_INIT = 0, FIN_BETA, FIN_ALPHA_INIT, FIN_ALPHA, FIN_RESID, FIN_PENALTY, FIN_S4,
-  FIN_BETA_PEND, FIN_ALPHA_PEND
+  FIN_BETA_PEND, FIN_ALPHA_PEND, FIN_BETA_PEND_T, FIN_ALPHA_PEND_T
 };
 
 }  // namespace plsqr

@@ -359,8 +359,52 @@ __device__ __forceinline__ bool tail_up_any(const InstDesc &D, const TailSm &m,
 
 }  // namespace
 
+// Part `part` of `parts` of an instance's pending f, w update (Algorithm 2's update of the step
+// before: f += (phi/rho) w, w = v/alpha - (theta/rho) w; n % 4 == 0), run by the extra
+// workgroups of a tail launch. It ignores the stop flag: a pending update comes from a step that
+// completed, and whatever stopped later leaves it to be applied.
+__device__ __forceinline__ void tail_update_part(const InstDesc &D, int part, int parts) {
+  const double *sc = sld(D.sc);
+  if (sc[SC_UPD] == 0.0) return;
+  const float cf = (float)sc[SC_CF], cw = (float)sc[SC_CW], sv = (float)sc[SC_SV];
+  const long long n4 = sld(D.n) / 4;
+  const long long per = (n4 + parts - 1) / parts;
+  const long long b = per * part, e = min(n4, b + per);
+  float4 *__restrict__ f = reinterpret_cast<float4 *>(sld(D.f));
+  float4 *__restrict__ w = reinterpret_cast<float4 *>(sld(D.w));
+  const float4 *__restrict__ v = reinterpret_cast<const float4 *>(sld(D.v));
+  // two groups per trip, every load of the trip issued before the first store
+  for (long long i0 = b + threadIdx.x; i0 < e; i0 += 2 * kTailBlock) {
+    const long long i1 = i0 + kTailBlock;
+    const bool h1 = i1 < e;
+    const long long j1 = h1 ? i1 : i0;
+    float4 w0 = w[i0], f0 = f[i0];
+    const float4 v0 = v[i0];
+    float4 w1 = w[j1], f1 = f[j1];
+    const float4 v1 = v[j1];
+    f0.x += cf * w0.x; f0.y += cf * w0.y; f0.z += cf * w0.z; f0.w += cf * w0.w;
+    w0.x = sv * v0.x - cw * w0.x; w0.y = sv * v0.y - cw * w0.y;
+    w0.z = sv * v0.z - cw * w0.z; w0.w = sv * v0.w - cw * w0.w;
+    f1.x += cf * w1.x; f1.y += cf * w1.y; f1.z += cf * w1.z; f1.w += cf * w1.w;
+    w1.x = sv * v1.x - cw * w1.x; w1.y = sv * v1.y - cw * w1.y;
+    w1.z = sv * v1.z - cw * w1.z; w1.w = sv * v1.w - cw * w1.w;
+    f[i0] = f0;
+    w[i0] = w0;
+    if (h1) {
+      f[i1] = f1;
+      w[i1] = w1;
+    }
+  }
+}
+
+// Block (0, i): the tail of instance i. Blocks (1 .. gridDim.x - 1, i): the parts of instance
+// i's pending f, w update (a launch with update parts).
 __global__ void __launch_bounds__(kTailBlock) k_vcycle_tail_lds(InstDesc *const *descs, int t) {
   const InstDesc &D = inst(descs);
+  if (blockIdx.x > 0) {
+    tail_update_part(D, (int)blockIdx.x - 1, (int)gridDim.x - 1);
+    return;
+  }
   if (stopped_inner(D)) return;
   if (t < 0) t = sld(D.tail_lds_t);   // instances of different hierarchies in one launch
   const int Lv = sld(D.levels);
@@ -463,8 +507,8 @@ long long tail_lds_floats(const long long *cells, int nlev) {
   return s;
 }
 
-void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t) {
-  hipLaunchKernelGGL(k_vcycle_tail_lds, dim3(1, B), dim3(kTailBlock), 0, st, d, t);
+void launch_vcycle_tail_lds(hipStream_t st, InstDesc *const *d, int B, int t, int upd_parts) {
+  hipLaunchKernelGGL(k_vcycle_tail_lds, dim3(1 + upd_parts, B), dim3(kTailBlock), 0, st, d, t);
 }
 
 }  // namespace plsqr

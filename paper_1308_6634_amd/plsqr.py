@@ -34,6 +34,7 @@ PLSQR_OP_RING = 3
 PLSQR_REG_TIKHONOV, PLSQR_REG_STV, PLSQR_REG_PM_LOG, PLSQR_REG_PM_EXP = 0, 1, 2, 3
 PLSQR_SMOOTH_JACOBI, PLSQR_SMOOTH_CHEBYSHEV = 0, 1
 PLSQR_VCYCLE_FUSED, PLSQR_VCYCLE_PER_SWEEP = 0, 1
+PLSQR_UPDATE_AUTO, PLSQR_UPDATE_PRODUCT, PLSQR_UPDATE_TAIL = 0, 1, 2
 PLSQR_PREC_FP32, PLSQR_PREC_BF16_REFINED, PLSQR_PREC_BF16 = 0, 1, 2
 PLSQR_ENGINE_SERVE = 1
 PLSQR_FLAG_TIME_PRODUCTS = 1
@@ -82,7 +83,7 @@ class plsqr_problem(ctypes.Structure):
                 ("tune_blur_window", ctypes.c_int32), ("tune_blur_xgroups", ctypes.c_int32),
                 ("tune_vcycle", ctypes.c_int32), ("tune_zm_ty", ctypes.c_int32),
                 ("tune_zm_zc", ctypes.c_int32), ("tune_zm_v", ctypes.c_int32),
-                ("tune_tail_cells", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("tune_tail_cells", ctypes.c_int32), ("tune_update_site", ctypes.c_int32)]
 
 
 class plsqr_result(ctypes.Structure):

@@ -105,6 +105,15 @@ def test_dominant_bytes():
     assert bench.blur_update_fused(p, {}) and not bench.blur_update_fused(p, {"tune_vcycle": 1})
     p.dims = (6, 8, 8)
     assert not bench.blur_update_fused(p, {})               # the x pass takes 4-voxel groups only
+    # above the tail the update runs in the V-cycle tail launch, unless the batch is large or
+    # the knob puts it in the product
+    p.dims, p.levels, p.smoother, p.nu_pre, p.cheb_degree = (64, 64, 64), 5, "chebyshev", 1, 3
+    assert bench.update_in_tail(p, {}) and not bench.blur_update_fused(p, {})
+    assert bench.blur_update_fused(p, {"tune_update_site": 1})
+    assert bench.blur_update_fused(p, {}, batch=17) and not bench.update_in_tail(p, {}, 17)
+    assert bench.update_in_tail(p, {"tune_update_site": 2}, 17)
+    p.nu_pre = 2                                            # Chebyshev level kernels: one polynomial
+    assert bench.blur_update_fused(p, {})
     import numpy as np
     p.dims, p.op_kind, p.A = (4, 4, 2), "dense", np.zeros((10, 32), np.float32)
     b, _, k = bench.dominant_bytes(p)

@@ -594,6 +594,34 @@ def test_graph_replay_equals_eager(engine, kind, inner):
             assert res.forward_launches == p.outer * p.inner
 
 
+@pytest.mark.parametrize("inner,stop_outer", [(6, False), (11, False), (9, True)])
+def test_update_site_tail_equals_product(engine, inner, stop_outer):
+    """The f, w update of each inner step run in extra workgroups of the next V-cycle's tail
+    launch (PLSQR_UPDATE_TAIL) and in the next forward product (PLSQR_UPDATE_PRODUCT): both meet
+    the oracle's bar, agree with each other, and the graph path (eight steps per graph and a
+    remainder) equals the eager one bitwise for each; also with the outer stop firing."""
+    from paper_1308_6634_amd import plsqr as P
+    from paper_1308_6634_amd.engine import solve
+    p = gen.small_blur_case(99, (32, 32, 16), reg="stv", T=0.05, tau=20.0, outer=4, inner=inner,
+                            levels=3, smoother="chebyshev", nu_pre=1, nu_post=1)
+    if stop_outer:
+        p.stop_outer, p.outer_rtol, p.outer_min = True, 0.5, 2
+    f_ref, rec = lagged.solve_problem(p)
+    outs = []
+    for site in (P.PLSQR_UPDATE_PRODUCT, P.PLSQR_UPDATE_TAIL):
+        knobs = {"tune_update_site": site}
+        got, res = solve(p, engine=engine, knobs=knobs)
+        eager, _ = solve(p, engine=engine, knobs=knobs, flags=P.PLSQR_FLAG_NO_GRAPHS)
+        np.testing.assert_array_equal(got, eager)
+        _say(f"[update site {site}] inner {inner} stop_outer {stop_outer}: rel L2 "
+             f"{_rel(got, f_ref):.3e}")
+        assert_parity(got, f_ref, TOL, f"update site {site}")
+        for k, r in enumerate(rec):
+            assert res.inner_done[k] == r["inner_done"]
+        outs.append(got)
+    assert _rel(outs[1], outs[0]) <= 1e-6
+
+
 @pytest.mark.parametrize("kind,graphs", [("blur_cheb", True), ("dense_jacobi", False)])
 def test_phase_times_are_reported(engine, kind, graphs):
     """PLSQR_FLAG_TIME_PHASES: every phase of the method carries a device time (events on the
