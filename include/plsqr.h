@@ -254,8 +254,9 @@ typedef struct {
        vcycle_ms  the inner steps' priorconditioner solves v = B p (one V-cycle, Section 4.2)
                   with the reduction alpha = sqrt(v.p) and the damping and Givens rotations
        update_ms  the inner steps' updates of f and w (and the S4 residual recurrence); for a
-                  blur operator with nx % 4 == 0 and the fused V-cycle, the first pass of the
-                  next forward product applies the update, and its time is part of forward_ms
+                  blur operator with nx % 4 == 0 and the fused V-cycle, the next forward
+                  product (its time is part of forward_ms) or the next V-cycle's tail launch
+                  (part of vcycle_ms, tune_update_site) applies the update
        diag_ms    the per-outer residual ||g - A f^k|| and penalty R(f^k), and the final copy
        phase_launches  inner steps timed */
   double setup_ms;
