@@ -308,6 +308,28 @@ def test_batch_fp32_blur_is_bitwise_equal_to_alone(engine):
         np.testing.assert_array_equal(fa, fb)
 
 
+def test_batch_fp32_blur_above_tail_equals_alone_and_oracle(engine):
+    """A lockstep batch of blur instances whose finest level runs as fused level kernels above
+    the V-cycle tail, so the pending f, w update runs in the tail launch's extra workgroups (84
+    per instance for three instances, 255 alone): bitwise equal to each instance alone, and at
+    the oracle's bar."""
+    from paper_1308_6634_amd.engine import solve
+    # dampings inside the float32 region (a float32 emulation of the oracle puts these three at
+    # 1.6e-7, 1.2e-4 and 2.8e-6; the Tikhonov instance at tau = 5 would be at 4.2e-3 by
+    # float32 rounding alone)
+    regs = [("stv", 0.05, 20.0), ("pm_log", 0.1, 20.0), ("tikhonov", 1.0, 50.0)]
+    probs = [gen.small_blur_case(70 + i, (32, 32, 16), reg=r, T=T, tau=tau, outer=2, inner=9,
+                                 levels=3, smoother="chebyshev", nu_pre=1, nu_post=1)
+             for i, (r, T, tau) in enumerate(regs)]
+    _say("[batch] fp32 blur x3 (32,32,16), update in the tail launch")
+    batched = _run_batch(engine, probs)
+    for p, fb in zip(probs, batched):
+        fa, _ = solve(p, engine=engine)
+        np.testing.assert_array_equal(fa, fb)
+        f_ref, _ = lagged.solve_problem(p)
+        assert_parity(fb, f_ref, TOL, p.name)
+
+
 def test_batch_fp32_dense_matches_oracle(engine):
     A = gen.small_dense_case(70, 8).A
     probs = [gen.small_dense_case(70 + i, 8, reg=("stv", "pm_log")[i % 2],
