@@ -78,3 +78,22 @@ def test_early_iterates_of_a_weakly_regularised_3d_solve():
         errs[inner] = float(np.linalg.norm(E.solve_blur(p, sm) - f_ref) / np.linalg.norm(f_ref))
     assert errs[4] > 3e-4
     assert errs[8] <= 5e-6
+
+
+def test_three_dimensional_tikhonov_edge_of_the_region():
+    # the region's edge depends on the problem: a 32 x 32 x 16 Tikhonov case with a Chebyshev
+    # V-cycle misses the bar in float32 at tau = 5 and is an order inside it at tau = 20 (the
+    # GPU's batch test of this shape uses tau >= 20)
+    kw = dict(dims=(32, 32, 16), levels=3, inner=9, seed=72)
+    p5 = _err_cheb("tikhonov", 1.0, 5.0, 1e-6, **kw)
+    p20 = _err_cheb("tikhonov", 1.0, 20.0, 1e-6, **kw)
+    assert p5 > 1e-3 and p20 < 1e-4, (p5, p20)
+
+
+def _err_cheb(reg, T, tau, eps, inner, dims, levels, seed):
+    p = gen.small_blur_case(seed, dims, reg=reg, T=T, tau=tau, outer=2, inner=inner,
+                            levels=levels, eps=eps, smoother="chebyshev", nu_pre=1, nu_post=1)
+    sm = multigrid.Smoother(p.smoother, p.nu_pre, p.nu_post, p.omega)
+    f_ref, _ = lagged.solve_problem(p)
+    f32 = E.solve_blur(p, sm)
+    return float(np.linalg.norm(f32 - f_ref) / np.linalg.norm(f_ref))
