@@ -13,12 +13,12 @@ problem the phantom parameters are drawn first, then the noise.
 from .phantoms import rectangles_2d, ellipsoids_3d, boxes_spheres_3d
 from .operators import gaussian_taps, ring_geometry, dense_sensitivity, blur_data, dense_data
 from .configs import (Problem, make_blur_problem, make_dense_problem, config_c1, config_c2,
-                      config_c3, config_c4, config_c5_requests, auto_levels, small_dense_case,
-                      small_blur_case)
+                      config_c3, config_c4, config_c5_requests, c5_request, auto_levels,
+                      small_dense_case, small_blur_case)
 
 __all__ = [
     "rectangles_2d", "ellipsoids_3d", "boxes_spheres_3d", "gaussian_taps", "ring_geometry",
     "dense_sensitivity", "blur_data", "dense_data", "Problem", "make_blur_problem",
     "make_dense_problem", "config_c1", "config_c2", "config_c3", "config_c4",
-    "config_c5_requests", "auto_levels", "small_dense_case", "small_blur_case",
+    "config_c5_requests", "c5_request", "auto_levels", "small_dense_case", "small_blur_case",
 ]

@@ -499,6 +499,16 @@ def test_served_mix_equals_alone(engine, budget_factor):
         assert sum(mixed) > 0
 
 
+@pytest.mark.parametrize("r", [133, 23])
+def test_served_stream_request_full_counts(engine, r):
+    """Requests of the served stream itself (generated as the stream generates them) at their
+    full 8 x 40 counts against the oracle: request 133 is the stream's least damped 32^3 one
+    (Tikhonov, tau = 14.6), request 23 a 32^3 Perona-Malik one (tau = 13.7)."""
+    p = gen.c5_request(r)
+    assert p.dims == (32, 32, 32) and (p.outer, p.inner) == (8, 40)
+    _check(p, engine)
+
+
 def test_served_mixed_sizes_match_oracle(engine):
     """The served form against the FP64 oracle: requests shaped like the served stream (blur
     sigma U(1.5, 3.5) with radius ceil(3 sigma) up to 11, Tikhonov / sTV 0.02 / PM-log 0.05,
